@@ -1,0 +1,238 @@
+"""Pins of the NumPy FMM oracle (no GPU).
+
+The FMM is an approximation, so it is pinned by what must hold for it:
+interpolation identities (§4, eq. interpolation_identity), the tree and its
+geometry (§3), the coverage and MAC invariants of the dual traversal (§8),
+proxy-weight moments (§6), the degenerate cases where it reduces to the direct
+sum, the error trends of Table 2 (smaller with higher degree, smaller with a
+smaller MAC), and agreement with the direct-sum oracle.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from workloads import cubed_sphere_grid, random_sphere_points, real_y43, real_y41
+from oracle import direct
+from oracle import fmm as F
+
+
+def rel_l2(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+# --------------------------------------------------------------- §4
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 10])
+def test_lagrange_identities(n):
+    s = F.chebyshev_points(n)
+    assert s[0] == 1.0 and s[-1] == -1.0
+    L = F.lagrange(n, s)
+    assert np.array_equal(L, np.eye(n + 1))
+    rng = np.random.default_rng(n)
+    u = rng.uniform(-1, 1, 200)
+    L = F.lagrange(n, u)
+    assert np.allclose(L.sum(1), 1.0, atol=1e-14)
+    # product form of the Lagrange polynomials, an independent formula
+    P = np.ones((u.size, n + 1))
+    for k in range(n + 1):
+        for m in range(n + 1):
+            if m != k:
+                P[:, k] *= (u - s[m]) / (s[k] - s[m])
+    assert np.max(np.abs(L - P)) < 1e-12
+    # exact for polynomials of degree <= n
+    for deg in range(n + 1):
+        assert np.max(np.abs(L @ s ** deg - u ** deg)) < 1e-13
+
+
+def test_interpolation_identity_parent_child():
+    """eq. (interpolation_identity): parent L_k at child nodes reproduces parent L_k."""
+    n = 6
+    s = F.chebyshev_points(n)
+    rng = np.random.default_rng(1)
+    for sigma in (-1.0, 1.0):
+        A = F.lagrange(n, (s + sigma) / 2.0)        # A[m, k] = L^p_k(s^c_m)
+        uc = rng.uniform(-1, 1, 50)                  # child-local coordinates
+        lhs = F.lagrange(n, (uc + sigma) / 2.0)      # L^p_k(y)
+        rhs = F.lagrange(n, uc) @ A                  # sum_m L^c_m(y) L^p_k(s^c_m)
+        assert np.max(np.abs(lhs - rhs)) < 1e-12
+
+
+# --------------------------------------------------------------- §3
+
+def test_face_frames_and_map_roundtrip():
+    for fr in F.FACE_FRAMES:
+        assert np.array_equal(np.cross(fr[1], fr[2]), fr[0])
+    rng = np.random.default_rng(3)
+    for f in range(6):
+        xi = rng.uniform(-math.pi / 4 + 1e-3, math.pi / 4 - 1e-3, 100)
+        eta = rng.uniform(-math.pi / 4 + 1e-3, math.pi / 4 - 1e-3, 100)
+        X = F.angles_to_sphere(np.full(100, f), xi, eta)
+        ff, xx, ee = F.face_and_angles(X)
+        assert np.all(ff == f)
+        assert np.max(np.abs(xx - xi)) < 1e-14 and np.max(np.abs(ee - eta)) < 1e-14
+
+
+@pytest.mark.parametrize("E,N0,nleaf_level", [(32, 64, 2), (16, 64, 1), (32, 128, 2), (8, 1, 3)])
+def test_tree_on_grid(E, N0, nleaf_level):
+    P, A = cubed_sphere_grid(E)
+    T = F.Tree(P, N0, 4)
+    seen = np.zeros(P.shape[0], dtype=int)
+    for C in T.leaves:
+        seen[C.idx] += 1
+        assert C.count <= N0 or C.level == F.MAX_LEVEL
+        assert C.level == nleaf_level
+    assert np.all(seen == 1)
+    for C in T.cells:
+        if not C.is_leaf:
+            assert sorted(np.concatenate([ch.idx for ch in C.children]).tolist()) == sorted(C.idx.tolist())
+        # every particle lies inside the ball of the cluster and in its angle square
+        if C.count:
+            d = np.sqrt(np.sum((P[C.idx] - C.center) ** 2, axis=1))
+            assert np.all(d <= C.radius * (1 + 1e-14))
+            u, v = C.local(T.xi[C.idx], T.eta[C.idx])
+            assert np.all(np.abs(u) <= 1 + 1e-12) and np.all(np.abs(v) <= 1 + 1e-12)
+        assert abs(np.linalg.norm(C.center) - 1) < 1e-15
+        assert np.allclose(np.linalg.norm(C.proxies, axis=1), 1.0, atol=1e-15)
+    # config 1: 6 + 24 + 96 cells, 96 leaves of 64 points
+    if (E, N0) == (32, 64):
+        assert len(T.cells) == 126 and len(T.leaves) == 96
+        assert all(C.count == 64 for C in T.leaves)
+
+
+# --------------------------------------------------------------- §8 traversal
+
+def _coverage(fm, nt, ns):
+    cover = np.zeros((nt, ns), dtype=np.int64)
+    for kind, pairs in fm.lists.items():
+        for T, S in pairs:
+            cover[np.ix_(T.idx, S.idx)] += 1
+    return cover
+
+
+@pytest.mark.parametrize("case", ["grid", "distinct", "clustered"])
+def test_coverage_and_mac_invariants(case):
+    rng = np.random.default_rng(7)
+    if case == "grid":
+        P, _ = cubed_sphere_grid(16)
+        fm = F.FMM(P, None, 1, 4, 0.7, 16)
+        nt = ns = P.shape[0]
+    elif case == "distinct":
+        P, _ = cubed_sphere_grid(8)
+        X = random_sphere_points(700, 8)
+        fm = F.FMM(X, P, 1, 4, 0.6, 20)
+        nt, ns = X.shape[0], P.shape[0]
+    else:
+        X = random_sphere_points(900, 9)
+        X = X[X[:, 2] > 0.3]                 # a cap: empty and unbalanced cells
+        X = np.concatenate([X, random_sphere_points(200, 10)])
+        fm = F.FMM(X, None, 1, 4, 0.5, 12)
+        nt = ns = X.shape[0]
+    cover = _coverage(fm, nt, ns)
+    assert np.all(cover == 1)
+    for kind in ("PC", "CP", "CC"):
+        for T, S in fm.lists[kind]:
+            assert F.well_separated(T, S, fm.theta)
+            assert (kind == "PC") == (T.is_leaf and not S.is_leaf)
+            assert (kind == "CP") == (S.is_leaf and not T.is_leaf)
+    for T, S in fm.lists["PP"]:
+        assert T.is_leaf and S.is_leaf
+    assert sum(len(v) for v in fm.lists.values()) > 0
+
+
+# --------------------------------------------------------------- §6 upward
+
+def test_upward_moments():
+    """sum_k wbar_k q(s_k) = sum_j w_j q(y_j) for q of degree <= n per variable."""
+    P, A = cubed_sphere_grid(16)
+    n = 5
+    T = F.Tree(P, 16, n)
+    w = np.random.default_rng(4).standard_normal(P.shape[0])
+    wbar = F.upward_pass(T, w)
+    s = F.chebyshev_points(n)
+    for C in T.cells:
+        wb = wbar[C.id]
+        assert abs(wb.sum() - w[C.idx].sum()) < 1e-12 * (1 + np.abs(w[C.idx]).sum())
+        u, v = C.local(T.xi[C.idx], T.eta[C.idx])
+        for a in (0, 1, n):
+            for b in (0, 2, n):
+                lhs = np.einsum("kl,k,l->", wb, s ** a, s ** b)
+                rhs = np.sum(w[C.idx] * u ** a * v ** b)
+                assert abs(lhs - rhs) < 1e-11 * (1 + np.abs(w[C.idx]).sum())
+
+
+# --------------------------------------------------------------- whole method
+
+@pytest.mark.parametrize("kernel", [1, 2, 3])
+def test_degenerate_cases_equal_direct(kernel):
+    P, A = cubed_sphere_grid(8)
+    w = real_y41(P) * A
+    ref = direct(kernel, P, P, w)
+    # MAC -> 0: nothing is well separated, every pair is PP
+    got = F.fmm(P, None, w, kernel, 4, 1e-9, 16)
+    assert rel_l2(got, ref) < 1e-14
+    # leaf size >= N: the six roots are leaves, every pair is PP
+    got = F.fmm(P, None, w, kernel, 4, 0.7, P.shape[0])
+    assert rel_l2(got, ref) < 1e-14
+
+
+def test_config1_against_direct_and_exact():
+    P, A = cubed_sphere_grid(32)
+    f = real_y43(P)
+    w = f * A
+    ds = direct(1, P, P, w)
+    fs = F.fmm(P, None, w, 1, 8, 0.7, 64)
+    assert rel_l2(fs, ds) < 1e-6
+
+    def E(a, b):
+        return math.sqrt(np.sum((a - b) ** 2 * A) / np.sum((f / 20) ** 2 * A))
+    assert abs(E(fs, f / 20) - E(ds, f / 20)) < 1e-6
+
+
+def test_error_trends_degree_and_mac():
+    P, A = cubed_sphere_grid(32)
+    w = real_y43(P) * A
+    ds = direct(1, P, P, w)
+    e = {}
+    for n in (4, 6, 8):
+        for th in (0.7, 0.5):
+            e[n, th] = rel_l2(F.fmm(P, None, w, 1, n, th, 64), ds)
+    for th in (0.7, 0.5):
+        assert e[4, th] > e[6, th] > e[8, th]
+    for n in (4, 6, 8):
+        assert e[n, 0.5] < e[n, 0.7]
+    # order of magnitude of Table 2 at MAC 0.7 (different grid and leaf size)
+    assert 1e-8 < e[6, 0.7] < 1e-4
+
+
+def test_cube_rotation_symmetry():
+    """A 90 degree turn about z maps the grid and the cubed-sphere tree to themselves."""
+    P, A = cubed_sphere_grid(16)
+    w = real_y43(P) * A
+    R = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    Q = P @ R.T
+    for kernel in (1, 2):
+        a = F.fmm(P, None, w, kernel, 3, 0.7, 16)
+        b = F.fmm(Q, None, w, kernel, 3, 0.7, 16)
+        if kernel == 2:
+            a = a @ R.T
+        ref = direct(kernel, P, P, w)
+        assert rel_l2(a, ref) > 1e-7          # the approximation error is visible
+        assert rel_l2(b, a) < 1e-13           # and it is the same after the turn
+
+
+@pytest.mark.parametrize("kernel", [1, 2, 3])
+def test_distinct_sets_and_sampling(kernel):
+    P, A = cubed_sphere_grid(16)
+    X = random_sphere_points(1500, 12)
+    X[:5] = P[[0, 17, 300, 301, 1535]]          # exact coincidences are skipped
+    w = real_y43(P) * A
+    fm = F.FMM(X, P, kernel, 8, 0.6, 32)
+    full = fm.evaluate(w)
+    ref = direct(kernel, X, P, w)
+    assert rel_l2(full, ref) < 1e-6
+    sample = np.array([0, 3, 10, 999, 1499])
+    part = fm.evaluate(w, sample=sample)
+    assert np.max(np.abs(part - full[sample])) <= 1e-15 * np.max(np.abs(full))
