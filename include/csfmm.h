@@ -1,0 +1,195 @@
+/*
+ * csfmm.h -- C ABI of the cubed sphere fast multipole method (CSFMM) on one
+ * AMD MI355X (gfx950).
+ *
+ * The library evaluates N-body sums on the unit sphere (paper §1, eq.
+ * nbodysum):
+ *
+ *     phi(x_i) = sum_j K(x_i, y_j) w_j ,   i = 1..n_t,
+ *
+ * for target points x_i and source points y_j on the unit sphere with source
+ * weights w_j, by the CSFMM of paper §8 (Algorithm 2): quadtrees of
+ * equiangular cubed-sphere cells (§3), barycentric Lagrange interpolation at
+ * tensor Chebyshev proxy points in each cell (§4), the four interactions PP,
+ * PC, CP and CC (§5), the upward pass (§6), a dual tree traversal with the
+ * MAC (r_t + r_s)/R < theta (§8) and the downward pass (§8.1).  The singular
+ * self term is omitted (§1): a source is skipped for a target exactly when
+ * their coordinates are equal.
+ *
+ * Conventions for every call:
+ *   - Array pointers are DEVICE pointers (for example a torch tensor's
+ *     data_ptr()), float64, C order.  Points are [n][3] (x, y, z).
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is ordered on
+ *     that stream; only csfmm_plan waits for the device.
+ *   - Inputs and outputs stay owned by the caller.  A plan owns its own device
+ *     memory until csfmm_plan_destroy.
+ *   - Results are in the caller's point order.
+ *   - Every call returns CSFMM_OK (0) or a negative csfmm_status; no
+ *     exception or abort crosses the boundary.  csfmm_last_error() then
+ *     returns a message for the calling thread.
+ *   - Argument errors are detected on the host before any launch.
+ */
+#ifndef CSFMM_H
+#define CSFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct csfmm_plan_s* csfmm_plan_t;
+
+enum csfmm_status {
+    CSFMM_OK = 0,
+    CSFMM_E_INVALID = -1,       /* bad argument (size, degree, theta, kernel, pointer) */
+    CSFMM_E_NOT_ON_SPHERE = -2, /* a point is not finite or | |x| - 1 | > 1e-12 */
+    CSFMM_E_OOM = -3,           /* device allocation failed */
+    CSFMM_E_HIP = -4,           /* a HIP runtime call failed */
+    CSFMM_E_BUSY = -5,          /* reserved */
+    CSFMM_E_UNSUPPORTED = -6    /* reserved */
+};
+
+/* Kernels K(x, y) for x, y on the unit sphere (paper §2). */
+enum csfmm_kernel {
+    CSFMM_K_POISSON_LOG = 1, /* -(1/4pi) ln(1 - x.y), eq. (G_L); one output */
+    CSFMM_K_BIOT_SAVART = 2, /* -(1/4pi) (x cross y)/(1 - x.y), eq. (K_BS); three outputs */
+    CSFMM_K_INV_DIST = 3     /* 1/|x - y| = 1/gamma(x, y), the first term of eq. (G_SAL_approx) */
+};
+
+/* Precision forms. */
+enum csfmm_flags {
+    CSFMM_FP64 = 0,     /* every step in FP64 */
+    CSFMM_FP32_FORM = 1 /* kernel evaluations (PP, PC, CP, CC, direct) in FP32 on
+                           coordinates recentred at the target cell in FP64;
+                           partial sums added into FP64; geometry, mapping,
+                           interpolation and final sums in FP64 */
+};
+
+typedef struct csfmm_stats {
+    int64_t n_targets, n_sources;
+    int32_t same_set, kernel, p, leaf_size;
+    double theta;
+    uint32_t flags;
+    int32_t depth_t, depth_s;              /* deepest level (roots are level 0) */
+    int64_t n_cells_t, n_cells_s;          /* all levels */
+    int64_t n_leaves_t, n_leaves_s;
+    int64_t n_pp, n_pc, n_cp, n_cc;        /* (target cell, source cell) pairs */
+    int64_t evals_pp, evals_pc, evals_cp, evals_cc; /* kernel evaluations per eval */
+    int64_t device_bytes;                  /* device memory the plan holds */
+} csfmm_stats;
+
+/*
+ * Build a plan: trees, cell geometry and proxy points, the fixed parent-child
+ * interpolation matrices and the PP/PC/CP/CC interaction lists (paper §3, §4,
+ * §8 Algorithm 2 lines 4 and 6-18; the lists depend only on the points, p,
+ * theta and N0, not on the weights).
+ *
+ *   targets   [n_t][3] device, unit vectors; copied into the plan
+ *   sources   [n_s][3] device, or NULL: the sources are the targets (one tree,
+ *             i = j omitted); copied into the plan
+ *   kernel_id csfmm_kernel; the default kernel of csfmm_eval
+ *   p         interpolation degree n of the paper, 1..16; (p+1)^2 proxies per cell
+ *   theta     MAC parameter, 0 < theta < 1
+ *   leaf_size N0: a cell with more than N0 points is split (deepest level 20)
+ *   flags     csfmm_flags
+ *   out       receives the plan handle
+ * n_t, n_s >= 1.  Waits for the device (list sizes are data dependent).
+ * Errors: CSFMM_E_INVALID, CSFMM_E_NOT_ON_SPHERE, CSFMM_E_OOM, CSFMM_E_HIP.
+ */
+int csfmm_plan(const double* targets, int64_t n_t, const double* sources, int64_t n_s,
+               int kernel_id, int p, double theta, int leaf_size, unsigned flags,
+               void* stream, csfmm_plan_t* out);
+
+/*
+ * Apply a plan to source weights (Algorithm 2 lines 3, 5-21): upward pass
+ * (P2M, M2M), interactions (PP, PC, CP, CC), downward pass (L2L, L2P).
+ *   weights [n_s] device (for a same-set plan n_s = n_t)
+ *   out     [n_t] device, or [n_t][3] for Biot-Savart
+ * Asynchronous on `stream`; weights must stay valid and out must not be read
+ * until the stream work completes.  One eval in flight per plan.
+ */
+int csfmm_eval(csfmm_plan_t plan, const double* weights, double* out, void* stream);
+
+/* As csfmm_eval, with the kernel given per call instead of the plan's
+ * default (the plan is geometry only). */
+int csfmm_eval_kernel(csfmm_plan_t plan, int kernel_id, const double* weights, double* out,
+                      void* stream);
+
+/*
+ * Direct sum of paper eq. (nbodysum) over all pairs (the O(N^2) method of §1):
+ * out[i] = sum_j K(x_i, y_j) w_j with exact coincidences omitted.
+ *   targets [n_t][3], sources [n_s][3], weights [n_s], out [n_t] or [n_t][3].
+ *   flags CSFMM_FP64 or CSFMM_FP32_FORM (FP32 evaluation on hi/lo split
+ *   coordinates, FP64 partial sums).  Asynchronous on `stream`.
+ */
+int csfmm_direct(const double* targets, int64_t n_t, const double* sources, int64_t n_s,
+                 const double* weights, int kernel_id, unsigned flags, double* out,
+                 void* stream);
+
+/* Release a plan's device memory (waits for the device first). NULL is OK. */
+int csfmm_plan_destroy(csfmm_plan_t plan);
+
+/* Sizes and interaction counts of a plan. */
+int csfmm_plan_stats(csfmm_plan_t plan, csfmm_stats* s);
+
+/*
+ * Per-stage timing of csfmm_eval with HIP events recorded on the eval's
+ * stream.  enable != 0 turns it on (and resets the sums), 0 turns it off.
+ * csfmm_plan_timing_read waits for the recorded events and returns the summed
+ * milliseconds of the 6 stages over the timed evals:
+ *   [0] weight gather + P2M, [1] M2M, [2] near field (PP+PC, one kernel),
+ *   [3] far field (CP+CC, one kernel, after zeroing), [4] L2L, [5] L2P+scatter.
+ */
+int csfmm_plan_timing(csfmm_plan_t plan, int enable);
+int csfmm_plan_timing_read(csfmm_plan_t plan, double* stage_ms /*[6]*/, int64_t* n_evals);
+
+/* Upper estimate of the device bytes a plan of these sizes holds (for
+ * admission control); -1 on bad arguments. */
+int64_t csfmm_estimate_bytes(int64_t n_t, int64_t n_s, int p, int leaf_size, unsigned flags);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* csfmm_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Inspection calls: copy a plan's internals to HOST memory, for checking the
+ * tree, geometry and lists against an independent builder.  `which` is 0 for
+ * the target tree, 1 for the source tree (the same tree for a same-set plan).
+ * ---------------------------------------------------------------------- */
+
+/* Cells in breadth-first order (level by level, Morton order in a level;
+ * the four children of a cell are consecutive).  Each array has n_cells
+ * entries (csfmm_plan_stats); any pointer may be NULL to skip it.
+ *   level, face, ci, cj: cell (face 0..5: +x, +y, -x, -y, +z, -z; index
+ *     (ci, cj) in the level's 2^l x 2^l grid of local angles (xi, eta))
+ *   begin, count: range of the cell's points in the plan's sorted order
+ *   child0: index of the first child, -1 for a leaf
+ *   center [n][3], radius [n]                                           */
+int csfmm_plan_cells(csfmm_plan_t plan, int which, int32_t* level, int32_t* face, int32_t* ci,
+                     int32_t* cj, int32_t* begin, int32_t* count, int32_t* child0,
+                     double* center, double* radius);
+
+/* Proxy points of every cell: [n_cells][(p+1)^2][3], proxy (k1, k2) at
+ * k1*(p+1)+k2 is the image of (xi_mid + h s_k1, eta_mid + h s_k2). */
+int csfmm_plan_proxies(csfmm_plan_t plan, int which, double* proxies);
+
+/* Sorted order: perm[k] = caller index of the k-th point in sorted order. */
+int csfmm_plan_permutation(csfmm_plan_t plan, int which, int64_t* perm);
+
+/* Interaction list `kind` (0 PP, 1 PC, 2 CP, 3 CC) as (target cell, source
+ * cell) pairs sorted by target then source; cap = room in tgt/src. */
+int csfmm_plan_list(csfmm_plan_t plan, int kind, int32_t* tgt, int32_t* src, int64_t cap);
+
+/* Eval that also copies the stage results to DEVICE buffers (NULL skips):
+ *   wbar [n_cells_s][(p+1)^2]      proxy weights after the upward pass
+ *   psi  [vdim][n_cells_t][(p+1)^2] proxy potentials after the downward pass
+ *   near [n_t][vdim] PP+PC part of phi in the caller's order
+ * where vdim = 3 for Biot-Savart, else 1. */
+int csfmm_eval_stages(csfmm_plan_t plan, int kernel_id, const double* weights, double* out,
+                      double* wbar, double* psi, double* near, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSFMM_H */

@@ -346,12 +346,14 @@ class FMM:
     def vdim(self):
         return 3 if self.kernel == KERNEL_BIOT_SAVART else 1
 
-    def evaluate(self, w, sample=None):
+    def evaluate(self, w, sample=None, stages=False):
         """phi at every target, or only at the target indices in `sample`.
 
         With a sample, target-side work is done only for the cells that hold
         sampled targets; the sampled values are the same numbers the full
-        evaluation gives.
+        evaluation gives.  With stages=True also returns a dict with the proxy
+        weights {cell id: [n+1,n+1]}, the proxy potentials after the downward
+        pass {cell id: [n+1,n+1,vdim]} and the PP+PC part of phi.
         """
         tt, st = self.ttree, self.stree
         w = np.asarray(w, dtype=np.float64)
@@ -400,6 +402,8 @@ class FMM:
                 val = apply_kernel(self.kernel, T.proxies, Y, wy).reshape(n1, n1, vd)
                 psi[tid] = psi.get(tid, 0.0) + val
 
+        near = phi.copy()
+
         # Line 20: downward pass, eq. (downward_2) through all levels, then
         # eq. (downward_1) at the leaves
         for lev in tt.levels:
@@ -423,7 +427,10 @@ class FMM:
                         add = np.einsum("am,bq,mqv->abv", A, B, psi[C.id])
                         psi[ch.id] = psi.get(ch.id, 0.0) + add
         out = phi if sample is None else phi[np.asarray(sample)]
-        return out[:, 0] if vd == 1 else out
+        out = out[:, 0] if vd == 1 else out
+        if stages:
+            return out, {"wbar": wbar, "psi": psi, "near": near}
+        return out
 
 
 def fmm(targets, sources, weights, kernel, n, theta, N0, sample=None):

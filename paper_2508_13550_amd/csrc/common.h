@@ -1,0 +1,178 @@
+// Internal declarations of the CSFMM library for gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/csfmm.h"
+
+namespace csfmm {
+
+// Deepest quadtree level; a level-l cell is a square of side (pi/2)/2^l in
+// the local angles of its face.  Morton keys hold 3 face bits and 2 bits per
+// level.
+constexpr int kMaxLevel = 20;
+constexpr int kMaxDegree = 16;
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kPi4 = 0.78539816339744830962;  // pi/4
+constexpr double kPi2 = 1.57079632679489661923;  // pi/2
+
+// Error reporting (thread-local message behind csfmm_last_error).
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define CSFMM_HIP_TRY(call)                                                                  \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            ::csfmm::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),       \
+                               __FILE__, __LINE__);                                          \
+            return (e_ == hipErrorOutOfMemory || e_ == hipErrorMemoryAllocation)             \
+                       ? CSFMM_E_OOM                                                         \
+                       : CSFMM_E_HIP;                                                        \
+        }                                                                                    \
+    } while (0)
+
+#define CSFMM_LAUNCH_CHECK()                                                                  \
+    do {                                                                                      \
+        hipError_t e_ = hipGetLastError();                                                    \
+        if (e_ != hipSuccess) {                                                               \
+            ::csfmm::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_),    \
+                               __FILE__, __LINE__);                                           \
+            return CSFMM_E_HIP;                                                               \
+        }                                                                                     \
+    } while (0)
+
+// Device allocation owned by a plan; freed in the plan's destructor.
+struct DevArena {
+    std::vector<void*> ptrs;
+    int64_t bytes = 0;
+    template <class T>
+    int alloc(T** p, int64_t n) {
+        *p = nullptr;
+        if (n <= 0) n = 1;
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, sizeof(T) * size_t(n));
+        if (e != hipSuccess) {
+            set_error("hipMalloc of %lld bytes failed: %s", (long long)(sizeof(T) * n),
+                      hipGetErrorString(e));
+            (void)hipGetLastError();
+            return CSFMM_E_OOM;
+        }
+        ptrs.push_back(q);
+        bytes += int64_t(sizeof(T)) * n;
+        *p = static_cast<T*>(q);
+        return CSFMM_OK;
+    }
+    void release() {
+        for (void* q : ptrs) (void)hipFree(q);
+        ptrs.clear();
+        bytes = 0;
+    }
+};
+
+// One quadtree forest over a point set, cells in breadth-first order.
+struct Tree {
+    int64_t n = 0;
+    int32_t ncells = 0, nleaves = 0, depth = 0;
+    std::vector<int32_t> level_begin;   // host: first cell of each level, + end
+    std::vector<int32_t> parents_begin; // host: first entry of each level in `parents`
+    // sorted points (SoA) and their caller indices
+    double *x = nullptr, *y = nullptr, *z = nullptr;
+    double *u = nullptr, *v = nullptr;  // local coordinates in their leaf, [-1,1]
+    int32_t* perm = nullptr;            // sorted position -> caller index
+    // cells
+    int32_t *level = nullptr, *face = nullptr, *ci = nullptr, *cj = nullptr;
+    int32_t *begin = nullptr, *count = nullptr, *child0 = nullptr;
+    double* center = nullptr;  // [ncells][3]
+    double* radius = nullptr;  // [ncells]
+    double* prox = nullptr;    // [ncells][3][KS] proxy coordinates (SoA per cell)
+    int32_t* leaves = nullptr;  // [nleaves] leaf cell ids (Morton order)
+    int32_t* parents = nullptr; // non-leaf cells grouped by level (host offsets above)
+};
+
+// Interaction lists in CSR form by target cell.
+enum ListKind { kPP = 0, kPC = 1, kCP = 2, kCC = 3 };
+
+struct Lists {
+    int64_t cnt[4] = {0, 0, 0, 0};
+    int32_t* off[4] = {nullptr, nullptr, nullptr, nullptr};  // [ncells_t + 1]
+    int32_t* src[4] = {nullptr, nullptr, nullptr, nullptr};  // [cnt]
+    int32_t* far_targets = nullptr;  // target cells with CP or CC entries
+    int32_t n_far_targets = 0;
+    int64_t evals[4] = {0, 0, 0, 0};
+};
+
+}  // namespace csfmm
+
+struct csfmm_plan_s {
+    int64_t nt = 0, ns = 0;
+    bool same = false;
+    int kernel = 1, p = 8, leaf = 64;
+    double theta = 0.7;
+    unsigned flags = 0;
+    int K = 81, KS = 84;  // (p+1)^2 and its stride rounded up to 4
+    csfmm::DevArena arena;
+    csfmm::Tree tt, st_own;
+    csfmm::Tree* st = nullptr;  // source tree (== &tt for a same-set plan)
+    csfmm::Lists lists;
+    // fixed interpolation operators (MFMA B operands)
+    double* bm2m = nullptr;  // [4*KS][NB1], NB1 = roundup(KS,16)
+    double* bl2l = nullptr;  // [KS][NB2],   NB2 = roundup(4*KS,16)
+    double* lag1d = nullptr; // [2][p+1][p+1] 1-D parent-at-child-node values (for inspection)
+    int nb1 = 0, nb2 = 0;
+    // eval workspace
+    double* ws = nullptr;      // [ns] sorted weights
+    double* wbar = nullptr;    // [ncells_s][KS]
+    double* psi = nullptr;     // [3][ncells_t][KS]
+    double* phinear = nullptr; // [3][nt]
+    // optional per-stage timing with HIP events (ring of event sets)
+    struct Timing {
+        static constexpr int kStages = 6;  // P2M, M2M, near, far, L2L, L2P
+        static constexpr int kSlots = 32;
+        bool on = false;
+        std::vector<hipEvent_t> ev;  // [kSlots][kStages + 1]
+        std::vector<int> pending;    // slot recorded and not yet read
+        double sum_ms[kStages] = {0, 0, 0, 0, 0, 0};
+        int64_t n = 0;
+        int next = 0;
+    } timing;
+    ~csfmm_plan_s() {
+        for (hipEvent_t e : timing.ev) (void)hipEventDestroy(e);
+        arena.release();
+    }
+};
+
+namespace csfmm {
+
+// ---- building blocks (sort_scan.hip)
+// exclusive scan of n int32 values; writes the total to *d_total (device)
+int scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* d_total,
+                       hipStream_t s);
+// stable LSD radix sort of (key, value) pairs on the low `bits` bits of the keys
+int radix_sort_u64(uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream_t s);
+
+// ---- plan (plan.hip)
+int build_plan(csfmm_plan_s* P, const double* targets, const double* sources, hipStream_t s);
+
+// ---- stage timing (eval.hip)
+int timing_enable(csfmm_plan_s* P, bool on);
+int timing_collect(csfmm_plan_s* P);
+
+// ---- eval (eval.hip)
+int run_eval(csfmm_plan_s* P, int kernel, const double* weights, double* out, double* wbar_out,
+             double* psi_out, double* near_out, hipStream_t s);
+
+// ---- tile engine (tile.hip)
+int launch_near(csfmm_plan_s* P, int kernel, hipStream_t s);
+int launch_far(csfmm_plan_s* P, int kernel, hipStream_t s);
+int launch_direct(const double* tgt, int64_t nt, const double* src, int64_t ns, const double* w,
+                  int kernel, bool fp32, double* out, hipStream_t s);
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+}  // namespace csfmm

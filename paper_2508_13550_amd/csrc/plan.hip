@@ -1,0 +1,832 @@
+// Plan construction on the GPU: face and Morton keys, sort, quadtree levels,
+// cell geometry and proxy points, fixed interpolation operators and the dual
+// tree traversal that produces the PP/PC/CP/CC lists.
+//
+// Paper passages: §3 (faces, quadtree of cubed-sphere cells, split when a
+// cluster has more than N0 particles), §4 (Chebyshev points s_k = cos(k pi/n),
+// barycentric weights, tensor-product proxies mapped affinely in the local
+// angles), §6 eq. (upwardpass2) and §8.1 eq. (downward_2) (parent polynomials
+// at child nodes), §8 Algorithm 2 and its MAC (r_t + r_s)/R < theta.
+//
+// Readings of the paper that this code fixes (the oracle takes the same ones):
+//  * the face of a point is the axis of its largest |coordinate| (ties x, y, z);
+//  * a level-l cell holds the points whose scaled angle t = (xi+pi/4)/(pi/2)
+//    satisfies floor(2^l t) = cell index (half-open intervals);
+//  * a split creates all four quadrants, also empty ones; leaf = no children;
+//  * centre = image of the angle midpoint, radius = largest chord distance to
+//    a corner, R = chord distance of the centres, MAC strict;
+//  * recursion goes into the coarser-level cluster (tie: target), or into the
+//    other one when that cluster is a leaf; both leaves -> PP even when
+//    separated; separated and not both leaves -> PC / CP / CC exclusively.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace csfmm {
+namespace {
+
+constexpr int kT = 256;
+
+inline unsigned nblk(int64_t n, int t = kT) { return unsigned((n + t - 1) / t); }
+
+// --------------------------------------------------------------- geometry
+// Face frames: (normal, e_a, e_b), right handed, for +x, +y, -x, -y, +z, -z.
+// c = x.normal, a = x.e_a, b = x.e_b; the map back is v = normal + A e_a + B e_b.
+__device__ __forceinline__ void face_coords(int f, double x, double y, double z, double& a,
+                                            double& b, double& c) {
+    switch (f) {
+        case 0: c = x; a = y; b = z; break;
+        case 1: c = y; a = -x; b = z; break;
+        case 2: c = -x; a = -y; b = z; break;
+        case 3: c = -y; a = x; b = z; break;
+        case 4: c = z; a = y; b = -x; break;
+        default: c = -z; a = y; b = x; break;
+    }
+}
+
+__device__ __forceinline__ void gnomonic(int f, double xi, double eta, double* out) {
+#pragma clang fp contract(off)
+    const double A = tan(xi), B = tan(eta);
+    double vx, vy, vz;
+    switch (f) {
+        case 0: vx = 1.0; vy = A; vz = B; break;
+        case 1: vx = -A; vy = 1.0; vz = B; break;
+        case 2: vx = -1.0; vy = -A; vz = B; break;
+        case 3: vx = A; vy = -1.0; vz = B; break;
+        case 4: vx = -B; vy = A; vz = 1.0; break;
+        default: vx = B; vy = A; vz = -1.0; break;
+    }
+    const double r = sqrt(vx * vx + vy * vy + vz * vz);
+    out[0] = vx / r;
+    out[1] = vy / r;
+    out[2] = vz / r;
+}
+
+__device__ __forceinline__ uint64_t spread_bits(uint32_t v) {
+    uint64_t x = v & 0xFFFFFull;  // 20 bits
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+// Morton prefix of cell (f, l, i, j): face bits above 2l interleaved bits (i high).
+__device__ __forceinline__ uint64_t cell_prefix(int f, int l, uint32_t i, uint32_t j) {
+    return (uint64_t(f) << (2 * l)) | (spread_bits(i) << 1) | spread_bits(j);
+}
+
+__global__ void k_check_points(const double* __restrict__ p, int64_t n, int* __restrict__ bad) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double x = p[3 * k], y = p[3 * k + 1], z = p[3 * k + 2];
+    const double r = sqrt(x * x + y * y + z * z);
+    const bool ok = isfinite(x) && isfinite(y) && isfinite(z) && fabs(r - 1.0) <= 1e-12;
+    if (!ok) atomicOr(bad, 1);
+}
+
+// §3: face of each point, local angles and the Morton key of its deepest cell.
+__global__ void k_face_key(const double* __restrict__ p, int64_t n, uint64_t* __restrict__ keys,
+                           int32_t* __restrict__ idx, double* __restrict__ xi_out,
+                           double* __restrict__ eta_out) {
+#pragma clang fp contract(off)
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double x = p[3 * k], y = p[3 * k + 1], z = p[3 * k + 2];
+    const double ax = fabs(x), ay = fabs(y), az = fabs(z);
+    int f;
+    if (ax >= ay && ax >= az)
+        f = x > 0 ? 0 : 2;
+    else if (ay >= az)
+        f = y > 0 ? 1 : 3;
+    else
+        f = z > 0 ? 4 : 5;
+    double a, b, c;
+    face_coords(f, x, y, z, a, b, c);
+    const double xi = atan(a / c), eta = atan(b / c);
+    const double scale = double(1u << kMaxLevel);
+    const double ti = floor(((xi + kPi4) / kPi2) * scale);
+    const double tj = floor(((eta + kPi4) / kPi2) * scale);
+    const double top = double((1u << kMaxLevel) - 1);
+    const uint32_t i = uint32_t(fmin(fmax(ti, 0.0), top));
+    const uint32_t j = uint32_t(fmin(fmax(tj, 0.0), top));
+    keys[k] = cell_prefix(f, kMaxLevel, i, j);
+    idx[k] = int32_t(k);
+    xi_out[k] = xi;
+    eta_out[k] = eta;
+}
+
+__global__ void k_gather_points(const double* __restrict__ p, const int32_t* __restrict__ idx,
+                                const double* __restrict__ xi, const double* __restrict__ eta,
+                                int64_t n, double* __restrict__ x, double* __restrict__ y,
+                                double* __restrict__ z, double* __restrict__ xs,
+                                double* __restrict__ es) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t i = idx[k];
+    x[k] = p[3 * i];
+    y[k] = p[3 * i + 1];
+    z[k] = p[3 * i + 2];
+    xs[k] = xi[i];
+    es[k] = eta[i];
+}
+
+__device__ __forceinline__ int64_t lower_bound_u64(const uint64_t* __restrict__ a, int64_t lo,
+                                                   int64_t hi, uint64_t key) {
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_roots(const uint64_t* __restrict__ keys, int64_t n, int32_t* face, int32_t* ci,
+                        int32_t* cj, int32_t* begin, int32_t* count) {
+    const int f = threadIdx.x;
+    if (f >= 6) return;
+    const uint64_t sh = 2 * kMaxLevel;
+    const int64_t b = lower_bound_u64(keys, 0, n, uint64_t(f) << sh);
+    const int64_t e = lower_bound_u64(keys, 0, n, uint64_t(f + 1) << sh);
+    face[f] = f;
+    ci[f] = 0;
+    cj[f] = 0;
+    begin[f] = int32_t(b);
+    count[f] = int32_t(e - b);
+}
+
+__global__ void k_split_flags(const int32_t* __restrict__ count, int n, int N0, int level,
+                              int32_t* __restrict__ flag) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    flag[k] = (count[k] > N0 && level < kMaxLevel) ? 1 : 0;
+}
+
+// Children of the split cells of one level; child ranges by binary search of
+// the sorted keys inside the parent's range.
+__global__ void k_children(const uint64_t* __restrict__ keys, int n, int level,
+                           const int32_t* __restrict__ flag, const int32_t* __restrict__ off,
+                           const int32_t* __restrict__ pface, const int32_t* __restrict__ pci,
+                           const int32_t* __restrict__ pcj, const int32_t* __restrict__ pbegin,
+                           const int32_t* __restrict__ pcount, int32_t next_level_begin,
+                           int32_t nchildren,
+                           int32_t* __restrict__ pchild0, int32_t* __restrict__ cface,
+                           int32_t* __restrict__ cci, int32_t* __restrict__ ccj,
+                           int32_t* __restrict__ cbegin, int32_t* __restrict__ ccount) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    if (!flag[k]) {
+        pchild0[k] = -1;
+        return;
+    }
+    const int slot = 4 * off[k];
+    if (slot + 4 > nchildren) {
+        pchild0[k] = -1;
+        return;
+    }
+    pchild0[k] = next_level_begin + slot;
+    const int l = level + 1;
+    const int f = pface[k];
+    const int64_t b = pbegin[k], e = b + pcount[k];
+    const int sh = 2 * (kMaxLevel - l);
+    int64_t lo = b;
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t i = 2u * uint32_t(pci[k]) + uint32_t(q >> 1);
+        const uint32_t j = 2u * uint32_t(pcj[k]) + uint32_t(q & 1);
+        const uint64_t pre = cell_prefix(f, l, i, j);
+        const int64_t cb = lower_bound_u64(keys, lo, e, pre << sh);
+        const int64_t ce = lower_bound_u64(keys, cb, e, (pre + 1) << sh);
+        cface[slot + q] = f;
+        cci[slot + q] = int32_t(i);
+        ccj[slot + q] = int32_t(j);
+        cbegin[slot + q] = int32_t(cb);
+        ccount[slot + q] = int32_t(ce - cb);
+        lo = ce;
+    }
+}
+
+__global__ void k_leaf_flags(const int32_t* __restrict__ child0, int n, int32_t* __restrict__ leaf,
+                             int32_t* __restrict__ parent) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    leaf[k] = child0[k] < 0 ? 1 : 0;
+    parent[k] = child0[k] < 0 ? 0 : 1;
+}
+
+__global__ void k_compact(const int32_t* __restrict__ flag, const int32_t* __restrict__ off, int n,
+                          int32_t* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    if (flag[k]) out[off[k]] = k;
+}
+
+// §4: centre, radius (largest chord distance to a corner) and the (p+1)^2
+// proxy points of every cell; proxies stored [cell][3][KS], zero padded.
+__global__ void k_cell_geometry(int n, const int32_t* __restrict__ level,
+                                const int32_t* __restrict__ face, const int32_t* __restrict__ ci,
+                                const int32_t* __restrict__ cj, int p, int KS,
+                                double* __restrict__ center, double* __restrict__ radius,
+                                double* __restrict__ prox) {
+#pragma clang fp contract(off)
+    const int c = blockIdx.x;
+    if (c >= n) return;
+    const int f = face[c], l = level[c];
+    const double d = kPi2 / double(1u << l);
+    const double half = 0.5 * d;
+    const double xm = -kPi4 + (double(ci[c]) + 0.5) * d;
+    const double ym = -kPi4 + (double(cj[c]) + 0.5) * d;
+    __shared__ double cen[3];
+    if (threadIdx.x == 0) {
+        gnomonic(f, xm, ym, cen);
+        double r = 0.0;
+        for (int q = 0; q < 4; ++q) {
+            const double sx = (q >> 1) ? 1.0 : -1.0, sy = (q & 1) ? 1.0 : -1.0;
+            double v[3];
+            gnomonic(f, xm + half * sx, ym + half * sy, v);
+            const double dx = v[0] - cen[0], dy = v[1] - cen[1], dz = v[2] - cen[2];
+            r = fmax(r, sqrt(dx * dx + dy * dy + dz * dz));
+        }
+        center[3 * c] = cen[0];
+        center[3 * c + 1] = cen[1];
+        center[3 * c + 2] = cen[2];
+        radius[c] = r;
+    }
+    const int K = (p + 1) * (p + 1);
+    double* pc = prox + int64_t(c) * 3 * KS;
+    for (int k = threadIdx.x; k < KS; k += blockDim.x) {
+        if (k < K) {
+            const int k1 = k / (p + 1), k2 = k % (p + 1);
+            const double s1 = cos(double(k1) * kPi / double(p));
+            const double s2 = cos(double(k2) * kPi / double(p));
+            double v[3];
+            gnomonic(f, xm + half * s1, ym + half * s2, v);
+            pc[k] = v[0];
+            pc[KS + k] = v[1];
+            pc[2 * KS + k] = v[2];
+        } else {
+            pc[k] = 0.0;
+            pc[KS + k] = 0.0;
+            pc[2 * KS + k] = 0.0;
+        }
+    }
+}
+
+// Local coordinates (u, v) in [-1,1]^2 of every point in its leaf (§4).
+__global__ void k_leaf_local(const int32_t* __restrict__ leaves, int nleaves,
+                             const int32_t* __restrict__ level, const int32_t* __restrict__ ci,
+                             const int32_t* __restrict__ cj, const int32_t* __restrict__ begin,
+                             const int32_t* __restrict__ count, const double* __restrict__ xi,
+                             const double* __restrict__ eta, double* __restrict__ u,
+                             double* __restrict__ v) {
+    const int L = blockIdx.x;
+    if (L >= nleaves) return;
+    const int c = leaves[L];
+    const double d = kPi2 / double(1u << level[c]);
+    const double half = 0.5 * d;
+    const double xm = -kPi4 + (double(ci[c]) + 0.5) * d;
+    const double ym = -kPi4 + (double(cj[c]) + 0.5) * d;
+    const int b = begin[c], m = count[c];
+    for (int k = threadIdx.x; k < m; k += blockDim.x) {
+        u[b + k] = (xi[b + k] - xm) / half;
+        v[b + k] = (eta[b + k] - ym) / half;
+    }
+}
+
+// §4 barycentric Lagrange L_k(x) at the Chebyshev points, exact hit -> delta.
+__device__ double lagrange1(int p, int k, double x) {
+    double num = 0.0, den = 0.0;
+    for (int m = 0; m <= p; ++m) {
+        const double s = cos(double(m) * kPi / double(p));
+        double b = (m & 1) ? -1.0 : 1.0;
+        if (m == 0 || m == p) b *= 0.5;
+        const double dx = x - s;
+        if (dx == 0.0) return m == k ? 1.0 : 0.0;
+        const double t = b / dx;
+        den += t;
+        if (m == k) num = t;
+    }
+    return num / den;
+}
+
+// Fixed operators of eq. (upwardpass2) and eq. (downward_2): with
+// A_s[m][k] = L_k((s_m + s)/2) (parent polynomial k at child node m, s = -1, +1),
+// child q = 2*bi + bj has T_q[k][m] = A_{2bi-1}[m1][k1] A_{2bj-1}[m2][k2].
+//   bm2m[q*KS + m][k] = T_q[k][m]   (M2M: parent = rows of children x bm2m)
+//   bl2l[m][q*KS + n] = T_q[m][n]   (L2L: children += parent x bl2l)
+__global__ void k_build_ops(int p, int KS, int nb1, int nb2, double* __restrict__ A1d,
+                            double* __restrict__ bm2m, double* __restrict__ bl2l) {
+    const int P1 = p + 1, K = P1 * P1;
+    for (int t = threadIdx.x; t < 2 * P1 * P1; t += blockDim.x) {
+        const int sgn = t / (P1 * P1), r = t % (P1 * P1);
+        const int m = r / P1, k = r % P1;
+        const double s = cos(double(m) * kPi / double(p));
+        A1d[t] = lagrange1(p, k, (s + (sgn ? 1.0 : -1.0)) * 0.5);
+    }
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < int64_t(4) * KS * nb1; t += blockDim.x) {
+        const int row = int(t / nb1), k = int(t % nb1);
+        const int q = row / KS, m = row % KS;
+        double val = 0.0;
+        if (m < K && k < K) {
+            const int bi = q >> 1, bj = q & 1;
+            val = A1d[bi * K + (m / P1) * P1 + (k / P1)] * A1d[bj * K + (m % P1) * P1 + (k % P1)];
+        }
+        bm2m[t] = val;
+    }
+    for (int64_t t = threadIdx.x; t < int64_t(KS) * nb2; t += blockDim.x) {
+        const int m = int(t / nb2), col = int(t % nb2);
+        const int q = col / KS, nn = col % KS;
+        double val = 0.0;
+        if (m < K && nn < K && q < 4) {
+            const int bi = q >> 1, bj = q & 1;
+            val = A1d[bi * K + (nn / P1) * P1 + (m / P1)] * A1d[bj * K + (nn % P1) * P1 + (m % P1)];
+        }
+        bl2l[t] = val;
+    }
+}
+
+// ------------------------------------------------------------- traversal
+// Action codes of one (T, S) pair.
+enum { A_NONE = 0, A_PP = 1, A_PC = 2, A_CP = 3, A_CC = 4, A_SPLIT_T = 5, A_SPLIT_S = 6 };
+
+struct TravTree {
+    const int32_t *level, *count, *child0;
+    const double *center, *radius;
+};
+
+__global__ void k_classify(const int32_t* __restrict__ ft, const int32_t* __restrict__ fs, int n,
+                           TravTree T, TravTree S, double theta, int32_t* __restrict__ act,
+                           int32_t* __restrict__ c0, int32_t* __restrict__ c1,
+                           int32_t* __restrict__ c2, int32_t* __restrict__ c3,
+                           int32_t* __restrict__ c4) {
+#pragma clang fp contract(off)
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int t = ft[k], s = fs[k];
+    int a = A_NONE;
+    if (T.count[t] > 0 && S.count[s] > 0) {
+        const bool lt = T.child0[t] < 0, ls = S.child0[s] < 0;
+        const bool both = lt && ls;
+        bool sep = false;
+        if (!both) {
+            const double rs = T.radius[t] + S.radius[s];
+            const double dx = T.center[3 * t] - S.center[3 * s];
+            const double dy = T.center[3 * t + 1] - S.center[3 * s + 1];
+            const double dz = T.center[3 * t + 2] - S.center[3 * s + 2];
+            const double R2 = dx * dx + dy * dy + dz * dz;
+            sep = rs * rs < (theta * theta) * R2;
+        }
+        if (!both && sep)
+            a = lt ? A_PC : (ls ? A_CP : A_CC);
+        else if (!both)
+            a = (!lt && (ls || T.level[t] <= S.level[s])) ? A_SPLIT_T : A_SPLIT_S;
+        else
+            a = A_PP;
+    }
+    act[k] = a;
+    c0[k] = a == A_PP;
+    c1[k] = a == A_PC;
+    c2[k] = a == A_CP;
+    c3[k] = a == A_CC;
+    c4[k] = (a == A_SPLIT_T || a == A_SPLIT_S) ? 4 : 0;
+}
+
+struct Caps {
+    int32_t c[5];
+};
+
+__global__ void k_emit(const int32_t* __restrict__ ft, const int32_t* __restrict__ fs, int n,
+                       const int32_t* __restrict__ act, const int32_t* __restrict__ o0,
+                       const int32_t* __restrict__ o1, const int32_t* __restrict__ o2,
+                       const int32_t* __restrict__ o3, const int32_t* __restrict__ o4,
+                       const int32_t* __restrict__ tchild0, const int32_t* __restrict__ schild0,
+                       int32_t* __restrict__ l0t, int32_t* __restrict__ l0s,
+                       int32_t* __restrict__ l1t, int32_t* __restrict__ l1s,
+                       int32_t* __restrict__ l2t, int32_t* __restrict__ l2s,
+                       int32_t* __restrict__ l3t, int32_t* __restrict__ l3s,
+                       int32_t* __restrict__ nt, int32_t* __restrict__ ns, Caps cap) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int a = act[k];
+    const int t = ft[k], s = fs[k];
+    switch (a) {
+        case A_PP: if (o0[k] < cap.c[0]) { l0t[o0[k]] = t; l0s[o0[k]] = s; } break;
+        case A_PC: if (o1[k] < cap.c[1]) { l1t[o1[k]] = t; l1s[o1[k]] = s; } break;
+        case A_CP: if (o2[k] < cap.c[2]) { l2t[o2[k]] = t; l2s[o2[k]] = s; } break;
+        case A_CC: if (o3[k] < cap.c[3]) { l3t[o3[k]] = t; l3s[o3[k]] = s; } break;
+        case A_SPLIT_T:
+            if (o4[k] + 4 > cap.c[4]) break;
+            for (int q = 0; q < 4; ++q) {
+                nt[o4[k] + q] = tchild0[t] + q;
+                ns[o4[k] + q] = s;
+            }
+            break;
+        case A_SPLIT_S:
+            if (o4[k] + 4 > cap.c[4]) break;
+            for (int q = 0; q < 4; ++q) {
+                nt[o4[k] + q] = t;
+                ns[o4[k] + q] = schild0[s] + q;
+            }
+            break;
+        default: break;
+    }
+}
+
+__global__ void k_root_pairs(int32_t* ft, int32_t* fs) {
+    const int k = threadIdx.x;
+    if (k < 36) {
+        ft[k] = k / 6;
+        fs[k] = k % 6;
+    }
+}
+
+__global__ void k_pair_keys(const int32_t* __restrict__ t, const int32_t* __restrict__ s, int64_t n,
+                            int64_t ns_cells, uint64_t* __restrict__ keys,
+                            int32_t* __restrict__ vals) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    keys[k] = uint64_t(t[k]) * uint64_t(ns_cells) + uint64_t(s[k]);
+    vals[k] = int32_t(k);
+}
+
+__global__ void k_csr_from_keys(const uint64_t* __restrict__ keys, int64_t n, int64_t ns_cells,
+                                int nt_cells, int32_t* __restrict__ off, int32_t* __restrict__ src) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k < n) src[k] = int32_t(keys[k] % uint64_t(ns_cells));
+    if (k <= nt_cells) off[k] = int32_t(lower_bound_u64(keys, 0, n, uint64_t(k) * uint64_t(ns_cells)));
+}
+
+__global__ void k_far_flags(const int32_t* __restrict__ ocp, const int32_t* __restrict__ occ, int n,
+                            int32_t* __restrict__ flag) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    flag[k] = (ocp[k + 1] > ocp[k] || occ[k + 1] > occ[k]) ? 1 : 0;
+}
+
+// ------------------------------------------------------------- host helpers
+
+struct Scratch {
+    hipStream_t s;
+    std::vector<void*> ptrs;
+    explicit Scratch(hipStream_t st) : s(st) {}
+    template <class T>
+    int get(T** p, int64_t n) {
+        if (n <= 0) n = 1;
+        hipError_t e = hipMallocAsync((void**)p, sizeof(T) * size_t(n), s);
+        if (e != hipSuccess) {
+            set_error("hipMallocAsync of %lld bytes failed: %s", (long long)(sizeof(T) * n),
+                      hipGetErrorString(e));
+            (void)hipGetLastError();
+            return CSFMM_E_OOM;
+        }
+        ptrs.push_back((void*)*p);
+        return CSFMM_OK;
+    }
+    ~Scratch() {
+        for (void* q : ptrs) (void)hipFreeAsync(q, s);
+    }
+};
+
+#define RC(x)                              \
+    do {                                   \
+        int rc_ = (x);                     \
+        if (rc_ != CSFMM_OK) return rc_;   \
+    } while (0)
+
+int read_i32(const int32_t* d, int32_t* h, hipStream_t s) {
+    CSFMM_HIP_TRY(hipMemcpyAsync(h, d, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    CSFMM_HIP_TRY(hipStreamSynchronize(s));
+    return CSFMM_OK;
+}
+
+// Build one tree over n points (device AoS coordinates).
+int build_tree(csfmm_plan_s* P, Tree& T, const double* pts, int64_t n, hipStream_t s) {
+    DevArena& A = P->arena;
+    Scratch S(s);
+    T.n = n;
+    uint64_t* keys;
+    int32_t* idx;
+    double *xi0, *eta0, *xi, *eta;
+    RC(S.get(&keys, n));
+    RC(S.get(&idx, n));
+    RC(S.get(&xi0, n));
+    RC(S.get(&eta0, n));
+    RC(S.get(&xi, n));
+    RC(S.get(&eta, n));
+    k_face_key<<<nblk(n), kT, 0, s>>>(pts, n, keys, idx, xi0, eta0);
+    CSFMM_LAUNCH_CHECK();
+    RC(radix_sort_u64(keys, idx, n, 3 + 2 * kMaxLevel, s));
+    RC(A.alloc(&T.x, n));
+    RC(A.alloc(&T.y, n));
+    RC(A.alloc(&T.z, n));
+    RC(A.alloc(&T.u, n));
+    RC(A.alloc(&T.v, n));
+    RC(A.alloc(&T.perm, n));
+    k_gather_points<<<nblk(n), kT, 0, s>>>(pts, idx, xi0, eta0, n, T.x, T.y, T.z, xi, eta);
+    CSFMM_LAUNCH_CHECK();
+    CSFMM_HIP_TRY(hipMemcpyAsync(T.perm, idx, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+
+    // levels, breadth first
+    struct Lev {
+        int32_t n;
+        int32_t *face, *ci, *cj, *begin, *count, *child0;
+    };
+    std::vector<Lev> levs;
+    Lev L0{6};
+    RC(S.get(&L0.face, 6));
+    RC(S.get(&L0.ci, 6));
+    RC(S.get(&L0.cj, 6));
+    RC(S.get(&L0.begin, 6));
+    RC(S.get(&L0.count, 6));
+    RC(S.get(&L0.child0, 6));
+    k_roots<<<1, 64, 0, s>>>(keys, n, L0.face, L0.ci, L0.cj, L0.begin, L0.count);
+    CSFMM_LAUNCH_CHECK();
+    levs.push_back(L0);
+    int32_t* dtot;
+    RC(S.get(&dtot, 1));
+    int32_t total_cells = 6;
+    for (int l = 0;; ++l) {
+        Lev& cur = levs.back();
+        int32_t *flag, *off;
+        RC(S.get(&flag, cur.n));
+        RC(S.get(&off, cur.n));
+        k_split_flags<<<nblk(cur.n), kT, 0, s>>>(cur.count, cur.n, P->leaf, l, flag);
+        CSFMM_LAUNCH_CHECK();
+        RC(scan_exclusive_i32(flag, off, cur.n, dtot, s));
+        int32_t nsplit = 0;
+        RC(read_i32(dtot, &nsplit, s));
+        Lev nx{4 * nsplit};
+        if (nsplit > 0) {
+            RC(S.get(&nx.face, nx.n));
+            RC(S.get(&nx.ci, nx.n));
+            RC(S.get(&nx.cj, nx.n));
+            RC(S.get(&nx.begin, nx.n));
+            RC(S.get(&nx.count, nx.n));
+            RC(S.get(&nx.child0, nx.n));
+        }
+        k_children<<<nblk(cur.n), kT, 0, s>>>(keys, cur.n, l, flag, off, cur.face, cur.ci, cur.cj,
+                                              cur.begin, cur.count, total_cells, nx.n, cur.child0,
+                                              nx.face, nx.ci, nx.cj, nx.begin, nx.count);
+        CSFMM_LAUNCH_CHECK();
+        if (nsplit == 0) break;
+        if (int64_t(total_cells) + nx.n > (int64_t(1) << 30)) {
+            set_error("tree too large");
+            return CSFMM_E_INVALID;
+        }
+        total_cells += nx.n;
+        levs.push_back(nx);
+    }
+    T.depth = int32_t(levs.size()) - 1;
+    T.ncells = total_cells;
+    T.level_begin.assign(levs.size() + 1, 0);
+    for (size_t l = 0; l < levs.size(); ++l) T.level_begin[l + 1] = T.level_begin[l] + levs[l].n;
+    const int nc = T.ncells;
+    RC(A.alloc(&T.level, nc));
+    RC(A.alloc(&T.face, nc));
+    RC(A.alloc(&T.ci, nc));
+    RC(A.alloc(&T.cj, nc));
+    RC(A.alloc(&T.begin, nc));
+    RC(A.alloc(&T.count, nc));
+    RC(A.alloc(&T.child0, nc));
+    std::vector<int32_t> hl(nc);
+    for (size_t l = 0; l < levs.size(); ++l) {
+        const int32_t o = T.level_begin[l], m = levs[l].n;
+        for (int k = 0; k < m; ++k) hl[o + k] = int32_t(l);
+        const size_t b = sizeof(int32_t) * m;
+        CSFMM_HIP_TRY(hipMemcpyAsync(T.face + o, levs[l].face, b, hipMemcpyDeviceToDevice, s));
+        CSFMM_HIP_TRY(hipMemcpyAsync(T.ci + o, levs[l].ci, b, hipMemcpyDeviceToDevice, s));
+        CSFMM_HIP_TRY(hipMemcpyAsync(T.cj + o, levs[l].cj, b, hipMemcpyDeviceToDevice, s));
+        CSFMM_HIP_TRY(hipMemcpyAsync(T.begin + o, levs[l].begin, b, hipMemcpyDeviceToDevice, s));
+        CSFMM_HIP_TRY(hipMemcpyAsync(T.count + o, levs[l].count, b, hipMemcpyDeviceToDevice, s));
+        CSFMM_HIP_TRY(hipMemcpyAsync(T.child0 + o, levs[l].child0, b, hipMemcpyDeviceToDevice, s));
+    }
+    CSFMM_HIP_TRY(hipMemcpyAsync(T.level, hl.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s));
+    CSFMM_HIP_TRY(hipStreamSynchronize(s));  // hl goes out of scope
+
+    // leaves and parents (non-leaf cells, grouped by level)
+    int32_t *lf, *pf, *lo, *po;
+    RC(S.get(&lf, nc));
+    RC(S.get(&pf, nc));
+    RC(S.get(&lo, nc));
+    RC(S.get(&po, nc));
+    k_leaf_flags<<<nblk(nc), kT, 0, s>>>(T.child0, nc, lf, pf);
+    CSFMM_LAUNCH_CHECK();
+    RC(scan_exclusive_i32(lf, lo, nc, dtot, s));
+    int32_t nleaves = 0;
+    RC(read_i32(dtot, &nleaves, s));
+    RC(scan_exclusive_i32(pf, po, nc, dtot, s));
+    int32_t nparents = 0;
+    RC(read_i32(dtot, &nparents, s));
+    T.nleaves = nleaves;
+    RC(A.alloc(&T.leaves, nleaves));
+    RC(A.alloc(&T.parents, nparents));
+    k_compact<<<nblk(nc), kT, 0, s>>>(lf, lo, nc, T.leaves);
+    k_compact<<<nblk(nc), kT, 0, s>>>(pf, po, nc, T.parents);
+    CSFMM_LAUNCH_CHECK();
+    // per-level offsets into `parents`: exclusive-scan value at each level start
+    std::vector<int32_t> hpo(nc);
+    CSFMM_HIP_TRY(hipMemcpyAsync(hpo.data(), po, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+    CSFMM_HIP_TRY(hipStreamSynchronize(s));
+    T.parents_begin.assign(levs.size() + 1, nparents);
+    for (size_t l = 0; l < levs.size(); ++l) T.parents_begin[l] = hpo[T.level_begin[l]];
+
+    // geometry and proxies
+    RC(A.alloc(&T.center, int64_t(3) * nc));
+    RC(A.alloc(&T.radius, nc));
+    RC(A.alloc(&T.prox, int64_t(3) * P->KS * nc));
+    k_cell_geometry<<<nc, 128, 0, s>>>(nc, T.level, T.face, T.ci, T.cj, P->p, P->KS, T.center,
+                                       T.radius, T.prox);
+    CSFMM_LAUNCH_CHECK();
+    k_leaf_local<<<nleaves, 128, 0, s>>>(T.leaves, nleaves, T.level, T.ci, T.cj, T.begin, T.count,
+                                         xi, eta, T.u, T.v);
+    CSFMM_LAUNCH_CHECK();
+    CSFMM_HIP_TRY(hipStreamSynchronize(s));
+    return CSFMM_OK;
+}
+
+int build_lists(csfmm_plan_s* P, hipStream_t s) {
+    Tree& T = P->tt;
+    Tree& Sx = *P->st;
+    DevArena& A = P->arena;
+    Scratch S(s);
+    TravTree tt{T.level, T.count, T.child0, T.center, T.radius};
+    TravTree st{Sx.level, Sx.count, Sx.child0, Sx.center, Sx.radius};
+
+    struct Chunk {
+        int32_t *t, *s;
+        int32_t n;
+    };
+    std::vector<Chunk> out[4];
+    int32_t *ft, *fs;
+    int32_t nf = 36;
+    RC(S.get(&ft, nf));
+    RC(S.get(&fs, nf));
+    k_root_pairs<<<1, 64, 0, s>>>(ft, fs);
+    CSFMM_LAUNCH_CHECK();
+    int32_t* dtot;
+    RC(S.get(&dtot, 5));
+    for (int iter = 0; nf > 0; ++iter) {
+        if (iter > 4 * kMaxLevel + 8) {
+            set_error("traversal did not terminate");
+            return CSFMM_E_HIP;
+        }
+        int32_t *act, *c[5], *o[5];
+        RC(S.get(&act, nf));
+        for (int k = 0; k < 5; ++k) {
+            RC(S.get(&c[k], nf));
+            RC(S.get(&o[k], nf));
+        }
+        k_classify<<<nblk(nf), kT, 0, s>>>(ft, fs, nf, tt, st, P->theta, act, c[0], c[1], c[2],
+                                           c[3], c[4]);
+        CSFMM_LAUNCH_CHECK();
+        for (int k = 0; k < 5; ++k) RC(scan_exclusive_i32(c[k], o[k], nf, dtot + k, s));
+        int32_t tot[5];
+        CSFMM_HIP_TRY(hipMemcpyAsync(tot, dtot, sizeof(tot), hipMemcpyDeviceToHost, s));
+        CSFMM_HIP_TRY(hipStreamSynchronize(s));
+        Chunk ch[4];
+        for (int k = 0; k < 4; ++k) {
+            ch[k].n = tot[k];
+            RC(S.get(&ch[k].t, tot[k]));
+            RC(S.get(&ch[k].s, tot[k]));
+            if (tot[k] > 0) out[k].push_back(ch[k]);
+        }
+        int32_t *nt, *ns;
+        RC(S.get(&nt, tot[4]));
+        RC(S.get(&ns, tot[4]));
+        k_emit<<<nblk(nf), kT, 0, s>>>(ft, fs, nf, act, o[0], o[1], o[2], o[3], o[4], T.child0,
+                                       Sx.child0, ch[0].t, ch[0].s, ch[1].t, ch[1].s, ch[2].t,
+                                       ch[2].s, ch[3].t, ch[3].s, nt, ns,
+                                       Caps{{tot[0], tot[1], tot[2], tot[3], tot[4]}});
+        CSFMM_LAUNCH_CHECK();
+        ft = nt;
+        fs = ns;
+        nf = tot[4];
+    }
+
+    // concatenate, sort by (target, source), CSR by target cell
+    const int64_t nsc = Sx.ncells;
+    const int64_t maxkey = int64_t(T.ncells) * nsc;
+    int bits = 1;
+    while (bits < 63 && (int64_t(1) << bits) < maxkey) ++bits;
+    for (int k = 0; k < 4; ++k) {
+        int64_t cnt = 0;
+        for (auto& c : out[k]) cnt += c.n;
+        P->lists.cnt[k] = cnt;
+        int32_t *lt, *ls;
+        RC(S.get(&lt, cnt));
+        RC(S.get(&ls, cnt));
+        int64_t pos = 0;
+        for (auto& c : out[k]) {
+            CSFMM_HIP_TRY(hipMemcpyAsync(lt + pos, c.t, sizeof(int32_t) * c.n, hipMemcpyDeviceToDevice, s));
+            CSFMM_HIP_TRY(hipMemcpyAsync(ls + pos, c.s, sizeof(int32_t) * c.n, hipMemcpyDeviceToDevice, s));
+            pos += c.n;
+        }
+        uint64_t* keys;
+        int32_t* vals;
+        RC(S.get(&keys, cnt));
+        RC(S.get(&vals, cnt));
+        if (cnt > 0) {
+            k_pair_keys<<<nblk(cnt), kT, 0, s>>>(lt, ls, cnt, nsc, keys, vals);
+            CSFMM_LAUNCH_CHECK();
+            RC(radix_sort_u64(keys, vals, cnt, bits, s));
+        }
+        RC(A.alloc(&P->lists.off[k], int64_t(T.ncells) + 1));
+        RC(A.alloc(&P->lists.src[k], cnt));
+        const int64_t m = std::max<int64_t>(cnt, int64_t(T.ncells) + 1);
+        k_csr_from_keys<<<nblk(m), kT, 0, s>>>(keys, cnt, nsc, T.ncells, P->lists.off[k],
+                                               P->lists.src[k]);
+        CSFMM_LAUNCH_CHECK();
+    }
+    // target cells with far-field (CP or CC) work
+    int32_t *ff, *fo;
+    RC(S.get(&ff, T.ncells));
+    RC(S.get(&fo, T.ncells));
+    k_far_flags<<<nblk(T.ncells), kT, 0, s>>>(P->lists.off[kCP], P->lists.off[kCC], T.ncells, ff);
+    CSFMM_LAUNCH_CHECK();
+    RC(scan_exclusive_i32(ff, fo, T.ncells, dtot, s));
+    int32_t nfar = 0;
+    RC(read_i32(dtot, &nfar, s));
+    P->lists.n_far_targets = nfar;
+    RC(A.alloc(&P->lists.far_targets, nfar));
+    k_compact<<<nblk(T.ncells), kT, 0, s>>>(ff, fo, T.ncells, P->lists.far_targets);
+    CSFMM_LAUNCH_CHECK();
+
+    // evaluation counts (host arithmetic on copies of the lists)
+    std::vector<int32_t> tc(T.ncells), sc(Sx.ncells);
+    CSFMM_HIP_TRY(hipMemcpyAsync(tc.data(), T.count, sizeof(int32_t) * T.ncells, hipMemcpyDeviceToHost, s));
+    CSFMM_HIP_TRY(hipMemcpyAsync(sc.data(), Sx.count, sizeof(int32_t) * Sx.ncells, hipMemcpyDeviceToHost, s));
+    for (int k = 0; k < 4; ++k) {
+        const int64_t cnt = P->lists.cnt[k];
+        std::vector<int32_t> off(T.ncells + 1), src(std::max<int64_t>(cnt, 1));
+        CSFMM_HIP_TRY(hipMemcpyAsync(off.data(), P->lists.off[k], sizeof(int32_t) * (T.ncells + 1), hipMemcpyDeviceToHost, s));
+        if (cnt > 0)
+            CSFMM_HIP_TRY(hipMemcpyAsync(src.data(), P->lists.src[k], sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, s));
+        CSFMM_HIP_TRY(hipStreamSynchronize(s));
+        int64_t ev = 0;
+        for (int t = 0; t < T.ncells; ++t)
+            for (int e = off[t]; e < off[t + 1]; ++e) {
+                const int64_t nt = (k == kPP || k == kPC) ? tc[t] : P->K;
+                const int64_t nsrc = (k == kPP || k == kCP) ? sc[src[e]] : P->K;
+                ev += nt * nsrc;
+                if (k == kPP && P->same && src[e] == t) ev -= tc[t];
+            }
+        P->lists.evals[k] = ev;
+    }
+    return CSFMM_OK;
+}
+
+}  // namespace
+
+int build_plan(csfmm_plan_s* P, const double* targets, const double* sources, hipStream_t s) {
+    DevArena& A = P->arena;
+    {
+        Scratch S(s);
+        int* bad;
+        RC(S.get(&bad, 1));
+        CSFMM_HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), s));
+        k_check_points<<<nblk(P->nt), kT, 0, s>>>(targets, P->nt, bad);
+        CSFMM_LAUNCH_CHECK();
+        if (!P->same) {
+            k_check_points<<<nblk(P->ns), kT, 0, s>>>(sources, P->ns, bad);
+            CSFMM_LAUNCH_CHECK();
+        }
+        int hbad = 0;
+        CSFMM_HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        CSFMM_HIP_TRY(hipStreamSynchronize(s));
+        if (hbad) {
+            set_error("a point is not finite or not on the unit sphere (| |x| - 1 | > 1e-12)");
+            return CSFMM_E_NOT_ON_SPHERE;
+        }
+    }
+    RC(build_tree(P, P->tt, targets, P->nt, s));
+    if (P->same) {
+        P->st = &P->tt;
+    } else {
+        RC(build_tree(P, P->st_own, sources, P->ns, s));
+        P->st = &P->st_own;
+    }
+    // fixed interpolation operators
+    P->nb1 = int(round_up(P->KS, 16));
+    P->nb2 = int(round_up(4 * P->KS, 16));
+    RC(A.alloc(&P->lag1d, 2 * (P->p + 1) * (P->p + 1)));
+    RC(A.alloc(&P->bm2m, int64_t(4) * P->KS * P->nb1));
+    RC(A.alloc(&P->bl2l, int64_t(P->KS) * P->nb2));
+    k_build_ops<<<1, 256, 0, s>>>(P->p, P->KS, P->nb1, P->nb2, P->lag1d, P->bm2m, P->bl2l);
+    CSFMM_LAUNCH_CHECK();
+    RC(build_lists(P, s));
+    // eval workspace
+    const int vd = 3;
+    RC(A.alloc(&P->ws, P->ns));
+    RC(A.alloc(&P->wbar, int64_t(P->st->ncells) * P->KS));
+    RC(A.alloc(&P->psi, int64_t(vd) * P->tt.ncells * P->KS));
+    RC(A.alloc(&P->phinear, int64_t(vd) * P->nt));
+    CSFMM_HIP_TRY(hipStreamSynchronize(s));
+    return CSFMM_OK;
+}
+
+}  // namespace csfmm

@@ -1,0 +1,529 @@
+// Tile engine: the direct sums behind the four interactions of paper §5
+// (eq. PP, PC, CP, CC) and the direct method of §1.
+//
+// All four interactions are sums  out(t) = sum_s K(t, s) w_s  of one target
+// set against a list of source sets (paper §5 notes they are all direct
+// sums).  One workgroup owns one target cell:
+//   near kernel: targets = the particles of a target leaf; sources = the
+//                particles of its PP cells, then the proxies (with proxy
+//                weights) of its PC cells;
+//   far kernel:  targets = the (p+1)^2 proxies of a target cell; sources =
+//                the particles of its CP cells, then the proxies of its CC
+//                cells; the result is its accumulated proxy potential
+//                (eq. CP_CC_accumulated).
+// The source list is flattened and staged through LDS in chunks, recentred
+// at the target cell's centre in FP64 (and, in the FP32 form, converted to
+// FP32 after recentring).  Thread (t, g) of the 256 owns target t and the
+// sources g, g+G, ... of each chunk; the G partial sums of a target are
+// combined in FP64 in a fixed order, so results are deterministic.
+//
+// Kernels (x, y unit vectors, 1 - x.y = |x-y|^2/2):
+//   Poisson   -(1/4pi) ln(1 - x.y): coordinates scaled by 1/sqrt2 so that the
+//             squared distance is 1 - x.y; FP32 uses log2 and folds ln 2 in.
+//   Biot-Savart -(1/4pi) (x cross y)/(1 - x.y) = -(1/2pi) x cross sum (y-x) w/|x-y|^2.
+//   1/|x-y|   rsqrt of the squared distance.
+// The self term (squared distance exactly 0) contributes nothing.
+#include <type_traits>
+
+#include "common.h"
+#include "dev_util.h"
+
+namespace csfmm {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kChunk = 512;
+constexpr int kMaxEntries = 256;
+constexpr double kInvSqrt2 = 0.70710678118654752440;
+constexpr double kLn2 = 0.69314718055994530942;
+
+template <bool F32>
+using Real = typename std::conditional<F32, float, double>::type;
+
+template <bool F32>
+struct alignas(F32 ? 16 : 32) Src {
+    Real<F32> x, y, z, w;
+};
+
+template <int KERN>
+constexpr int vdim() {
+    return KERN == CSFMM_K_BIOT_SAVART ? 3 : 1;
+}
+
+template <int KERN>
+constexpr double coord_scale() {
+    return KERN == CSFMM_K_POISSON_LOG ? kInvSqrt2 : 1.0;
+}
+
+__device__ __forceinline__ float dev_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float dev_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float dev_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// One kernel evaluation, accumulated into p[].
+template <int KERN, bool F32>
+__device__ __forceinline__ void interact(Real<F32> tx, Real<F32> ty, Real<F32> tz,
+                                         const Src<F32>& s, Real<F32>* p) {
+    using R = Real<F32>;
+    const R dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    if constexpr (KERN == CSFMM_K_POISSON_LOG) {
+        R lg;
+        if constexpr (F32)
+            lg = dev_log2(r2);
+        else
+            lg = log(r2);
+        lg = r2 > R(0) ? lg : R(0);
+        p[0] = fma(s.w, lg, p[0]);
+    } else if constexpr (KERN == CSFMM_K_BIOT_SAVART) {
+        R inv;
+        if constexpr (F32)
+            inv = dev_rcp(r2);
+        else
+            inv = R(1) / r2;
+        const R f = r2 > R(0) ? s.w * inv : R(0);
+        p[0] = fma(dx, f, p[0]);
+        p[1] = fma(dy, f, p[1]);
+        p[2] = fma(dz, f, p[2]);
+    } else {
+        R inv;
+        if constexpr (F32)
+            inv = dev_rsq(r2);
+        else
+            inv = rsqrt(r2);
+        const R f = r2 > R(0) ? inv : R(0);
+        p[0] = fma(s.w, f, p[0]);
+    }
+}
+
+// Final scaling of an accumulated sum at a target point (x, y, z) (FP64).
+template <int KERN, bool F32>
+__device__ __forceinline__ void epilogue(const double* acc, double x, double y, double z,
+                                         double* out) {
+    if constexpr (KERN == CSFMM_K_POISSON_LOG) {
+        out[0] = (F32 ? -kLn2 / (4.0 * kPi) : -1.0 / (4.0 * kPi)) * acc[0];
+    } else if constexpr (KERN == CSFMM_K_BIOT_SAVART) {
+        const double c = -1.0 / (2.0 * kPi);
+        out[0] = c * (y * acc[2] - z * acc[1]);
+        out[1] = c * (z * acc[0] - x * acc[2]);
+        out[2] = c * (x * acc[1] - y * acc[0]);
+    } else {
+        out[0] = acc[0];
+    }
+}
+
+struct TileArgs {
+    const int32_t* tcells;
+    const int32_t *tbegin, *tcount;
+    const double* tcenter;
+    const double *tx, *ty, *tz;  // target particles (near kernel)
+    const double* tprox;         // target proxies [cell][3][KS] (far kernel)
+    const int32_t *off_a, *src_a;  // list with particle sources (PP or CP)
+    const int32_t *off_b, *src_b;  // list with proxy sources (PC or CC)
+    const int32_t *sbegin, *scount;
+    const double *sx, *sy, *sz, *sw;
+    const double *sprox, *swbar;
+    int K, KS;
+    double* out;
+    int64_t comp_stride;
+};
+
+template <int KERN, bool F32, bool TPROX>
+__global__ __launch_bounds__(kThreads) void k_tile(TileArgs a) {
+    using R = Real<F32>;
+    constexpr int VD = vdim<KERN>();
+    constexpr double scale = coord_scale<KERN>();
+    __shared__ Src<F32> src[kChunk];
+    __shared__ int e_code[kMaxEntries];
+    __shared__ int e_pref[kMaxEntries + 1];
+    __shared__ int lw[4];
+    __shared__ double red[VD][kThreads];
+
+    const int T = a.tcells[xcd_logical_block(blockIdx.x, gridDim.x)];
+    const int tid = threadIdx.x;
+    const double cx = a.tcenter[3 * T], cy = a.tcenter[3 * T + 1], cz = a.tcenter[3 * T + 2];
+    const int KS = a.KS;
+    const int nT = TPROX ? a.K : a.tcount[T];
+    const int tb = TPROX ? 0 : a.tbegin[T];
+    const int ea0 = a.off_a[T], nea = a.off_a[T + 1] - ea0;
+    const int eb0 = a.off_b[T], neb = a.off_b[T + 1] - eb0;
+    const int ne_all = nea + neb;
+
+    for (int t0 = 0; t0 < nT; t0 += kThreads) {
+        const int TC = min(nT - t0, kThreads);
+        const int G = kThreads / TC;
+        const int t = tid % TC, g = tid / TC;
+        const bool active = g < G;
+        double gx = cx, gy = cy, gz = cz;
+        if (active) {
+            if constexpr (TPROX) {
+                const double* pc = a.tprox + int64_t(T) * 3 * KS;
+                gx = pc[t0 + t];
+                gy = pc[KS + t0 + t];
+                gz = pc[2 * KS + t0 + t];
+            } else {
+                gx = a.tx[tb + t0 + t];
+                gy = a.ty[tb + t0 + t];
+                gz = a.tz[tb + t0 + t];
+            }
+        }
+        const R qx = R((gx - cx) * scale), qy = R((gy - cy) * scale), qz = R((gz - cz) * scale);
+        double acc[VD];
+#pragma unroll
+        for (int v = 0; v < VD; ++v) acc[v] = 0.0;
+
+        for (int ebase = 0; ebase < ne_all; ebase += kMaxEntries) {
+            const int ne = min(kMaxEntries, ne_all - ebase);
+            int sz = 0;
+            if (tid < ne) {
+                const int e = ebase + tid;
+                if (e < nea) {
+                    const int s = a.src_a[ea0 + e];
+                    e_code[tid] = a.sbegin[s];
+                    sz = a.scount[s];
+                } else {
+                    const int s = a.src_b[eb0 + e - nea];
+                    e_code[tid] = -(s + 1);
+                    sz = a.K;
+                }
+            }
+            const int incl = block_scan_incl_256(sz, lw);
+            e_pref[tid] = incl - sz;
+            if (tid == kThreads - 1) e_pref[kMaxEntries] = incl;
+            __syncthreads();
+            const int total = e_pref[kMaxEntries];
+            for (int q0 = 0; q0 < total; q0 += kChunk) {
+                const int nq = min(kChunk, total - q0);
+                for (int q = tid; q < nq; q += kThreads) {
+                    const int gq = q0 + q;
+                    int lo = 0, hi = ne - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (e_pref[mid] <= gq)
+                            lo = mid;
+                        else
+                            hi = mid - 1;
+                    }
+                    const int o = gq - e_pref[lo];
+                    const int code = e_code[lo];
+                    double yx, yy, yz, w;
+                    if (code >= 0) {
+                        const int j = code + o;
+                        yx = a.sx[j];
+                        yy = a.sy[j];
+                        yz = a.sz[j];
+                        w = a.sw[j];
+                    } else {
+                        const int64_t s = -(code + 1);
+                        const double* ps = a.sprox + s * 3 * KS;
+                        yx = ps[o];
+                        yy = ps[KS + o];
+                        yz = ps[2 * KS + o];
+                        w = a.swbar[s * KS + o];
+                    }
+                    Src<F32> e;
+                    e.x = R((yx - cx) * scale);
+                    e.y = R((yy - cy) * scale);
+                    e.z = R((yz - cz) * scale);
+                    e.w = R(w);
+                    src[q] = e;
+                }
+                __syncthreads();
+                if (active) {
+                    R p[VD];
+#pragma unroll
+                    for (int v = 0; v < VD; ++v) p[v] = R(0);
+                    for (int j = g; j < nq; j += G) interact<KERN, F32>(qx, qy, qz, src[j], p);
+#pragma unroll
+                    for (int v = 0; v < VD; ++v) acc[v] += double(p[v]);
+                }
+                __syncthreads();
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < VD; ++v) red[v][tid] = active ? acc[v] : 0.0;
+        __syncthreads();
+        if (tid < TC) {
+            double r[VD], o[VD];
+#pragma unroll
+            for (int v = 0; v < VD; ++v) {
+                r[v] = 0.0;
+                for (int gg = 0; gg < G; ++gg) r[v] += red[v][gg * TC + tid];
+            }
+            epilogue<KERN, F32>(r, gx, gy, gz, o);
+            const int64_t base = TPROX ? int64_t(T) * KS + t0 + tid : int64_t(tb) + t0 + tid;
+#pragma unroll
+            for (int v = 0; v < VD; ++v) a.out[v * a.comp_stride + base] = o[v];
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------- direct
+// Direct sum over all sources (paper §1).  Grid (target blocks of 64, source
+// splits); FP32 form on hi/lo split coordinates.  Partial sums per split
+// [split][VD][nt] are combined in order by k_direct_reduce.
+template <bool F32>
+struct DSrc;
+template <>
+struct alignas(16) DSrc<true> {
+    float hx, hy, hz, w, lx, ly, lz, pad;
+};
+template <>
+struct alignas(32) DSrc<false> {
+    double x, y, z, w;
+};
+
+template <int KERN, bool F32>
+__global__ __launch_bounds__(kThreads) void k_direct(const double* __restrict__ tgt, int64_t nt,
+                                                     const double* __restrict__ srcp, int64_t ns,
+                                                     const double* __restrict__ w, int64_t nsp,
+                                                     double* __restrict__ part) {
+    using R = Real<F32>;
+    constexpr int VD = vdim<KERN>();
+    __shared__ DSrc<F32> src[kChunk];
+    __shared__ double red[VD][kThreads];
+    const int tid = threadIdx.x;
+    const int t = tid & 63, g = tid >> 6;  // 64 targets x 4 source groups
+    const int64_t i = int64_t(blockIdx.x) * 64 + t;
+    const bool valid = i < nt;
+    const double gx = valid ? tgt[3 * i] : 0.0, gy = valid ? tgt[3 * i + 1] : 0.0,
+                 gz = valid ? tgt[3 * i + 2] : 0.0;
+    R hx, hy, hz, lx = R(0), ly = R(0), lz = R(0);
+    hx = R(gx);
+    hy = R(gy);
+    hz = R(gz);
+    if constexpr (F32) {
+        lx = R(gx - double(hx));
+        ly = R(gy - double(hy));
+        lz = R(gz - double(hz));
+    }
+    const int64_t s0 = int64_t(blockIdx.y) * nsp;
+    const int64_t s1 = (s0 + nsp < ns) ? s0 + nsp : ns;
+    double acc[VD];
+#pragma unroll
+    for (int v = 0; v < VD; ++v) acc[v] = 0.0;
+    for (int64_t q0 = s0; q0 < s1; q0 += kChunk) {
+        const int nq = int((s1 - q0 < kChunk) ? s1 - q0 : int64_t(kChunk));
+        for (int q = tid; q < nq; q += kThreads) {
+            const int64_t j = q0 + q;
+            const double yx = srcp[3 * j], yy = srcp[3 * j + 1], yz = srcp[3 * j + 2];
+            DSrc<F32> e;
+            if constexpr (F32) {
+                e.hx = float(yx);
+                e.hy = float(yy);
+                e.hz = float(yz);
+                e.lx = float(yx - double(e.hx));
+                e.ly = float(yy - double(e.hy));
+                e.lz = float(yz - double(e.hz));
+                e.w = float(w[j]);
+                e.pad = 0.f;
+            } else {
+                e.x = yx;
+                e.y = yy;
+                e.z = yz;
+                e.w = w[j];
+            }
+            src[q] = e;
+        }
+        __syncthreads();
+        R p[VD];
+#pragma unroll
+        for (int v = 0; v < VD; ++v) p[v] = R(0);
+        for (int j = g; j < nq; j += 4) {
+            const DSrc<F32>& e = src[j];
+            R dx, dy, dz;
+            if constexpr (F32) {
+                dx = (e.hx - hx) + (e.lx - lx);
+                dy = (e.hy - hy) + (e.ly - ly);
+                dz = (e.hz - hz) + (e.lz - lz);
+            } else {
+                dx = e.x - hx;
+                dy = e.y - hy;
+                dz = e.z - hz;
+            }
+            const R r2 = dx * dx + dy * dy + dz * dz;
+            if constexpr (KERN == CSFMM_K_POISSON_LOG) {
+                R lg;
+                if constexpr (F32)
+                    lg = dev_log2(R(0.5) * r2);
+                else
+                    lg = log(R(0.5) * r2);
+                lg = r2 > R(0) ? lg : R(0);
+                p[0] = fma(e.w, lg, p[0]);
+            } else if constexpr (KERN == CSFMM_K_BIOT_SAVART) {
+                R inv;
+                if constexpr (F32)
+                    inv = dev_rcp(r2);
+                else
+                    inv = R(1) / r2;
+                const R f = r2 > R(0) ? e.w * inv : R(0);
+                p[0] = fma(dx, f, p[0]);
+                p[1] = fma(dy, f, p[1]);
+                p[2] = fma(dz, f, p[2]);
+            } else {
+                R inv;
+                if constexpr (F32)
+                    inv = dev_rsq(r2);
+                else
+                    inv = rsqrt(r2);
+                const R f = r2 > R(0) ? inv : R(0);
+                p[0] = fma(e.w, f, p[0]);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < VD; ++v) acc[v] += double(p[v]);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int v = 0; v < VD; ++v) red[v][tid] = acc[v];
+    __syncthreads();
+    if (tid < 64 && valid) {
+#pragma unroll
+        for (int v = 0; v < VD; ++v) {
+            const double r = red[v][tid] + red[v][64 + tid] + red[v][128 + tid] + red[v][192 + tid];
+            part[(int64_t(blockIdx.y) * VD + v) * nt + i] = r;
+        }
+    }
+}
+
+template <int KERN, bool F32>
+__global__ void k_direct_reduce(const double* __restrict__ tgt, int64_t nt,
+                                const double* __restrict__ part, int nsplit,
+                                double* __restrict__ out) {
+    constexpr int VD = vdim<KERN>();
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    double acc[VD], o[VD];
+#pragma unroll
+    for (int v = 0; v < VD; ++v) {
+        acc[v] = 0.0;
+        for (int sp = 0; sp < nsplit; ++sp) acc[v] += part[(int64_t(sp) * VD + v) * nt + i];
+    }
+    epilogue<KERN, F32>(acc, tgt[3 * i], tgt[3 * i + 1], tgt[3 * i + 2], o);
+    // Biot-Savart acc holds sum (y - x) w / |x-y|^2 like the tile kernels.
+#pragma unroll
+    for (int v = 0; v < VD; ++v) out[i * VD + v] = o[v];
+}
+
+template <int KERN, bool F32, bool TPROX>
+int launch_tile_t(const TileArgs& a, int nblocks, hipStream_t s) {
+    if (nblocks <= 0) return CSFMM_OK;
+    k_tile<KERN, F32, TPROX><<<nblocks, kThreads, 0, s>>>(a);
+    CSFMM_LAUNCH_CHECK();
+    return CSFMM_OK;
+}
+
+template <bool TPROX>
+int launch_tile(int kernel, bool f32, const TileArgs& a, int nblocks, hipStream_t s) {
+    switch (kernel) {
+        case CSFMM_K_POISSON_LOG:
+            return f32 ? launch_tile_t<1, true, TPROX>(a, nblocks, s)
+                       : launch_tile_t<1, false, TPROX>(a, nblocks, s);
+        case CSFMM_K_BIOT_SAVART:
+            return f32 ? launch_tile_t<2, true, TPROX>(a, nblocks, s)
+                       : launch_tile_t<2, false, TPROX>(a, nblocks, s);
+        case CSFMM_K_INV_DIST:
+            return f32 ? launch_tile_t<3, true, TPROX>(a, nblocks, s)
+                       : launch_tile_t<3, false, TPROX>(a, nblocks, s);
+        default:
+            set_error("unknown kernel id %d", kernel);
+            return CSFMM_E_INVALID;
+    }
+}
+
+TileArgs common_args(csfmm_plan_s* P) {
+    TileArgs a{};
+    const Tree& T = P->tt;
+    const Tree& S = *P->st;
+    a.tbegin = T.begin;
+    a.tcount = T.count;
+    a.tcenter = T.center;
+    a.tx = T.x;
+    a.ty = T.y;
+    a.tz = T.z;
+    a.tprox = T.prox;
+    a.sbegin = S.begin;
+    a.scount = S.count;
+    a.sx = S.x;
+    a.sy = S.y;
+    a.sz = S.z;
+    a.sw = P->ws;
+    a.sprox = S.prox;
+    a.swbar = P->wbar;
+    a.K = P->K;
+    a.KS = P->KS;
+    return a;
+}
+
+template <int KERN, bool F32>
+int launch_direct_t(const double* tgt, int64_t nt, const double* src, int64_t ns, const double* w,
+                    double* out, hipStream_t s) {
+    constexpr int VD = vdim<KERN>();
+    const int64_t ntb = (nt + 63) / 64;
+    const int64_t maxsplit = (ns + kChunk - 1) / kChunk;
+    int64_t nsplit = (4096 + ntb - 1) / ntb;
+    nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, std::min<int64_t>(maxsplit, 65535)));
+    const int64_t nsp = (ns + nsplit - 1) / nsplit;
+    double* part = nullptr;
+    CSFMM_HIP_TRY(hipMallocAsync((void**)&part, sizeof(double) * size_t(nsplit * VD * nt), s));
+    k_direct<KERN, F32><<<dim3(unsigned(ntb), unsigned(nsplit)), kThreads, 0, s>>>(tgt, nt, src, ns,
+                                                                                  w, nsp, part);
+    hipError_t e1 = hipGetLastError();
+    k_direct_reduce<KERN, F32><<<unsigned((nt + 255) / 256), 256, 0, s>>>(tgt, nt, part,
+                                                                          int(nsplit), out);
+    hipError_t e2 = hipGetLastError();
+    (void)hipFreeAsync(part, s);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        set_error("direct launch failed: %s",
+                  hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        return CSFMM_E_HIP;
+    }
+    return CSFMM_OK;
+}
+
+}  // namespace
+
+int launch_near(csfmm_plan_s* P, int kernel, hipStream_t s) {
+    TileArgs a = common_args(P);
+    a.tcells = P->tt.leaves;
+    a.off_a = P->lists.off[kPP];
+    a.src_a = P->lists.src[kPP];
+    a.off_b = P->lists.off[kPC];
+    a.src_b = P->lists.src[kPC];
+    a.out = P->phinear;
+    a.comp_stride = P->nt;
+    return launch_tile<false>(kernel, (P->flags & CSFMM_FP32_FORM) != 0, a, P->tt.nleaves, s);
+}
+
+int launch_far(csfmm_plan_s* P, int kernel, hipStream_t s) {
+    TileArgs a = common_args(P);
+    a.tcells = P->lists.far_targets;
+    a.off_a = P->lists.off[kCP];
+    a.src_a = P->lists.src[kCP];
+    a.off_b = P->lists.off[kCC];
+    a.src_b = P->lists.src[kCC];
+    a.out = P->psi;
+    a.comp_stride = int64_t(P->tt.ncells) * P->KS;
+    return launch_tile<true>(kernel, (P->flags & CSFMM_FP32_FORM) != 0, a,
+                             P->lists.n_far_targets, s);
+}
+
+int launch_direct(const double* tgt, int64_t nt, const double* src, int64_t ns, const double* w,
+                  int kernel, bool fp32, double* out, hipStream_t s) {
+    switch (kernel) {
+        case CSFMM_K_POISSON_LOG:
+            return fp32 ? launch_direct_t<1, true>(tgt, nt, src, ns, w, out, s)
+                        : launch_direct_t<1, false>(tgt, nt, src, ns, w, out, s);
+        case CSFMM_K_BIOT_SAVART:
+            return fp32 ? launch_direct_t<2, true>(tgt, nt, src, ns, w, out, s)
+                        : launch_direct_t<2, false>(tgt, nt, src, ns, w, out, s);
+        case CSFMM_K_INV_DIST:
+            return fp32 ? launch_direct_t<3, true>(tgt, nt, src, ns, w, out, s)
+                        : launch_direct_t<3, false>(tgt, nt, src, ns, w, out, s);
+        default:
+            set_error("unknown kernel id %d", kernel);
+            return CSFMM_E_INVALID;
+    }
+}
+
+}  // namespace csfmm

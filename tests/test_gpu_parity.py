@@ -1,0 +1,266 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+* direct sum vs the FP64 oracle;
+* plan internals (tree cells, point sets, geometry, proxies, interaction
+  lists) vs the oracle's tree and traversal: integers bit-exact, geometry to
+  rounding;
+* eval stages (proxy weights, proxy potentials, near field) and results vs the
+  oracle FMM to rounding (same algorithm, other summation order), and vs the
+  direct-sum oracle within the approximation gate;
+* degenerate cases, distinct sets, adaptive trees, determinism, FP32 form.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2508_13550_amd as cs
+from workloads import cubed_sphere_grid, random_sphere_points, real_y43, real_y41
+from oracle import direct as odirect
+from oracle import fmm as F
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def tdev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel_l2(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+def rel_max(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _announce(msg):
+    print("\n[gpu case] " + msg, flush=True)
+
+
+# ------------------------------------------------------------------ direct
+
+@pytest.mark.parametrize("kernel", [1, 2, 3])
+def test_direct_matches_oracle(kernel):
+    _announce("direct config-1 grid kernel %d" % kernel)
+    P, A = cubed_sphere_grid(32)
+    w = real_y43(P) * A
+    ref = odirect(kernel, P, P, w)
+    got = host(cs.direct(tdev(P), tdev(P), tdev(w), kernel=kernel))
+    assert rel_l2(got, ref) < 1e-13 and rel_max(got, ref) < 1e-12
+    got32 = host(cs.direct(tdev(P), tdev(P), tdev(w), kernel=kernel, fp32=True))
+    assert rel_l2(got32, ref) < 2e-6
+
+
+def test_direct_distinct_and_ragged():
+    _announce("direct distinct sets, ragged sizes")
+    S, A = cubed_sphere_grid(8)
+    X = random_sphere_points(1001, 5)
+    X[:3] = S[[0, 7, 100]]  # exact coincidences are skipped
+    w = np.random.default_rng(1).standard_normal(S.shape[0])
+    for k in (1, 2, 3):
+        ref = odirect(k, X, S, w)
+        got = host(cs.direct(tdev(X), tdev(S), tdev(w), kernel=k))
+        assert rel_max(got, ref) < 1e-12
+    one = host(cs.direct(tdev(X[:1]), tdev(S[:1]), tdev(w[:1]), kernel=1))
+    assert one[0] == 0.0  # the only source coincides with the target
+
+
+# ------------------------------------------------------------------ plan internals
+
+def _compare_tree(plan, otree, which):
+    c = plan.cells(which)
+    n = len(otree.cells)
+    assert c["level"].shape[0] == n
+    lv = np.array([C.level for C in otree.cells])
+    fc = np.array([C.face for C in otree.cells])
+    ii = np.array([C.i for C in otree.cells])
+    jj = np.array([C.j for C in otree.cells])
+    cnt = np.array([C.count for C in otree.cells])
+    ch0 = np.array([-1 if C.is_leaf else C.children[0].id for C in otree.cells])
+    assert np.array_equal(c["level"], lv)
+    assert np.array_equal(c["face"], fc)
+    assert np.array_equal(c["ci"], ii) and np.array_equal(c["cj"], jj)
+    assert np.array_equal(c["count"], cnt)
+    assert np.array_equal(c["child0"], ch0)
+    perm = plan.permutation(which)
+    assert np.array_equal(np.sort(perm), np.arange(perm.shape[0]))
+    for k, C in enumerate(otree.cells):
+        got = np.sort(perm[c["begin"][k]:c["begin"][k] + c["count"][k]])
+        assert np.array_equal(got, np.sort(C.idx))
+    cen = np.array([C.center for C in otree.cells])
+    rad = np.array([C.radius for C in otree.cells])
+    assert np.max(np.abs(c["center"] - cen)) < 4e-16
+    assert np.max(np.abs(c["radius"] - rad) / rad) < 1e-14
+    prox = plan.proxies(which)
+    oprox = np.array([C.proxies for C in otree.cells])
+    assert np.max(np.abs(prox - oprox)) < 4e-16
+
+
+def _compare_lists(plan, ofmm):
+    got = plan.lists()
+    for kind in ("PP", "PC", "CP", "CC"):
+        t, s = got[kind]
+        mine = sorted(zip(t.tolist(), s.tolist()))
+        ref = sorted((T.id, S.id) for T, S in ofmm.lists[kind])
+        assert mine == ref, kind
+
+
+CASES = {
+    # name: (targets, sources or None, kernel, p, theta, leaf)
+    "config1": lambda: (cubed_sphere_grid(32)[0], None, 1, 8, 0.7, 64),
+    "grid_E64_leaf128": lambda: (cubed_sphere_grid(64)[0], None, 1, 6, 0.7, 128),
+    "ragged_leaf50": lambda: (cubed_sphere_grid(32)[0], None, 3, 5, 0.6, 50),
+    "distinct_random": lambda: (random_sphere_points(3000, 41), cubed_sphere_grid(16)[0], 2, 6, 0.6, 40),
+    "clustered": lambda: (_clustered(), None, 1, 4, 0.5, 12),
+    "tiny_p1_leaf1": lambda: (cubed_sphere_grid(2)[0], None, 1, 1, 0.5, 1),
+}
+
+
+def _clustered():
+    X = random_sphere_points(2500, 9)
+    X = X[X[:, 2] > 0.3]
+    return np.concatenate([X, random_sphere_points(300, 10)])
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def case(request):
+    name = request.param
+    T, S, k, p, th, leaf = CASES[name]()
+    _announce("plan case %s: n_t=%d n_s=%s kernel=%d p=%d theta=%g leaf=%d"
+              % (name, T.shape[0], None if S is None else S.shape[0], k, p, th, leaf))
+    ofmm = F.FMM(T, S, k, p, th, leaf)
+    plan = cs.Plan(tdev(T), None if S is None else tdev(S), kernel=k, p=p, theta=th, leaf_size=leaf)
+    yield name, T, S, k, p, th, leaf, ofmm, plan
+    plan.close()
+
+
+def test_tree_and_geometry(case):
+    name, T, S, k, p, th, leaf, ofmm, plan = case
+    _compare_tree(plan, ofmm.ttree, 0)
+    if S is not None:
+        _compare_tree(plan, ofmm.stree, 1)
+
+
+def test_lists(case):
+    name, T, S, k, p, th, leaf, ofmm, plan = case
+    _compare_lists(plan, ofmm)
+    st = plan.stats()
+    assert st["n_pp"] == len(ofmm.lists["PP"]) and st["n_cc"] == len(ofmm.lists["CC"])
+
+
+def test_stages_and_result(case):
+    name, T, S, k, p, th, leaf, ofmm, plan = case
+    src = T if S is None else S
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal(src.shape[0])
+    ref, stg = ofmm.evaluate(w, stages=True)
+    out, wbar, psi, near = plan.eval_stages(tdev(w))
+    out, wbar, psi, near = host(out), host(wbar), host(psi), host(near)
+    # proxy weights after the upward pass
+    ow = np.array([stg["wbar"][C.id].reshape(-1) for C in ofmm.stree.cells])
+    assert rel_max(wbar, ow) < 1e-13
+    # proxy potentials after the downward pass, on the cells that hold targets
+    # (the library also interpolates into empty cells, which the oracle skips)
+    vd = 3 if k == 2 else 1
+    n1 = p + 1
+    op = np.zeros((vd, len(ofmm.ttree.cells), n1 * n1))
+    for cid, val in stg["psi"].items():
+        op[:, cid, :] = np.asarray(val).reshape(n1 * n1, vd).T
+    full = np.array([C.count > 0 for C in ofmm.ttree.cells])
+    if np.any(op[:, full] != 0):
+        assert rel_max(psi[:, full], op[:, full]) < 1e-12
+    # near field (PP + PC)
+    onear = stg["near"]
+    assert rel_max(near, onear) < 1e-12
+    # the whole result, vs the oracle FMM and vs the direct sum
+    assert rel_max(out, ref) < 1e-12
+    d = odirect(k, T, src, w)
+    assert rel_l2(out, d) < 1e-3
+
+
+def test_fp32_form_close_to_fp64(case):
+    name, T, S, k, p, th, leaf, ofmm, plan = case
+    src = T if S is None else S
+    w = np.random.default_rng(4).standard_normal(src.shape[0])
+    plan32 = cs.Plan(tdev(T), None if S is None else tdev(S), kernel=k, p=p, theta=th,
+                     leaf_size=leaf, fp32=True)
+    a = host(plan.eval(tdev(w)))
+    b = host(plan32.eval(tdev(w)))
+    plan32.close()
+    assert rel_l2(b, a) < 5e-6
+
+
+def test_deterministic(case):
+    name, T, S, k, p, th, leaf, ofmm, plan = case
+    src = T if S is None else S
+    w = tdev(np.random.default_rng(5).standard_normal(src.shape[0]))
+    a = host(plan.eval(w))
+    b = host(plan.eval(w))
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ whole method
+
+@pytest.mark.parametrize("kernel", [1, 2, 3])
+def test_degenerate_all_pp_equals_direct(kernel):
+    _announce("degenerate theta->0 and leaf>=N, kernel %d" % kernel)
+    P, A = cubed_sphere_grid(8)
+    w = real_y41(P) * A
+    ref = host(cs.direct(tdev(P), tdev(P), tdev(w), kernel=kernel))
+    for th, leaf in ((1e-9, 16), (0.7, P.shape[0])):
+        pl = cs.Plan(tdev(P), None, kernel=kernel, p=4, theta=th, leaf_size=leaf)
+        st = pl.stats()
+        assert st["n_pc"] == st["n_cp"] == st["n_cc"] == 0
+        got = host(pl.eval(tdev(w)))
+        pl.close()
+        assert rel_l2(got, ref) < 1e-14
+
+
+def test_config1_gate_and_eigenrelation():
+    _announce("config 1 end to end")
+    P, A = cubed_sphere_grid(32)
+    f = real_y43(P)
+    w = f * A
+    pl = cs.Plan(tdev(P), None, kernel=1, p=8, theta=0.7, leaf_size=64)
+    fs = host(pl.eval(tdev(w)))
+    pl.close()
+    ds = odirect(1, P, P, w)
+    assert rel_l2(fs, ds) < 1e-6
+    e = math.sqrt(np.sum((fs - f / 20) ** 2 * A) / np.sum((f / 20) ** 2 * A))
+    assert e < 4e-2
+
+
+def test_single_point_and_empty_faces():
+    _announce("single point, one populated face")
+    X = np.array([[0.0, 0.0, 1.0]])
+    pl = cs.Plan(tdev(X), None, kernel=1, p=3, theta=0.5, leaf_size=4)
+    assert host(pl.eval(tdev(np.array([2.0]))))[0] == 0.0
+    pl.close()
+    Y = random_sphere_points(500, 2)
+    Y = Y[Y[:, 2] > 0.9]  # all on the +z face
+    w = np.random.default_rng(2).standard_normal(Y.shape[0])
+    pl = cs.Plan(tdev(Y), None, kernel=3, p=5, theta=0.5, leaf_size=4)
+    got = host(pl.eval(tdev(w)))
+    pl.close()
+    assert rel_l2(got, odirect(3, Y, Y, w)) < 1e-4
+
+
+def test_plan_rejects_points_off_the_sphere():
+    _announce("off-sphere rejection")
+    X = random_sphere_points(100, 3)
+    X[5] *= 1.001
+    with pytest.raises(cs.CsfmmError) as ei:
+        cs.Plan(tdev(X), None, kernel=1, p=4, theta=0.5, leaf_size=8)
+    assert ei.value.status == -2
