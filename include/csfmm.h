@@ -177,7 +177,9 @@ int csfmm_plan_proxies(csfmm_plan_t plan, int which, double* proxies);
 int csfmm_plan_permutation(csfmm_plan_t plan, int which, int64_t* perm);
 
 /* Interaction list `kind` (0 PP, 1 PC, 2 CP, 3 CC) as (target cell, source
- * cell) pairs sorted by target then source; cap = room in tgt/src. */
+ * cell) pairs grouped by target cell; within a target the PP entries whose
+ * cells overlap it (the only ones that can hold coincident points) come
+ * first, then entries by source index; cap = room in tgt/src. */
 int csfmm_plan_list(csfmm_plan_t plan, int kind, int32_t* tgt, int32_t* src, int64_t cap);
 
 /* Eval that also copies the stage results to DEVICE buffers (NULL skips):

@@ -102,6 +102,7 @@ struct Lists {
     int64_t cnt[4] = {0, 0, 0, 0};
     int32_t* off[4] = {nullptr, nullptr, nullptr, nullptr};  // [ncells_t + 1]
     int32_t* src[4] = {nullptr, nullptr, nullptr, nullptr};  // [cnt]
+    int32_t* novl = nullptr;  // [ncells_t] leading PP entries whose cells overlap the target
     int32_t* far_targets = nullptr;  // target cells with CP or CC entries
     int32_t n_far_targets = 0;
     int64_t evals[4] = {0, 0, 0, 0};

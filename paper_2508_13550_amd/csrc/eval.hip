@@ -114,45 +114,75 @@ __global__ __launch_bounds__(256) void k_mfma_pass(const int32_t* __restrict__ r
                                                    const double* __restrict__ Abase,
                                                    double* __restrict__ Cbase, int64_t comp_stride,
                                                    const double* __restrict__ B, int nb, int KS) {
+    // MODE 0: one block per (16-row tile, 16-column tile); wave q takes the
+    //   K-slice of child q (split-K) and the four partial tiles are summed in LDS.
+    // MODE 1: one wave per (16-row tile, 16-column tile).
+    // Operand loads are issued kAhead MFMA steps ahead of their use.
+    constexpr int kAhead = 16;
+    __shared__ double4_t part[MODE == 0 ? 3 : 1][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ntiles = nb / 16;
+    const int gw = MODE == 0 ? int(blockIdx.x) : int(blockIdx.x) * 4 + wave;
+    const int rt = gw / ntiles, tile = gw % ntiles;
     const int nrows = np * ncomp;
-    const int r0 = blockIdx.x * 16;
-    const int Kd = MODE == 0 ? 4 * KS : KS;
+    const int r0 = rt * 16;
+    if (r0 >= nrows) return;  // uniform over the block in MODE 0, over the wave in MODE 1
+    const int Kd = KS;        // K-slice per wave: one child (MODE 0) or the parent (MODE 1)
+    const int koff = MODE == 0 ? wave * KS : 0;
     const int Nw = MODE == 0 ? KS : 4 * KS;
     const int ra = r0 + (lane & 15);
     const double* arow = nullptr;
     if (ra < nrows) {
         const int comp = ra / np, P = rows[ra % np];
         const int cell = MODE == 0 ? child0[P] : P;
-        arow = Abase + comp * comp_stride + int64_t(cell) * KS;
+        arow = Abase + comp * comp_stride + int64_t(cell) * KS + koff;
     }
-    const int ntiles = nb / 16;
     const int kq = lane >> 4;
-    for (int tile = wave; tile < ntiles; tile += 4) {
-        double4_t acc = {0.0, 0.0, 0.0, 0.0};
-        const double* bcol = B + tile * 16 + (lane & 15);
-        for (int kk = 0; kk < Kd; kk += 4) {
-            const double a = arow ? arow[kk + kq] : 0.0;
-            const double b = bcol[int64_t(kk + kq) * nb];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-        }
-        const int col = tile * 16 + (lane & 15);
-        if (col < Nw) {
+    const double* bcol = B + int64_t(koff) * nb + tile * 16 + (lane & 15);
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kk = 0; kk < Kd; kk += 4 * kAhead) {
+        double av[kAhead], bv[kAhead];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = r0 + kq + 4 * i;
-                if (r < nrows) {
-                    const int comp = r / np, P = rows[r % np];
-                    const int cell = MODE == 0 ? P : child0[P];
-                    double* crow = Cbase + comp * comp_stride + int64_t(cell) * KS;
-                    if (MODE == 0)
-                        crow[col] = acc[i];
-                    else
-                        crow[col] += acc[i];
-                }
+        for (int u = 0; u < kAhead; ++u) {
+            const int k = kk + 4 * u + kq;
+            const bool in = k < Kd;
+            av[u] = (arow && in) ? arow[k] : 0.0;
+            bv[u] = in ? bcol[int64_t(k) * nb] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+            if (kk + 4 * u < Kd)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+    }
+    if constexpr (MODE == 0) {
+        if (wave > 0) part[wave - 1][lane] = acc;
+        __syncthreads();
+        if (wave > 0) return;
+        acc += part[0][lane];
+        acc += part[1][lane];
+        acc += part[2][lane];
+    }
+    const int col = tile * 16 + (lane & 15);
+    if (col < Nw) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = r0 + kq + 4 * i;
+            if (r < nrows) {
+                const int comp = r / np, P = rows[r % np];
+                const int cell = MODE == 0 ? P : child0[P];
+                double* crow = Cbase + comp * comp_stride + int64_t(cell) * KS;
+                if (MODE == 0)
+                    crow[col] = acc[i];
+                else
+                    crow[col] += acc[i];
             }
         }
     }
+}
+
+inline unsigned mfma_blocks(int mode, int64_t nrows, int nb) {
+    const int64_t tiles = ((nrows + 15) / 16) * (nb / 16);
+    return unsigned(mode == 0 ? tiles : (tiles + 3) / 4);
 }
 
 // L2P (eq. downward_1 at the leaves) + near field + scatter to caller order.
@@ -294,7 +324,7 @@ int run_eval(csfmm_plan_s* P, int kernel, const double* weights, double* out, do
     for (int l = S.depth - 1; l >= 0; --l) {
         const int pb = S.parents_begin[l], np = S.parents_begin[l + 1] - pb;
         if (np <= 0) continue;
-        k_mfma_pass<0><<<unsigned((np + 15) / 16), 256, 0, s>>>(
+        k_mfma_pass<0><<<mfma_blocks(0, np, P->nb1), 256, 0, s>>>(
             S.parents + pb, np, 1, S.child0, P->wbar, P->wbar, 0, P->bm2m, P->nb1, P->KS);
         CSFMM_LAUNCH_CHECK();
     }
@@ -317,7 +347,7 @@ int run_eval(csfmm_plan_s* P, int kernel, const double* weights, double* out, do
     for (int l = 0; l < T.depth; ++l) {
         const int pb = T.parents_begin[l], np = T.parents_begin[l + 1] - pb;
         if (np <= 0) continue;
-        k_mfma_pass<1><<<unsigned((int64_t(np) * vd + 15) / 16), 256, 0, s>>>(
+        k_mfma_pass<1><<<mfma_blocks(1, int64_t(np) * vd, P->nb2), 256, 0, s>>>(
             T.parents + pb, np, vd, T.child0, P->psi, P->psi, psi_stride, P->bl2l, P->nb2, P->KS);
         CSFMM_LAUNCH_CHECK();
     }

@@ -445,20 +445,45 @@ __global__ void k_root_pairs(int32_t* ft, int32_t* fs) {
     }
 }
 
+struct CellIds {
+    const int32_t *level, *face, *ci, *cj;
+};
+
+// Two cells overlap when one contains the other (same face, same ancestor at
+// the coarser level); only then can they hold coincident points.
+__device__ __forceinline__ bool cells_overlap(const CellIds& A, int a, const CellIds& B, int b) {
+    if (A.face[a] != B.face[b]) return false;
+    const int la = A.level[a], lb = B.level[b];
+    const int l = la < lb ? la : lb;
+    return (A.ci[a] >> (la - l)) == (B.ci[b] >> (lb - l)) &&
+           (A.cj[a] >> (la - l)) == (B.cj[b] >> (lb - l));
+}
+
+// Sort key of a (target, source) entry: by target, then overlapping entries
+// first (for PP only), then by source:  t*2ns + (overlap ? 0 : ns) + s.
 __global__ void k_pair_keys(const int32_t* __restrict__ t, const int32_t* __restrict__ s, int64_t n,
-                            int64_t ns_cells, uint64_t* __restrict__ keys,
-                            int32_t* __restrict__ vals) {
+                            int64_t ns_cells, bool mark_overlap, CellIds TC, CellIds SC,
+                            uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    keys[k] = uint64_t(t[k]) * uint64_t(ns_cells) + uint64_t(s[k]);
+    const bool ovl = mark_overlap && cells_overlap(TC, t[k], SC, s[k]);
+    keys[k] = uint64_t(t[k]) * uint64_t(2 * ns_cells) + (ovl ? 0ull : uint64_t(ns_cells)) +
+              uint64_t(s[k]);
     vals[k] = int32_t(k);
 }
 
 __global__ void k_csr_from_keys(const uint64_t* __restrict__ keys, int64_t n, int64_t ns_cells,
-                                int nt_cells, int32_t* __restrict__ off, int32_t* __restrict__ src) {
+                                int nt_cells, int32_t* __restrict__ off, int32_t* __restrict__ src,
+                                int32_t* __restrict__ novl) {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k < n) src[k] = int32_t(keys[k] % uint64_t(ns_cells));
-    if (k <= nt_cells) off[k] = int32_t(lower_bound_u64(keys, 0, n, uint64_t(k) * uint64_t(ns_cells)));
+    const uint64_t ns2 = uint64_t(2 * ns_cells);
+    if (k < n) src[k] = int32_t((keys[k] % ns2) % uint64_t(ns_cells));
+    if (k <= nt_cells) {
+        const int64_t b = lower_bound_u64(keys, 0, n, uint64_t(k) * ns2);
+        off[k] = int32_t(b);
+        if (novl && k < nt_cells)
+            novl[k] = int32_t(lower_bound_u64(keys, b, n, uint64_t(k) * ns2 + uint64_t(ns_cells)) - b);
+    }
 }
 
 __global__ void k_far_flags(const int32_t* __restrict__ ocp, const int32_t* __restrict__ occ, int n,
@@ -710,7 +735,10 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
 
     // concatenate, sort by (target, source), CSR by target cell
     const int64_t nsc = Sx.ncells;
-    const int64_t maxkey = int64_t(T.ncells) * nsc;
+    const int64_t maxkey = int64_t(T.ncells) * 2 * nsc;
+    const CellIds tcid{T.level, T.face, T.ci, T.cj};
+    const CellIds scid{Sx.level, Sx.face, Sx.ci, Sx.cj};
+    RC(A.alloc(&P->lists.novl, T.ncells));
     int bits = 1;
     while (bits < 63 && (int64_t(1) << bits) < maxkey) ++bits;
     for (int k = 0; k < 4; ++k) {
@@ -731,7 +759,8 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
         RC(S.get(&keys, cnt));
         RC(S.get(&vals, cnt));
         if (cnt > 0) {
-            k_pair_keys<<<nblk(cnt), kT, 0, s>>>(lt, ls, cnt, nsc, keys, vals);
+            k_pair_keys<<<nblk(cnt), kT, 0, s>>>(lt, ls, cnt, nsc, k == kPP, tcid, scid, keys,
+                                                 vals);
             CSFMM_LAUNCH_CHECK();
             RC(radix_sort_u64(keys, vals, cnt, bits, s));
         }
@@ -739,7 +768,8 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
         RC(A.alloc(&P->lists.src[k], cnt));
         const int64_t m = std::max<int64_t>(cnt, int64_t(T.ncells) + 1);
         k_csr_from_keys<<<nblk(m), kT, 0, s>>>(keys, cnt, nsc, T.ncells, P->lists.off[k],
-                                               P->lists.src[k]);
+                                               P->lists.src[k],
+                                               k == kPP ? P->lists.novl : nullptr);
         CSFMM_LAUNCH_CHECK();
     }
     // target cells with far-field (CP or CC) work

@@ -40,11 +40,6 @@ constexpr double kLn2 = 0.69314718055994530942;
 template <bool F32>
 using Real = typename std::conditional<F32, float, double>::type;
 
-template <bool F32>
-struct alignas(F32 ? 16 : 32) Src {
-    Real<F32> x, y, z, w;
-};
-
 template <int KERN>
 constexpr int vdim() {
     return KERN == CSFMM_K_BIOT_SAVART ? 3 : 1;
@@ -59,39 +54,70 @@ __device__ __forceinline__ float dev_log2(float x) { return __builtin_amdgcn_log
 __device__ __forceinline__ float dev_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float dev_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// One kernel evaluation, accumulated into p[].
-template <int KERN, bool F32>
-__device__ __forceinline__ void interact(Real<F32> tx, Real<F32> ty, Real<F32> tz,
-                                         const Src<F32>& s, Real<F32>* p) {
+// Evaluation forms of one (target, source) pair:
+//  FORM_CHECK  direct differences, a zero squared distance (coincident point)
+//              contributes nothing; for entries whose cells overlap the target
+//  FORM_NEAR   direct differences, no check (cells do not overlap)
+//  FORM_FAR    MAC-separated entries; in the FP32 form Poisson and 1/|x-y| use
+//              |t-s|^2 = |t|^2 + |s|^2 - 2 t.s (no cancellation at separation)
+enum { FORM_CHECK = 0, FORM_NEAR = 1, FORM_FAR = 2 };
+
+struct TargetRegs {
+    double tx, ty, tz;          // FP64 form
+    float fx, fy, fz, f2;       // FP32 form: recentred target and |t|^2
+    float mx, my, mz;           // -2 t
+};
+
+template <int KERN, bool F32, int FORM>
+__device__ __forceinline__ void eval_pair(const TargetRegs& T, Real<F32> sx, Real<F32> sy,
+                                          Real<F32> sz, Real<F32> s2, Real<F32> w,
+                                          Real<F32>* p) {
     using R = Real<F32>;
-    const R dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
-    const R r2 = dx * dx + dy * dy + dz * dz;
-    if constexpr (KERN == CSFMM_K_POISSON_LOG) {
-        R lg;
-        if constexpr (F32)
-            lg = dev_log2(r2);
-        else
-            lg = log(r2);
-        lg = r2 > R(0) ? lg : R(0);
-        p[0] = fma(s.w, lg, p[0]);
-    } else if constexpr (KERN == CSFMM_K_BIOT_SAVART) {
-        R inv;
-        if constexpr (F32)
-            inv = dev_rcp(r2);
-        else
-            inv = R(1) / r2;
-        const R f = r2 > R(0) ? s.w * inv : R(0);
-        p[0] = fma(dx, f, p[0]);
-        p[1] = fma(dy, f, p[1]);
-        p[2] = fma(dz, f, p[2]);
+    R tx, ty, tz;
+    if constexpr (F32) {
+        tx = T.fx; ty = T.fy; tz = T.fz;
     } else {
-        R inv;
-        if constexpr (F32)
-            inv = dev_rsq(r2);
+        tx = T.tx; ty = T.ty; tz = T.tz;
+    }
+    constexpr bool expanded = F32 && FORM == FORM_FAR && KERN != CSFMM_K_BIOT_SAVART;
+    if constexpr (expanded) {
+        const float d = fmaf(T.mx, sx, fmaf(T.my, sy, fmaf(T.mz, sz, s2 + T.f2)));
+        if constexpr (KERN == CSFMM_K_POISSON_LOG)
+            p[0] = fmaf(w, dev_log2(d), p[0]);
         else
-            inv = rsqrt(r2);
-        const R f = r2 > R(0) ? inv : R(0);
-        p[0] = fma(s.w, f, p[0]);
+            p[0] = fmaf(w, dev_rsq(d), p[0]);
+    } else {
+        (void)s2;
+        const R dx = sx - tx, dy = sy - ty, dz = sz - tz;
+        const R r2 = dx * dx + dy * dy + dz * dz;
+        if constexpr (KERN == CSFMM_K_POISSON_LOG) {
+            R lg;
+            if constexpr (F32)
+                lg = dev_log2(r2);
+            else
+                lg = log(r2);
+            if constexpr (FORM == FORM_CHECK) lg = r2 > R(0) ? lg : R(0);
+            p[0] = fma(w, lg, p[0]);
+        } else if constexpr (KERN == CSFMM_K_BIOT_SAVART) {
+            R inv;
+            if constexpr (F32)
+                inv = dev_rcp(r2);
+            else
+                inv = R(1) / r2;
+            R f = w * inv;
+            if constexpr (FORM == FORM_CHECK) f = r2 > R(0) ? f : R(0);
+            p[0] = fma(dx, f, p[0]);
+            p[1] = fma(dy, f, p[1]);
+            p[2] = fma(dz, f, p[2]);
+        } else {
+            R inv;
+            if constexpr (F32)
+                inv = dev_rsq(r2);
+            else
+                inv = rsqrt(r2);
+            if constexpr (FORM == FORM_CHECK) inv = r2 > R(0) ? inv : R(0);
+            p[0] = fma(w, inv, p[0]);
+        }
     }
 }
 
@@ -119,6 +145,7 @@ struct TileArgs {
     const double* tprox;         // target proxies [cell][3][KS] (far kernel)
     const int32_t *off_a, *src_a;  // list with particle sources (PP or CP)
     const int32_t *off_b, *src_b;  // list with proxy sources (PC or CC)
+    const int32_t* novl;           // leading overlapping entries of list a (PP), or NULL
     const int32_t *sbegin, *scount;
     const double *sx, *sy, *sz, *sw;
     const double *sprox, *swbar;
@@ -127,12 +154,51 @@ struct TileArgs {
     int64_t comp_stride;
 };
 
+constexpr int kMaxG = 32;   // source groups per target
+constexpr int kUnroll = 4;
+constexpr int kLds = kChunk + kUnroll * kMaxG;
+
+// Staged sources: FP32 form (x, y, z, |s|^2) and weights; FP64 form (x, y, z, w).
+template <bool F32>
+struct Stage;
+template <>
+struct Stage<true> {
+    float4 p[kLds];
+    float w[kLds];
+};
+template <>
+struct Stage<false> {
+    double4 p[kLds];
+};
+
+template <int KERN, bool F32, int FORM>
+__device__ __forceinline__ void run_group(const Stage<F32>& L, int base, int nj,
+                                          const TargetRegs& T, Real<F32>* p) {
+    for (int j = 0; j < nj; j += kUnroll) {
+        if constexpr (F32) {
+            const float4 w4 = *reinterpret_cast<const float4*>(&L.w[base + j]);
+            const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const float4 s = L.p[base + j + u];
+                eval_pair<KERN, true, FORM>(T, s.x, s.y, s.z, s.w, ws[u], p);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const double4 s = L.p[base + j + u];
+                eval_pair<KERN, false, FORM>(T, s.x, s.y, s.z, 0.0, s.w, p);
+            }
+        }
+    }
+}
+
 template <int KERN, bool F32, bool TPROX>
 __global__ __launch_bounds__(kThreads) void k_tile(TileArgs a) {
     using R = Real<F32>;
     constexpr int VD = vdim<KERN>();
     constexpr double scale = coord_scale<KERN>();
-    __shared__ Src<F32> src[kChunk];
+    __shared__ Stage<F32> L[2];
     __shared__ int e_code[kMaxEntries];
     __shared__ int e_pref[kMaxEntries + 1];
     __shared__ int lw[4];
@@ -146,11 +212,15 @@ __global__ __launch_bounds__(kThreads) void k_tile(TileArgs a) {
     const int tb = TPROX ? 0 : a.tbegin[T];
     const int ea0 = a.off_a[T], nea = a.off_a[T + 1] - ea0;
     const int eb0 = a.off_b[T], neb = a.off_b[T + 1] - eb0;
+    const int nov = a.novl ? a.novl[T] : 0;
+    // entry ranges of the three forms: [0,nov) check, [nov,nea) near, [nea,nea+neb) far;
+    // sources of the far kernel are all MAC separated
+    const int ph_hi[3] = {TPROX ? 0 : nov, TPROX ? 0 : nea, nea + neb};
     const int ne_all = nea + neb;
 
     for (int t0 = 0; t0 < nT; t0 += kThreads) {
         const int TC = min(nT - t0, kThreads);
-        const int G = kThreads / TC;
+        const int G = min(kThreads / TC, kMaxG);
         const int t = tid % TC, g = tid / TC;
         const bool active = g < G;
         double gx = cx, gy = cy, gz = cz;
@@ -166,11 +236,26 @@ __global__ __launch_bounds__(kThreads) void k_tile(TileArgs a) {
                 gz = a.tz[tb + t0 + t];
             }
         }
-        const R qx = R((gx - cx) * scale), qy = R((gy - cy) * scale), qz = R((gz - cz) * scale);
+        TargetRegs TR;
+        TR.tx = (gx - cx) * scale;
+        TR.ty = (gy - cy) * scale;
+        TR.tz = (gz - cz) * scale;
+        TR.fx = float(TR.tx);
+        TR.fy = float(TR.ty);
+        TR.fz = float(TR.tz);
+        TR.f2 = float(double(TR.fx) * TR.fx + double(TR.fy) * TR.fy + double(TR.fz) * TR.fz);
+        TR.mx = -2.f * TR.fx;
+        TR.my = -2.f * TR.fy;
+        TR.mz = -2.f * TR.fz;
         double acc[VD];
 #pragma unroll
         for (int v = 0; v < VD; ++v) acc[v] = 0.0;
 
+        // Entries are processed in batches of up to kMaxEntries; inside a batch
+        // the flattened sources split into the three forms (check, near, far)
+        // and each form into chunks of kChunk.  Chunks are double buffered in
+        // LDS: the global loads of chunk c+1 are in flight while chunk c is
+        // evaluated, with one barrier per chunk.
         for (int ebase = 0; ebase < ne_all; ebase += kMaxEntries) {
             const int ne = min(kMaxEntries, ne_all - ebase);
             int sz = 0;
@@ -190,54 +275,107 @@ __global__ __launch_bounds__(kThreads) void k_tile(TileArgs a) {
             e_pref[tid] = incl - sz;
             if (tid == kThreads - 1) e_pref[kMaxEntries] = incl;
             __syncthreads();
-            const int total = e_pref[kMaxEntries];
-            for (int q0 = 0; q0 < total; q0 += kChunk) {
-                const int nq = min(kChunk, total - q0);
-                for (int q = tid; q < nq; q += kThreads) {
-                    const int gq = q0 + q;
-                    int lo = 0, hi = ne - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (e_pref[mid] <= gq)
-                            lo = mid;
-                        else
-                            hi = mid - 1;
+            // source offsets where the forms change inside this batch
+            int bnd[4];
+            bnd[0] = 0;
+            bnd[3] = e_pref[kMaxEntries];
+            {
+                const int k1 = min(max(ph_hi[0] - ebase, 0), kMaxEntries);
+                const int k2 = min(max(ph_hi[1] - ebase, 0), kMaxEntries);
+                bnd[1] = e_pref[k1];
+                bnd[2] = e_pref[k2];
+            }
+            // chunk cursor: (form, start offset)
+            int ph = 0, q0 = 0;
+            while (ph < 3 && bnd[ph] >= bnd[ph + 1]) ++ph;
+            if (ph < 3) q0 = bnd[ph];
+            // prefetch registers: at most two real sources per thread per chunk
+            double ry[2][4];
+            auto fetch = [&](int cph, int cq0) {
+                const int nq = min(kChunk, bnd[cph + 1] - cq0);
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int q = tid + r * kThreads;
+                    if (q < nq) {
+                        const int gq = cq0 + q;
+                        int lo = 0, hi = ne - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (e_pref[mid] <= gq)
+                                lo = mid;
+                            else
+                                hi = mid - 1;
+                        }
+                        const int o = gq - e_pref[lo];
+                        const int code = e_code[lo];
+                        if (code >= 0) {
+                            const int j = code + o;
+                            ry[r][0] = a.sx[j];
+                            ry[r][1] = a.sy[j];
+                            ry[r][2] = a.sz[j];
+                            ry[r][3] = a.sw[j];
+                        } else {
+                            const int64_t sc = -(code + 1);
+                            const double* ps = a.sprox + sc * 3 * KS;
+                            ry[r][0] = ps[o];
+                            ry[r][1] = ps[KS + o];
+                            ry[r][2] = ps[2 * KS + o];
+                            ry[r][3] = a.swbar[sc * KS + o];
+                        }
                     }
-                    const int o = gq - e_pref[lo];
-                    const int code = e_code[lo];
-                    double yx, yy, yz, w;
-                    if (code >= 0) {
-                        const int j = code + o;
-                        yx = a.sx[j];
-                        yy = a.sy[j];
-                        yz = a.sz[j];
-                        w = a.sw[j];
+                }
+            };
+            if (ph < 3) fetch(ph, q0);
+            int buf = 0;
+            while (ph < 3) {
+                const int nq = min(kChunk, bnd[ph + 1] - q0);
+                const int Tj = (((nq + G - 1) / G) + kUnroll - 1) / kUnroll * kUnroll;
+                const int npad = G * Tj;
+                Stage<F32>& Lb = L[buf];
+                for (int q = tid; q < npad; q += kThreads) {
+                    double yx = 2.0, yy = 2.0, yz = 2.0, w = 0.0;  // padding: far, weightless
+                    if (q < nq) {
+                        const int r = q >= kThreads ? 1 : 0;
+                        yx = (ry[r][0] - cx) * scale;
+                        yy = (ry[r][1] - cy) * scale;
+                        yz = (ry[r][2] - cz) * scale;
+                        w = ry[r][3];
+                    }
+                    if constexpr (F32) {
+                        const float fx = float(yx), fy = float(yy), fz = float(yz);
+                        const float f2 = float(double(fx) * fx + double(fy) * fy + double(fz) * fz);
+                        Lb.p[q] = make_float4(fx, fy, fz, f2);
+                        Lb.w[q] = float(w);
                     } else {
-                        const int64_t s = -(code + 1);
-                        const double* ps = a.sprox + s * 3 * KS;
-                        yx = ps[o];
-                        yy = ps[KS + o];
-                        yz = ps[2 * KS + o];
-                        w = a.swbar[s * KS + o];
+                        Lb.p[q] = make_double4(yx, yy, yz, w);
                     }
-                    Src<F32> e;
-                    e.x = R((yx - cx) * scale);
-                    e.y = R((yy - cy) * scale);
-                    e.z = R((yz - cz) * scale);
-                    e.w = R(w);
-                    src[q] = e;
                 }
                 __syncthreads();
+                // advance the cursor and start the next chunk's loads
+                const int cph = ph;
+                q0 += nq;
+                if (q0 >= bnd[ph + 1]) {
+                    ++ph;
+                    while (ph < 3 && bnd[ph] >= bnd[ph + 1]) ++ph;
+                    if (ph < 3) q0 = bnd[ph];
+                }
+                if (ph < 3) fetch(ph, q0);
                 if (active) {
                     R p[VD];
 #pragma unroll
                     for (int v = 0; v < VD; ++v) p[v] = R(0);
-                    for (int j = g; j < nq; j += G) interact<KERN, F32>(qx, qy, qz, src[j], p);
+                    if (cph == 0)
+                        run_group<KERN, F32, FORM_CHECK>(Lb, g * Tj, Tj, TR, p);
+                    else if (cph == 1)
+                        run_group<KERN, F32, FORM_NEAR>(Lb, g * Tj, Tj, TR, p);
+                    else
+                        run_group<KERN, F32, FORM_FAR>(Lb, g * Tj, Tj, TR, p);
 #pragma unroll
                     for (int v = 0; v < VD; ++v) acc[v] += double(p[v]);
                 }
-                __syncthreads();
+                buf ^= 1;
             }
+            __syncthreads();
         }
 #pragma unroll
         for (int v = 0; v < VD; ++v) red[v][tid] = active ? acc[v] : 0.0;
@@ -490,6 +628,7 @@ int launch_near(csfmm_plan_s* P, int kernel, hipStream_t s) {
     a.src_a = P->lists.src[kPP];
     a.off_b = P->lists.off[kPC];
     a.src_b = P->lists.src[kPC];
+    a.novl = P->lists.novl;
     a.out = P->phinear;
     a.comp_stride = P->nt;
     return launch_tile<false>(kernel, (P->flags & CSFMM_FP32_FORM) != 0, a, P->tt.nleaves, s);
@@ -502,6 +641,7 @@ int launch_far(csfmm_plan_s* P, int kernel, hipStream_t s) {
     a.src_a = P->lists.src[kCP];
     a.off_b = P->lists.off[kCC];
     a.src_b = P->lists.src[kCC];
+    a.novl = nullptr;
     a.out = P->psi;
     a.comp_stride = int64_t(P->tt.ncells) * P->KS;
     return launch_tile<true>(kernel, (P->flags & CSFMM_FP32_FORM) != 0, a,

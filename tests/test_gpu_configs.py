@@ -1,0 +1,130 @@
+"""Full-size workloads on the GPU, checked on seeded samples of targets.
+
+The oracle computes the direct sum at 4,096 seeded targets against every
+source (and, for the Poisson workload, the oracle FMM at 256 targets); the
+library runs at full size in the launch configuration the benchmark times.
+
+Gates (relative L2 over the sampled targets, Euclidean norm for vectors):
+  Poisson N=393,216, theta 0.7: FP64 2e-5 (p=6), 1e-6 (p=8), 1e-7 (p=10);
+      FP32 form max(FP64 gate, 2e-6)
+  Biot-Savart N=1,572,864, theta 0.6, p=8, FP32 form: 1e-5
+  1/|x-y| 6,291,456 sources x 1,000,000 random targets, theta 0.6, p=10, FP32 form: 1e-5
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2508_13550_amd as cs
+from workloads import make_config, config_subset
+from oracle import direct as odirect
+from oracle import fmm as F
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
+
+
+def tdev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def rel_l2(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+def say(msg):
+    print("\n[gpu case] " + msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    say("config 2 inputs")
+    c = make_config(2)
+    P, w = c["sources"], c["weights"]
+    S = config_subset(P.shape[0], 4096, c["subset_seed"])
+    ref = odirect(1, P[S], P, w)
+    return c, S, ref
+
+
+@pytest.mark.parametrize("p,gate", [(6, 2e-5), (8, 1e-6), (10, 1e-7)])
+def test_config2_poisson_both_forms(cfg2, p, gate):
+    c, S, ref = cfg2
+    P, w = c["sources"], c["weights"]
+    T, W = tdev(P), tdev(w)
+    for fp32, g in ((False, gate), (True, max(gate, 2e-6))):
+        say("config 2 p=%d fp32=%s" % (p, fp32))
+        pl = cs.Plan(T, None, kernel=1, p=p, theta=c["theta"], leaf_size=c["leaf"], fp32=fp32)
+        out = pl.eval(W).cpu().numpy()
+        pl.close()
+        err = rel_l2(out[S], ref)
+        print("p=%d fp32=%s rel L2 %.3e (gate %.0e)" % (p, fp32, err, g), flush=True)
+        assert err <= g
+
+
+def test_config2_matches_oracle_fmm_on_sample(cfg2):
+    c, S, ref = cfg2
+    P, w = c["sources"], c["weights"]
+    say("config 2 oracle FMM on 256 sampled targets")
+    samp = config_subset(P.shape[0], 256, 2004)
+    ofmm = F.FMM(P, None, 1, 8, c["theta"], c["leaf"])
+    want = ofmm.evaluate(w, sample=samp)
+    pl = cs.Plan(tdev(P), None, kernel=1, p=8, theta=c["theta"], leaf_size=c["leaf"])
+    got = pl.eval(tdev(w)).cpu().numpy()[samp]
+    st = pl.stats()
+    pl.close()
+    assert st["n_pp"] == len(ofmm.lists["PP"]) and st["n_cc"] == len(ofmm.lists["CC"])
+    assert st["n_pc"] == len(ofmm.lists["PC"]) and st["n_cp"] == len(ofmm.lists["CP"])
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def _bs_exact(P):
+    c = -(3.0 / 8.0) * math.sqrt(5.0 / math.pi)
+    x, y, z = P[:, 0], P[:, 1], P[:, 2]
+    g = np.stack([c * (4 * z ** 3 - 9 * x * x * z - 3 * y * y * z), c * (-6 * x * y * z),
+                  c * (12 * x * z * z - 3 * x ** 3 - 3 * x * y * y)], axis=1) / 20.0
+    return np.cross(g, P)
+
+
+def test_config3_biot_savart_fp32():
+    say("config 3 inputs")
+    c = make_config(3)
+    P, w, A = c["sources"], c["weights"], c["areas"]
+    S = config_subset(P.shape[0], 4096, c["subset_seed"])
+    ref = odirect(2, P[S], P, w)
+    T = tdev(P)
+    say("config 3 plan + eval (FP32 form, p=8, theta=0.6)")
+    pl = cs.Plan(T, None, kernel=2, p=c["p"], theta=c["theta"], leaf_size=c["leaf"], fp32=True)
+    out = pl.eval(tdev(w)).cpu().numpy()
+    err = rel_l2(out[S], ref)
+    print("config 3 rel L2 %.3e" % err, flush=True)
+    assert out.shape == (P.shape[0], 3)
+    assert err <= 1e-5
+    # noise off: the whole-sphere result against u = grad(zeta/20) x x (paper §2.3 + eq. G_L)
+    from workloads import real_y41
+    w0 = real_y41(P) * A
+    u = pl.eval(tdev(w0)).cpu().numpy()
+    pl.close()
+    ex = _bs_exact(P)
+    e = math.sqrt(np.sum(np.sum((u - ex) ** 2, 1) * A) / np.sum(np.sum(ex ** 2, 1) * A))
+    print("config 3 E(u_FS, u_exact) %.3e" % e, flush=True)
+    assert e < 3e-5   # discretization error at N = 1.57M is ~1.4e-5 (second order)
+
+
+def test_config4_distinct_inverse_distance_fp32():
+    say("config 4 inputs (6.3M sources, degree-64 field, 1M targets)")
+    c = make_config(4)
+    Y, w, X = c["sources"], c["weights"], c["targets"]
+    S = config_subset(X.shape[0], 4096, c["subset_seed"])
+    say("config 4 oracle direct on 4,096 targets x 6.3M sources")
+    ref = odirect(3, X[S], Y, w)
+    say("config 4 plan + eval (FP32 form, p=10, theta=0.6)")
+    pl = cs.Plan(tdev(X), tdev(Y), kernel=3, p=c["p"], theta=c["theta"], leaf_size=c["leaf"],
+                 fp32=True)
+    out = pl.eval(tdev(w)).cpu().numpy()
+    st = pl.stats()
+    pl.close()
+    err = rel_l2(out[S], ref)
+    print("config 4 rel L2 %.3e stats %s" % (err, st), flush=True)
+    assert err <= 1e-5

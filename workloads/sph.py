@@ -10,6 +10,9 @@ The normalised functions come from the standard three-term recurrence in n
 at fixed m, which is stable to the degrees used here (n <= 64).
 """
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 
@@ -52,7 +55,7 @@ def real_sph_harm_all(points, nmax):
     return out
 
 
-def bandlimited_field(points, nmax, sigma, seed, nmin=0, chunk=1 << 18):
+def bandlimited_field(points, nmax, sigma, seed, nmin=0, chunk=1 << 16):
     """f = sum_{n=nmin..nmax} sum_m a_nm Y_{n,m}, a_nm ~ N(0, sigma(n)^2).
 
     The coefficients are drawn in (n, m = -n..n) order from PCG64(seed) for
@@ -67,7 +70,8 @@ def bandlimited_field(points, nmax, sigma, seed, nmin=0, chunk=1 << 18):
         a[sl] *= sigma(n) if n >= nmin else 0.0
     P = np.asarray(points, dtype=np.float64)
     f = np.zeros(P.shape[0])
-    for lo in range(0, P.shape[0], chunk):
+
+    def one_chunk(lo):
         Q = P[lo:lo + chunk]
         x, y, z = Q[:, 0], Q[:, 1], Q[:, 2]
         s = np.sqrt(np.maximum(0.0, x * x + y * y))
@@ -84,6 +88,16 @@ def bandlimited_field(points, nmax, sigma, seed, nmin=0, chunk=1 << 18):
                     n = m + k
                     acc += pnm * (a[_index(n, m)] * c + a[_index(n, -m)] * sn)
         f[lo:lo + chunk] = acc
+
+    # chunks are independent; NumPy releases the GIL inside its loops
+    starts = list(range(0, P.shape[0], chunk))
+    workers = max(1, min(16, os.cpu_count() or 1, len(starts)))
+    if workers == 1:
+        for lo in starts:
+            one_chunk(lo)
+    else:
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(one_chunk, starts))
     return f
 
 
