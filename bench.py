@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="serving stream instead (2,000 requests)")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--rho", type=float, nargs="*", default=[0.5, 0.8])
     return ap.parse_args()
 
 
@@ -138,6 +141,111 @@ def cpu_baseline(P, w, seconds):
             "host": platform.processor() or platform.machine()}
 
 
+def serve_bench(args):
+    """Serving stream: requests of mixed resolution, kernel and degree arriving
+    as a Poisson process at rho x capacity; continuous batching on one GPU."""
+    import torch
+    import paper_2508_13550_amd as cs
+    from paper_2508_13550_amd.serve import Server, Request, latency_stats, plan_key
+    from workloads import cubed_sphere_grid, real_sph_harm_all, config_subset
+    from workloads.serving import request_mix, poisson_arrivals, E_CHOICES
+
+    theta, leaf = 0.6, 128
+    n = args.requests
+    mix = request_mix(n)
+    dev = torch.device("cuda:0")
+    grids = {}
+    for E in E_CHOICES:
+        P, A = cubed_sphere_grid(E)
+        Y = real_sph_harm_all(P, 8)
+        grids[E] = (torch.tensor(P, device=dev), torch.tensor(Y, device=dev),
+                    torch.tensor(A, device=dev))
+    W = [(grids[E][1] @ torch.tensor(c, device=dev)) * grids[E][2] for E, k, p, c in mix]
+    nn = [6 * E * E for E, k, p, c in mix]
+    # solo service time per class with resident plans (capacity = 1 / mean service time)
+    plans = {}
+    solo = {}
+    for E, k, p, c in mix:
+        if (E, k, p) in solo:
+            continue
+        if (E, p) not in plans:
+            plans[(E, p)] = cs.Plan(grids[E][0], None, kernel=k, p=p, theta=theta,
+                                    leaf_size=leaf, fp32=True)
+        pl = plans[(E, p)]
+        w = W[[i for i, m in enumerate(mix) if m[:3] == (E, k, p)][0]]
+        pl.eval(w, kernel=k)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(5):
+            pl.eval(w, kernel=k)
+        b.record()
+        torch.cuda.synchronize()
+        solo[(E, k, p)] = a.elapsed_time(b) / 5 / 1e3
+    for pl in plans.values():
+        pl.close()
+    mean_service = float(np.mean([solo[m[:3]] for m in mix]))
+    capacity = 1.0 / mean_service
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.9 * free)
+    results = []
+    samples = config_subset(n, 50, 5007)
+    for rho in args.rho:
+        srv = Server(budget_bytes=budget, theta=theta, leaf=leaf, fp32=True, max_batch=32)
+        # warm the plan cache: one request per (E, p)
+        warm, seen = [], set()
+        for i, (E, k, p, c) in enumerate(mix):
+            if (E, p) not in seen:
+                seen.add((E, p))
+                warm.append(Request(id=-1 - len(warm), geometry=("grid", E), targets=grids[E][0],
+                                    sources=None, kernel=k, p=p, weights=W[i]))
+        srv.run(warm)
+        srv.done.clear()
+        srv.batch_sizes.clear()
+        arr = poisson_arrivals(n, rho * capacity, seed=5005)
+        reqs = [Request(id=i, geometry=("grid", E), targets=grids[E][0], sources=None,
+                        kernel=k, p=p, weights=W[i], t_arrival=float(arr[i]))
+                for i, (E, k, p, c) in enumerate(mix)]
+        t0 = time.perf_counter()
+        done = srv.run(reqs)
+        makespan = time.perf_counter() - t0
+        st = srv.sched.stats()
+        lat = latency_stats(done)
+        # accuracy and alone-vs-mix identity on 50 sampled requests
+        by_id = {r.id: r for r in done}
+        worst, same = 0.0, True
+        for i in samples:
+            r = by_id[int(i)]
+            E = mix[i][0]
+            T = grids[E][0]
+            pl = srv.plans[plan_key(("grid", E), r.p, theta, leaf, True)]
+            alone = pl.eval(r.weights, kernel=r.kernel)
+            same = same and bool(torch.equal(alone, r.out))
+            S = torch.tensor(config_subset(T.shape[0], 1024, 5008), device=dev)
+            ref = cs.direct(T[S].contiguous(), T, r.weights, kernel=r.kernel)
+            got = r.out[S]
+            err = float(torch.sqrt(torch.sum((got - ref) ** 2) / torch.sum(ref ** 2)))
+            worst = max(worst, err)
+        n2 = float(sum(x * x for x in nn))
+        results.append({"rho": rho, "arrival_rate_per_s": rho * capacity,
+                        "latency_ms": lat, "makespan_s": makespan,
+                        "throughput_req_per_s": len(done) / makespan,
+                        "throughput_n2eq_per_s": n2 / makespan,
+                        "mean_batch": float(np.mean(srv.batch_sizes)),
+                        "max_batch": int(max(srv.batch_sizes)),
+                        "sched": st, "sample_max_rel_l2": worst, "alone_equals_mix": same})
+        srv.close()
+    line = {"metric": "serving: p50/p99 latency and throughput of a CSFMM request stream",
+            "n_requests": n, "capacity_req_per_s": capacity, "mean_solo_service_ms":
+            mean_service * 1e3, "budget_bytes": budget, "theta": theta, "leaf": leaf,
+            "form": "fp32", "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": "2,000 requests, E in {16..512} (N 1,536..1,572,864), "
+                                   "kernel in {Poisson, Biot-Savart, 1/|x-y|}, p in {6, 8}, "
+                                   "Poisson arrivals (seed 5005)"},
+            "runs": results}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -146,6 +254,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.serve:
+        serve_bench(args)
         return
     import torch
     import paper_2508_13550_amd as cs

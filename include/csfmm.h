@@ -39,6 +39,7 @@ extern "C" {
 #endif
 
 typedef struct csfmm_plan_s* csfmm_plan_t;
+typedef struct csfmm_workspace_s* csfmm_workspace_t;
 
 enum csfmm_status {
     CSFMM_OK = 0,
@@ -127,7 +128,66 @@ int csfmm_direct(const double* targets, int64_t n_t, const double* sources, int6
                  const double* weights, int kernel_id, unsigned flags, double* out,
                  void* stream);
 
-/* Release a plan's device memory (waits for the device first). NULL is OK. */
+/*
+ * Serving: several requests evaluated together (continuous batching).
+ * A workspace holds one request's eval buffers (sorted weights, proxy
+ * weights, proxy potentials, near field) for a given plan, so one resident
+ * plan can serve several in-flight requests.  csfmm_eval_many runs the eval
+ * phases of n_req requests with one packed launch per phase (per kernel id and
+ * precision form for the near and far field): request r uses plans[r] with
+ * workspaces[r] (created for that plan), kernel_ids[r] (NULL: each plan's
+ * default), weights[r] [n_s] and outs[r] [n_t] or [n_t][3].  Each request's
+ * arithmetic is the same as csfmm_eval's, whatever it is batched with.
+ * A workspace must not be used by two evals in flight at once.
+ */
+int csfmm_workspace_create(csfmm_plan_t plan, void* stream, csfmm_workspace_t* out);
+                                                        /* waits for `stream` */
+int csfmm_workspace_destroy(csfmm_workspace_t ws);     /* waits for the device; NULL is OK */
+int64_t csfmm_workspace_bytes(csfmm_plan_t plan);       /* device bytes of one workspace */
+int csfmm_eval_many(int n_req, const csfmm_plan_t* plans, const csfmm_workspace_t* workspaces,
+                    const int* kernel_ids, const double* const* weights, double* const* outs,
+                    void* stream);
+
+/*
+ * Continuous-batching scheduler (host only; it decides, the caller executes).
+ * Requests are submitted with a plan key (equal keys share one resident plan),
+ * the device bytes of that plan and of one workspace (csfmm_workspace_bytes).
+ * csfmm_sched_step(now) admits waiting requests with t_arrival <= now in
+ * arrival order into one batch of at most max_batch while their memory fits
+ * the budget, and reports what the caller must do before launching it:
+ *   evict_keys  destroy these resident plans and their workspaces (idle, LRU)
+ *   build_keys  build these plans
+ *   new_ws_keys create one more workspace for each listed plan key
+ *   launch_ids  run these requests now (one csfmm_eval_many)
+ *   reject_ids  these requests can never fit the budget
+ * A resident plan keeps a pool of workspaces as large as its peak number of
+ * requests in flight; csfmm_sched_complete returns one to the pool. The oldest
+ * waiting request is never overtaken. Every array is caller owned; cap_* is
+ * its room (new_ws_keys has room for cap_launch).
+ */
+typedef struct csfmm_sched_s* csfmm_sched_t;
+typedef struct csfmm_sched_decision {
+    int64_t* launch_ids;  int cap_launch;  int n_launch;
+    uint64_t* build_keys; int cap_build;   int n_build;
+    uint64_t* new_ws_keys;                 int n_new_ws;
+    uint64_t* evict_keys; int cap_evict;   int n_evict;
+    int64_t* reject_ids;  int cap_reject;  int n_reject;
+} csfmm_sched_decision;
+typedef struct csfmm_sched_stats {
+    int64_t submitted, launched, completed, rejected, batches;
+    int64_t plan_hits, plan_misses, evictions;
+    int64_t used_bytes, budget_bytes, queued, in_flight, resident_plans;
+} csfmm_sched_stats;
+int csfmm_sched_create(int64_t hbm_budget_bytes, int max_batch, csfmm_sched_t* out);
+int csfmm_sched_destroy(csfmm_sched_t s);
+int csfmm_sched_submit(csfmm_sched_t s, int64_t req_id, uint64_t plan_key, int64_t plan_bytes,
+                       int64_t ws_bytes, double t_arrival);
+int csfmm_sched_step(csfmm_sched_t s, double now, csfmm_sched_decision* d);
+int csfmm_sched_complete(csfmm_sched_t s, int64_t req_id, double now);
+int csfmm_sched_get_stats(csfmm_sched_t s, csfmm_sched_stats* out);
+
+/* Release a plan's device memory (waits for the device first). NULL is OK.
+ * Workspaces of the plan must be destroyed first. */
 int csfmm_plan_destroy(csfmm_plan_t plan);
 
 /* Sizes and interaction counts of a plan. */
@@ -182,9 +242,10 @@ int csfmm_plan_permutation(csfmm_plan_t plan, int which, int64_t* perm);
  * first, then entries by source index; cap = room in tgt/src. */
 int csfmm_plan_list(csfmm_plan_t plan, int kind, int32_t* tgt, int32_t* src, int64_t cap);
 
-/* Eval that also copies the stage results to DEVICE buffers (NULL skips):
- *   wbar [n_cells_s][(p+1)^2]      proxy weights after the upward pass
- *   psi  [vdim][n_cells_t][(p+1)^2] proxy potentials after the downward pass
+/* Eval that also copies the stage results to DEVICE buffers (NULL skips);
+ * KS = (p+1)^2 rounded up to a multiple of 4 (the entries past (p+1)^2 are 0):
+ *   wbar [n_cells_s][KS]        proxy weights after the upward pass
+ *   psi  [vdim][n_cells_t][KS]  proxy potentials after the downward pass
  *   near [n_t][vdim] PP+PC part of phi in the caller's order
  * where vdim = 3 for Biot-Savart, else 1. */
 int csfmm_eval_stages(csfmm_plan_t plan, int kernel_id, const double* weights, double* out,

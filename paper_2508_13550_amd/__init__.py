@@ -63,7 +63,8 @@ EXPORTED = (
     "csfmm_plan", "csfmm_eval", "csfmm_eval_kernel", "csfmm_direct", "csfmm_plan_destroy",
     "csfmm_plan_stats", "csfmm_estimate_bytes", "csfmm_last_error", "csfmm_plan_cells",
     "csfmm_plan_proxies", "csfmm_plan_permutation", "csfmm_plan_list", "csfmm_eval_stages",
-    "csfmm_plan_timing", "csfmm_plan_timing_read",
+    "csfmm_plan_timing", "csfmm_plan_timing_read", "csfmm_workspace_create",
+    "csfmm_workspace_destroy", "csfmm_workspace_bytes", "csfmm_eval_many",
 )
 
 STAGES = ("p2m", "m2m", "near", "far", "l2l", "l2p")
@@ -95,10 +96,17 @@ def load_library(path=LIB_PATH):
     L.csfmm_plan_permutation.argtypes = [vp, ctypes.c_int, dp]
     L.csfmm_plan_list.argtypes = [vp, ctypes.c_int, i32p, i32p, i64]
     L.csfmm_plan_timing.argtypes = [vp, ctypes.c_int]
+    L.csfmm_workspace_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
+    L.csfmm_workspace_destroy.argtypes = [vp]
+    L.csfmm_workspace_bytes.argtypes = [vp]
+    L.csfmm_workspace_bytes.restype = ctypes.c_int64
+    L.csfmm_eval_many.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp),
+                                  ctypes.POINTER(vp), vp]
     L.csfmm_plan_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTED:
         f = getattr(L, name)
-        if name not in ("csfmm_estimate_bytes", "csfmm_last_error"):
+        if name not in ("csfmm_estimate_bytes", "csfmm_last_error", "csfmm_workspace_bytes"):
             f.restype = ctypes.c_int
     _lib = L
     return L
@@ -275,6 +283,71 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Workspace:
+    """csfmm_workspace_create: eval buffers of one in-flight request on a plan."""
+
+    def __init__(self, plan):
+        _require_gpu()
+        self.plan = plan
+        h = ctypes.c_void_p()
+        _check(_lib.csfmm_workspace_create(plan.handle, _stream(), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("workspace was destroyed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.csfmm_workspace_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_bytes(plan):
+    """Device bytes of one workspace for this plan."""
+    return int(load_library().csfmm_workspace_bytes(plan.handle))
+
+
+def eval_many(requests, outs=None):
+    """csfmm_eval_many over [(plan, workspace, kernel, weights), ...] -> outputs.
+
+    One packed launch per phase serves all requests (near and far field: one
+    per kernel id and form).  Returns the list of output tensors.
+    """
+    _require_gpu()
+    n = len(requests)
+    P = (ctypes.c_void_p * n)()
+    W = (ctypes.c_void_p * n)()
+    K = (ctypes.c_int * n)()
+    WP = (ctypes.c_void_p * n)()
+    OP = (ctypes.c_void_p * n)()
+    res = []
+    keep = []
+    for i, (plan, ws, kernel, weights) in enumerate(requests):
+        if ws.plan is not plan:
+            raise ValueError("request %d: workspace belongs to another plan" % i)
+        k = plan.kernel if kernel is None else int(kernel)
+        w = _vec(weights, plan.n_s, "weights")
+        o = plan._out(k, None if outs is None else outs[i])
+        keep.append(w)
+        res.append(o)
+        P[i] = plan.handle.value
+        W[i] = ws.handle.value
+        K[i] = k
+        WP[i] = w.data_ptr()
+        OP[i] = o.data_ptr()
+    _check(_lib.csfmm_eval_many(n, P, W, K, WP, OP, _stream()))
+    return res
 
 
 def direct(targets, sources, weights, kernel=POISSON, fp32=False, out=None):

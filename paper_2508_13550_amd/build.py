@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcsfmm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "plan.hip", "eval.hip", "tile.hip", "sort_scan.hip"]
+SOURCES = ["api.hip", "plan.hip", "eval.hip", "tile.hip", "sort_scan.hip", "sched.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -27,7 +27,7 @@ FLAGS = [
 
 
 def _compile(src):
-    obj = os.path.join(BUILD_DIR, src.replace(".hip", ".o"))
+    obj = os.path.join(BUILD_DIR, src.rsplit(".", 1)[0] + ".o")
     cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -201,6 +201,56 @@ int64_t csfmm_estimate_bytes(int64_t n_t, int64_t n_s, int p, int leaf_size, uns
     return b;
 }
 
+int csfmm_workspace_create(csfmm_plan_t plan, void* stream, csfmm_workspace_t* out) {
+    clear_error();
+    if (!plan || !out) {
+        set_error("plan and out must be non-NULL");
+        return CSFMM_E_INVALID;
+    }
+    return workspace_create(plan, static_cast<hipStream_t>(stream), out);
+}
+
+int csfmm_workspace_destroy(csfmm_workspace_t ws) {
+    clear_error();
+    if (!ws) return CSFMM_OK;
+    (void)hipDeviceSynchronize();
+    delete ws;
+    return CSFMM_OK;
+}
+
+int64_t csfmm_workspace_bytes(csfmm_plan_t plan) {
+    if (!plan) return -1;
+    return int64_t(sizeof(double)) *
+           (plan->ns + int64_t(plan->st->ncells) * plan->KS +
+            int64_t(3) * plan->tt.ncells * plan->KS + int64_t(3) * plan->nt) +
+           int64_t(sizeof(csfmm::ReqView));
+}
+
+int csfmm_eval_many(int n_req, const csfmm_plan_t* plans, const csfmm_workspace_t* workspaces,
+                    const int* kernel_ids, const double* const* weights, double* const* outs,
+                    void* stream) {
+    clear_error();
+    if (n_req < 0 || (n_req > 0 && (!plans || !workspaces || !weights || !outs))) {
+        set_error("eval_many: bad arguments");
+        return CSFMM_E_INVALID;
+    }
+    std::vector<EvalReq> reqs(size_t(n_req > 0 ? n_req : 0));
+    for (int r = 0; r < n_req; ++r) {
+        csfmm_plan_t P = plans[r];
+        csfmm_workspace_t W = workspaces[r];
+        const int k = kernel_ids ? kernel_ids[r] : (P ? P->kernel : 0);
+        if (!P || !W || W->plan != P || !weights[r] || !outs[r] || !valid_kernel(k)) {
+            set_error("eval_many: request %d has a NULL pointer, a workspace of another plan or "
+                      "a bad kernel id",
+                      r);
+            return CSFMM_E_INVALID;
+        }
+        reqs[r] = EvalReq{P, W, k, weights[r], outs[r]};
+    }
+    if (n_req == 0) return CSFMM_OK;
+    return run_eval_batch(reqs.data(), n_req, static_cast<hipStream_t>(stream));
+}
+
 int csfmm_plan_timing(csfmm_plan_t plan, int enable) {
     clear_error();
     if (!plan) {

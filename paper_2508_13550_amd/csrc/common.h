@@ -108,7 +108,57 @@ struct Lists {
     int64_t evals[4] = {0, 0, 0, 0};
 };
 
+// Device-resident description of one (plan, workspace) pair: every pointer and
+// size an eval kernel needs about one request.
+struct ReqView {
+    // target tree
+    const int32_t *t_begin, *t_count, *t_child0, *t_leaves, *t_parents, *t_perm;
+    const double *t_x, *t_y, *t_z, *t_u, *t_v, *t_center, *t_prox;
+    // source tree
+    const int32_t *s_begin, *s_count, *s_child0, *s_leaves, *s_parents, *s_perm;
+    const double *s_x, *s_y, *s_z, *s_u, *s_v, *s_prox;
+    // interaction lists
+    const int32_t* off[4];
+    const int32_t* src[4];
+    const int32_t *novl, *far_targets;
+    // fixed operators
+    const double *bm2m, *bl2l;
+    // workspace
+    double *ws, *wbar, *psi, *phinear;
+    int64_t nt, ns, psi_stride;
+    int32_t p, K, KS, nb1, nb2;
+};
+
+// Kernel argument of every eval launch: up to kMaxBatch requests; block b of
+// the grid belongs to request r with prefix[r] <= b < prefix[r+1].
+constexpr int kMaxBatch = 32;
+struct Batch {
+    int32_t n;
+    const ReqView* v[kMaxBatch];
+    const double* w[kMaxBatch];     // caller weights (caller order)
+    double* out[kMaxBatch];         // caller outputs (caller order)
+    int32_t vd[kMaxBatch];          // output components: 3 for Biot-Savart, else 1
+    int32_t a0[kMaxBatch];          // M2M / L2L: first parent of the level in `parents`
+    int32_t a1[kMaxBatch];          // M2M / L2L: number of parents at the level
+    int32_t prefix[kMaxBatch + 1];
+};
+
+__device__ __forceinline__ void batch_locate(const Batch& b, int blk, int& r, int& local) {
+    int lo = 0, hi = b.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.prefix[mid] <= blk)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    r = lo;
+    local = blk - b.prefix[lo];
+}
+
 }  // namespace csfmm
+
+struct csfmm_workspace_s;
 
 struct csfmm_plan_s {
     int64_t nt = 0, ns = 0;
@@ -126,11 +176,8 @@ struct csfmm_plan_s {
     double* bl2l = nullptr;  // [KS][NB2],   NB2 = roundup(4*KS,16)
     double* lag1d = nullptr; // [2][p+1][p+1] 1-D parent-at-child-node values (for inspection)
     int nb1 = 0, nb2 = 0;
-    // eval workspace
-    double* ws = nullptr;      // [ns] sorted weights
-    double* wbar = nullptr;    // [ncells_s][KS]
-    double* psi = nullptr;     // [3][ncells_t][KS]
-    double* phinear = nullptr; // [3][nt]
+    // the plan's own workspace, used by csfmm_eval
+    csfmm_workspace_s* ws0 = nullptr;
     // optional per-stage timing with HIP events (ring of event sets)
     struct Timing {
         static constexpr int kStages = 6;  // P2M, M2M, near, far, L2L, L2P
@@ -142,11 +189,28 @@ struct csfmm_plan_s {
         int64_t n = 0;
         int next = 0;
     } timing;
-    ~csfmm_plan_s() {
-        for (hipEvent_t e : timing.ev) (void)hipEventDestroy(e);
-        arena.release();
-    }
+    ~csfmm_plan_s();
 };
+
+// Eval workspace bound to one plan: sorted weights, proxy weights, proxy
+// potentials and near field, plus the device copy of the request view.
+struct csfmm_workspace_s {
+    csfmm_plan_s* plan = nullptr;
+    csfmm::DevArena arena;
+    double* ws = nullptr;       // [ns]
+    double* wbar = nullptr;     // [ncells_s][KS]
+    double* psi = nullptr;      // [3][ncells_t][KS]
+    double* phinear = nullptr;  // [3][nt]
+    csfmm::ReqView* dview = nullptr;  // device copy of dview_host
+    csfmm::ReqView dview_host{};
+    ~csfmm_workspace_s() { arena.release(); }
+};
+
+inline csfmm_plan_s::~csfmm_plan_s() {
+    for (hipEvent_t e : timing.ev) (void)hipEventDestroy(e);
+    delete ws0;
+    arena.release();
+}
 
 namespace csfmm {
 
@@ -165,12 +229,21 @@ int timing_enable(csfmm_plan_s* P, bool on);
 int timing_collect(csfmm_plan_s* P);
 
 // ---- eval (eval.hip)
+int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** out);
+struct EvalReq {
+    csfmm_plan_s* plan;
+    csfmm_workspace_s* ws;
+    int kernel;
+    const double* w;
+    double* out;
+};
+// one packed eval of up to kMaxBatch requests (timing marks when n == 1)
+int run_eval_batch(const EvalReq* reqs, int n, hipStream_t s);
 int run_eval(csfmm_plan_s* P, int kernel, const double* weights, double* out, double* wbar_out,
              double* psi_out, double* near_out, hipStream_t s);
 
-// ---- tile engine (tile.hip)
-int launch_near(csfmm_plan_s* P, int kernel, hipStream_t s);
-int launch_far(csfmm_plan_s* P, int kernel, hipStream_t s);
+// ---- tile engine (tile.hip): b holds requests of one kernel and form
+int launch_tile_batch(const Batch& b, int kernel, bool fp32, bool far, hipStream_t s);
 int launch_direct(const double* tgt, int64_t nt, const double* src, int64_t ns, const double* w,
                   int kernel, bool fp32, double* out, hipStream_t s);
 

@@ -1,9 +1,20 @@
-// Evaluation of a plan (paper §8, Algorithm 2 lines 3, 5 and 7-21):
+// Evaluation of plans (paper §8, Algorithm 2 lines 3, 5 and 7-21):
 //   gather weights -> P2M (eq. PC proxy weights of the leaves) -> M2M by
 //   levels (eq. upwardpass2, FP64 MFMA) -> near field PP+PC and far field
 //   CP+CC (tile engine) -> L2L by levels (eq. downward_2, FP64 MFMA) ->
 //   L2P at the leaves (eq. downward_1) fused with the scatter to the caller's
 //   order.
+//
+// Every launch is a batch of up to kMaxBatch requests (a request is a plan
+// with its own workspace, weights and output); block b works for the request
+// r with prefix[r] <= b < prefix[r+1].  A single csfmm_eval is a batch of
+// one, and every block's arithmetic depends only on its own request, so a
+// request's result does not depend on what it is batched with.
+#include <algorithm>
+#include <map>
+#include <new>
+#include <utility>
+
 #include "common.h"
 #include "dev_util.h"
 
@@ -16,15 +27,26 @@ constexpr int kMaxP1 = kMaxDegree + 1;
 
 __device__ __forceinline__ double cheb(int k, int p) { return cos(double(k) * kPi / double(p)); }
 
-__global__ void k_gather_w(const double* __restrict__ w, const int32_t* __restrict__ perm, int64_t n,
-                           double* __restrict__ ws) {
-    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k < n) ws[k] = w[perm[k]];
+__device__ __forceinline__ void locate(const Batch& b, int& r, int& local) {
+    batch_locate(b, xcd_logical_block(blockIdx.x, gridDim.x), r, local);
 }
 
-__global__ void k_fill_zero(double* __restrict__ a, int64_t n) {
-    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k < n) a[k] = 0.0;
+// e1: ws[k] = w[perm[k]]   (256 sorted sources per block)
+__global__ __launch_bounds__(256) void k_gather_w(Batch b) {
+    int r, local;
+    locate(b, r, local);
+    const ReqView& V = *b.v[r];
+    const int64_t k = int64_t(local) * 256 + threadIdx.x;
+    if (k < V.ns) V.ws[k] = b.w[r][V.s_perm[k]];
+}
+
+// psi = 0 for the request's output components (256 values per block)
+__global__ __launch_bounds__(256) void k_zero_psi(Batch b) {
+    int r, local;
+    locate(b, r, local);
+    const ReqView& V = *b.v[r];
+    const int64_t k = int64_t(local) * 256 + threadIdx.x;
+    if (k < int64_t(b.vd[r]) * V.psi_stride) V.psi[k] = 0.0;
 }
 
 // Barycentric values L_0..L_p at x (§4, eq. barycentric), exact hit -> delta.
@@ -49,80 +71,87 @@ __device__ __forceinline__ void bary_row(int p, const double* s, const double* b
 __device__ __forceinline__ void cheb_setup(int p, double* s, double* beta) {
     for (int k = threadIdx.x; k <= p; k += blockDim.x) {
         s[k] = cheb(k, p);
-        double b = (k & 1) ? -1.0 : 1.0;
-        if (k == 0 || k == p) b *= 0.5;
-        beta[k] = b;
+        double bb = (k & 1) ? -1.0 : 1.0;
+        if (k == 0 || k == p) bb *= 0.5;
+        beta[k] = bb;
     }
 }
 
-// P2M: wbar_k(leaf) = sum_j L_k1(u_j) L_k2(v_j) w_j   (eq. PC, §6)
+// e2 P2M: wbar_k(leaf) = sum_j L_k1(u_j) L_k2(v_j) w_j (eq. PC, §6); one source leaf per block
 constexpr int kP2MThreads = 128;
-__global__ __launch_bounds__(kP2MThreads) void k_p2m(const int32_t* __restrict__ leaves,
-                                                     const int32_t* __restrict__ begin,
-                                                     const int32_t* __restrict__ count,
-                                                     const double* __restrict__ u,
-                                                     const double* __restrict__ v,
-                                                     const double* __restrict__ ws, int p, int KS,
-                                                     double* __restrict__ wbar) {
+__global__ __launch_bounds__(kP2MThreads) void k_p2m(Batch b) {
     __shared__ double s[kMaxP1], beta[kMaxP1];
     __shared__ double Lu[kP2MThreads][kMaxP1 + 1];
     __shared__ double Lv[kP2MThreads][kMaxP1 + 1];
     __shared__ double wv[kP2MThreads];
-    const int c = leaves[xcd_logical_block(blockIdx.x, gridDim.x)];
-    const int b = begin[c], m = count[c];
-    const int P1 = p + 1, K = P1 * P1;
+    int r, local;
+    locate(b, r, local);
+    const ReqView& V = *b.v[r];
+    const int c = V.s_leaves[local];
+    const int bgn = V.s_begin[c], m = V.s_count[c];
+    const int p = V.p, P1 = p + 1, K = P1 * P1, KS = V.KS;
     cheb_setup(p, s, beta);
     __syncthreads();
     double acc[3] = {0.0, 0.0, 0.0};  // K <= 3 * kP2MThreads
     for (int j0 = 0; j0 < m; j0 += kP2MThreads) {
         const int nj = min(kP2MThreads, m - j0);
         if (threadIdx.x < nj) {
-            const int j = b + j0 + threadIdx.x;
-            bary_row(p, s, beta, u[j], Lu[threadIdx.x]);
-            bary_row(p, s, beta, v[j], Lv[threadIdx.x]);
-            wv[threadIdx.x] = ws[j];
+            const int j = bgn + j0 + threadIdx.x;
+            bary_row(p, s, beta, V.s_u[j], Lu[threadIdx.x]);
+            bary_row(p, s, beta, V.s_v[j], Lv[threadIdx.x]);
+            wv[threadIdx.x] = V.ws[j];
         }
         __syncthreads();
-        for (int r = 0; r < 3; ++r) {
-            const int k = threadIdx.x + r * kP2MThreads;
+        for (int q = 0; q < 3; ++q) {
+            const int k = threadIdx.x + q * kP2MThreads;
             if (k < K) {
                 const int k1 = k / P1, k2 = k % P1;
-                double a = acc[r];
+                double a = acc[q];
                 for (int j = 0; j < nj; ++j) a += Lu[j][k1] * Lv[j][k2] * wv[j];
-                acc[r] = a;
+                acc[q] = a;
             }
         }
         __syncthreads();
     }
-    for (int r = 0; r < 3; ++r) {
-        const int k = threadIdx.x + r * kP2MThreads;
-        if (k < KS) wbar[int64_t(c) * KS + k] = (k < K) ? acc[r] : 0.0;
+    for (int q = 0; q < 3; ++q) {
+        const int k = threadIdx.x + q * kP2MThreads;
+        if (k < KS) V.wbar[int64_t(c) * KS + k] = (k < K) ? acc[q] : 0.0;
     }
 }
 
-// Batched small GEMM on FP64 MFMA (v_mfma_f64_16x16x4f64), 16 rows per block,
-// the four waves share the 16-column tiles of the output.
-//   MODE 0 (M2M, eq. upwardpass2): row = parent P;  A = wbar of its 4 children
-//     (4*KS contiguous values), B = bm2m [4KS][nb], C = wbar(P) (KS columns, written)
-//   MODE 1 (L2L, eq. downward_2):  row = (component, parent P); A = psi(P) (KS),
-//     B = bl2l [KS][nb], C = psi of the 4 children (4*KS columns, accumulated)
+// Batched small GEMMs on FP64 MFMA (v_mfma_f64_16x16x4f64) for the fixed
+// parent-child operators at one tree level; request r's parents at the level
+// are parents[a0[r] .. a0[r] + a1[r]).
+//   MODE 0 (M2M, eq. upwardpass2): row = parent P; A = wbar of its 4 children
+//     (4*KS contiguous values), B = bm2m [4KS][nb1], C = wbar(P), written.
+//     One block per (16-row tile, 16-column tile); wave q takes the K-slice of
+//     child q (split-K) and the four partial tiles are summed in LDS.
+//   MODE 1 (L2L, eq. downward_2): row = (component, parent P); A = psi(P) (KS
+//     values), B = bl2l [KS][nb2], C = psi of the 4 children, accumulated.
+//     One wave per (16-row tile, 16-column tile).
 // MFMA f64 16x16x4 operand layout: lane l holds A[l%16][l/16], B[l/16][l%16]
 // and D[l/16 + 4*i][l%16], i = 0..3 (checked with a one-hot probe).
+// Operand loads are issued kAhead MFMA steps ahead of their use.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_mfma_pass(const int32_t* __restrict__ rows, int np,
-                                                   int ncomp, const int32_t* __restrict__ child0,
-                                                   const double* __restrict__ Abase,
-                                                   double* __restrict__ Cbase, int64_t comp_stride,
-                                                   const double* __restrict__ B, int nb, int KS) {
-    // MODE 0: one block per (16-row tile, 16-column tile); wave q takes the
-    //   K-slice of child q (split-K) and the four partial tiles are summed in LDS.
-    // MODE 1: one wave per (16-row tile, 16-column tile).
-    // Operand loads are issued kAhead MFMA steps ahead of their use.
+__global__ __launch_bounds__(256) void k_mfma_pass(Batch b) {
     constexpr int kAhead = 16;
     __shared__ double4_t part[MODE == 0 ? 3 : 1][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int r, local;
+    locate(b, r, local);
+    const ReqView& V = *b.v[r];
+    const int32_t* rows = (MODE == 0 ? V.s_parents : V.t_parents) + b.a0[r];
+    const int np = b.a1[r];
+    const int32_t* child0 = MODE == 0 ? V.s_child0 : V.t_child0;
+    const int KS = V.KS;
+    const int nb = MODE == 0 ? V.nb1 : V.nb2;
+    const double* B = MODE == 0 ? V.bm2m : V.bl2l;
+    double* Cbase = MODE == 0 ? V.wbar : V.psi;
+    const double* Abase = Cbase;
+    const int64_t comp_stride = MODE == 0 ? 0 : V.psi_stride;
+    const int ncomp = MODE == 0 ? 1 : b.vd[r];
     const int ntiles = nb / 16;
-    const int gw = MODE == 0 ? int(blockIdx.x) : int(blockIdx.x) * 4 + wave;
+    const int gw = MODE == 0 ? local : local * 4 + wave;
     const int rt = gw / ntiles, tile = gw % ntiles;
     const int nrows = np * ncomp;
     const int r0 = rt * 16;
@@ -166,9 +195,9 @@ __global__ __launch_bounds__(256) void k_mfma_pass(const int32_t* __restrict__ r
     if (col < Nw) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int r = r0 + kq + 4 * i;
-            if (r < nrows) {
-                const int comp = r / np, P = rows[r % np];
+            const int rr = r0 + kq + 4 * i;
+            if (rr < nrows) {
+                const int comp = rr / np, P = rows[rr % np];
                 const int cell = MODE == 0 ? P : child0[P];
                 double* crow = Cbase + comp * comp_stride + int64_t(cell) * KS;
                 if (MODE == 0)
@@ -180,52 +209,52 @@ __global__ __launch_bounds__(256) void k_mfma_pass(const int32_t* __restrict__ r
     }
 }
 
-inline unsigned mfma_blocks(int mode, int64_t nrows, int nb) {
-    const int64_t tiles = ((nrows + 15) / 16) * (nb / 16);
-    return unsigned(mode == 0 ? tiles : (tiles + 3) / 4);
-}
-
-// L2P (eq. downward_1 at the leaves) + near field + scatter to caller order.
+// e7+e8: L2P (eq. downward_1 at the leaves) + near field + scatter to caller
+// order; one target leaf per block; VD output components (every request of
+// the launch has the same VD).
 constexpr int kL2PThreads = 128;
 template <int VD>
-__global__ __launch_bounds__(kL2PThreads) void k_l2p(
-    const int32_t* __restrict__ leaves, const int32_t* __restrict__ begin,
-    const int32_t* __restrict__ count, const double* __restrict__ u, const double* __restrict__ v,
-    const double* __restrict__ psi, int64_t psi_stride, const double* __restrict__ near,
-    int64_t nt, const int32_t* __restrict__ perm, int p, int KS, double* __restrict__ out) {
+__global__ __launch_bounds__(kL2PThreads) void k_l2p(Batch b) {
     __shared__ double s[kMaxP1], beta[kMaxP1];
-    __shared__ double ps[VD][(kMaxP1) * (kMaxP1) + 4];
+    __shared__ double ps[VD][kMaxP1 * kMaxP1 + 4];
     __shared__ double Lu[kL2PThreads][kMaxP1 + 1];
     __shared__ double Lv[kL2PThreads][kMaxP1 + 1];
-    const int c = leaves[xcd_logical_block(blockIdx.x, gridDim.x)];
-    const int b = begin[c], m = count[c];
+    int r, local;
+    locate(b, r, local);
+    const ReqView& V = *b.v[r];
+    constexpr int vd = VD;
+    double* out = b.out[r];
+    const int c = V.t_leaves[local];
+    const int bgn = V.t_begin[c], m = V.t_count[c];
     if (m == 0) return;
-    const int P1 = p + 1, K = P1 * P1;
+    const int p = V.p, P1 = p + 1, K = P1 * P1, KS = V.KS;
     cheb_setup(p, s, beta);
     for (int k = threadIdx.x; k < K; k += blockDim.x)
-        for (int d = 0; d < VD; ++d) ps[d][k] = psi[d * psi_stride + int64_t(c) * KS + k];
+        for (int d = 0; d < vd; ++d) ps[d][k] = V.psi[d * V.psi_stride + int64_t(c) * KS + k];
     __syncthreads();
     for (int j0 = 0; j0 < m; j0 += kL2PThreads) {
         const int jj = j0 + threadIdx.x;
         if (jj < m) {
-            const int j = b + jj;
+            const int j = bgn + jj;
             double* L1 = Lu[threadIdx.x];
             double* L2 = Lv[threadIdx.x];
-            bary_row(p, s, beta, u[j], L1);
-            bary_row(p, s, beta, v[j], L2);
+            bary_row(p, s, beta, V.t_u[j], L1);
+            bary_row(p, s, beta, V.t_v[j], L2);
             double acc[VD];
+#pragma unroll
             for (int d = 0; d < VD; ++d) acc[d] = 0.0;
             for (int n1 = 0; n1 < P1; ++n1) {
                 double inner[VD];
+#pragma unroll
                 for (int d = 0; d < VD; ++d) inner[d] = 0.0;
                 for (int n2 = 0; n2 < P1; ++n2) {
                     const double l2 = L2[n2];
-                    for (int d = 0; d < VD; ++d) inner[d] += ps[d][n1 * P1 + n2] * l2;
+                    for (int d = 0; d < vd; ++d) inner[d] += ps[d][n1 * P1 + n2] * l2;
                 }
-                for (int d = 0; d < VD; ++d) acc[d] += L1[n1] * inner[d];
+                for (int d = 0; d < vd; ++d) acc[d] += L1[n1] * inner[d];
             }
-            const int64_t o = perm[j];
-            for (int d = 0; d < VD; ++d) out[o * VD + d] = near[d * nt + j] + acc[d];
+            const int64_t o = V.t_perm[j];
+            for (int d = 0; d < vd; ++d) out[o * vd + d] = V.phinear[d * V.nt + j] + acc[d];
         }
     }
 }
@@ -236,6 +265,12 @@ __global__ void k_scatter_near(const double* __restrict__ near, int64_t nt, int 
     if (k >= nt) return;
     const int64_t o = perm[k];
     for (int d = 0; d < vd; ++d) out[o * vd + d] = near[d * nt + k];
+}
+
+// Writes a request view to device memory (kernel argument instead of a copy,
+// so that it is ordered on the caller's stream only).
+__global__ void k_set_view(ReqView* dst, ReqView v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
 }
 
 inline unsigned nblk(int64_t n, int t = 256) { return unsigned((n + t - 1) / t); }
@@ -254,6 +289,145 @@ int drain_slot(Timing& tm, int slot) {
     }
     tm.n += 1;
     tm.pending[slot] = 0;
+    return CSFMM_OK;
+}
+
+// Launch helper: fills b.prefix from per-request block counts, skips empty launches.
+template <class F>
+int launch_batched(Batch& b, const int64_t* blocks, F&& launch) {
+    int64_t tot = 0;
+    for (int r = 0; r < b.n; ++r) {
+        b.prefix[r] = int32_t(tot);
+        tot += blocks[r];
+    }
+    b.prefix[b.n] = int32_t(tot);
+    if (tot <= 0) return CSFMM_OK;
+    if (tot > (int64_t(1) << 31) - 1) {
+        set_error("batched launch too large");
+        return CSFMM_E_INVALID;
+    }
+    launch(unsigned(tot));
+    CSFMM_LAUNCH_CHECK();
+    return CSFMM_OK;
+}
+
+int64_t mfma_tiles(int64_t nrows, int nb) { return ((nrows + 15) / 16) * (nb / 16); }
+
+int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
+    Batch b{};
+    b.n = n;
+    for (int r = 0; r < n; ++r) {
+        b.v[r] = reqs[r].ws->dview;
+        b.w[r] = reqs[r].w;
+        b.out[r] = reqs[r].out;
+        b.vd[r] = reqs[r].kernel == CSFMM_K_BIOT_SAVART ? 3 : 1;
+    }
+    int64_t blk[kMaxBatch];
+    // optional stage timing (single request)
+    hipEvent_t* ev = nullptr;
+    if (n == 1 && reqs[0].plan->timing.on) {
+        Timing& tm = reqs[0].plan->timing;
+        const int slot = tm.next;
+        tm.next = (tm.next + 1) % Timing::kSlots;
+        int rc = drain_slot(tm, slot);
+        if (rc != CSFMM_OK) return rc;
+        ev = &tm.ev[size_t(slot) * (Timing::kStages + 1)];
+        tm.pending[slot] = 1;
+    }
+    auto mark = [&](int k) -> int {
+        if (ev) CSFMM_HIP_TRY(hipEventRecord(ev[k], s));
+        return CSFMM_OK;
+    };
+#define RCX(x)                              \
+    do {                                    \
+        int rc_ = (x);                      \
+        if (rc_ != CSFMM_OK) return rc_;    \
+    } while (0)
+    RCX(mark(0));
+    // e1 gather, e2 P2M
+    for (int r = 0; r < n; ++r) blk[r] = (reqs[r].plan->ns + 255) / 256;
+    RCX(launch_batched(b, blk, [&](unsigned g) { k_gather_w<<<g, 256, 0, s>>>(b); }));
+    for (int r = 0; r < n; ++r) blk[r] = reqs[r].plan->st->nleaves;
+    RCX(launch_batched(b, blk, [&](unsigned g) { k_p2m<<<g, kP2MThreads, 0, s>>>(b); }));
+    RCX(mark(1));
+    // e3 M2M, deepest parents first
+    int maxd = 0;
+    for (int r = 0; r < n; ++r) maxd = std::max(maxd, int(reqs[r].plan->st->depth));
+    for (int l = maxd - 1; l >= 0; --l) {
+        for (int r = 0; r < n; ++r) {
+            const Tree& S = *reqs[r].plan->st;
+            const int np = l < S.depth ? S.parents_begin[l + 1] - S.parents_begin[l] : 0;
+            b.a0[r] = l < S.depth ? S.parents_begin[l] : 0;
+            b.a1[r] = np;
+            blk[r] = mfma_tiles(np, reqs[r].plan->nb1);
+        }
+        RCX(launch_batched(b, blk, [&](unsigned g) { k_mfma_pass<0><<<g, 256, 0, s>>>(b); }));
+    }
+    RCX(mark(2));
+    // e4 near field (PP + PC), one launch per (kernel, form) group
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    for (int r = 0; r < n; ++r)
+        groups[{reqs[r].kernel, (reqs[r].plan->flags & CSFMM_FP32_FORM) ? 1 : 0}].push_back(r);
+    auto sub_batch = [&](const std::vector<int>& idx, bool far) -> int {
+        Batch g{};
+        g.n = int(idx.size());
+        int64_t gb[kMaxBatch];
+        for (int q = 0; q < g.n; ++q) {
+            const int r = idx[q];
+            g.v[q] = b.v[r];
+            g.w[q] = b.w[r];
+            g.out[q] = b.out[r];
+            g.vd[q] = b.vd[r];
+            gb[q] = far ? reqs[r].plan->lists.n_far_targets : reqs[r].plan->tt.nleaves;
+        }
+        int64_t tot = 0;
+        for (int q = 0; q < g.n; ++q) {
+            g.prefix[q] = int32_t(tot);
+            tot += gb[q];
+        }
+        g.prefix[g.n] = int32_t(tot);
+        const int kern = reqs[idx[0]].kernel;
+        const bool f32 = (reqs[idx[0]].plan->flags & CSFMM_FP32_FORM) != 0;
+        return launch_tile_batch(g, kern, f32, far, s);
+    };
+    for (auto& kv : groups) RCX(sub_batch(kv.second, false));
+    RCX(mark(3));
+    // e5 far field (CP + CC) into zeroed proxy potentials
+    for (int r = 0; r < n; ++r)
+        blk[r] = (int64_t(b.vd[r]) * reqs[r].ws->dview_host.psi_stride + 255) / 256;
+    RCX(launch_batched(b, blk, [&](unsigned g) { k_zero_psi<<<g, 256, 0, s>>>(b); }));
+    for (auto& kv : groups) RCX(sub_batch(kv.second, true));
+    RCX(mark(4));
+    // e6 L2L, root level first
+    int maxt = 0;
+    for (int r = 0; r < n; ++r) maxt = std::max(maxt, int(reqs[r].plan->tt.depth));
+    for (int l = 0; l < maxt; ++l) {
+        for (int r = 0; r < n; ++r) {
+            const Tree& T = reqs[r].plan->tt;
+            const int np = l < T.depth ? T.parents_begin[l + 1] - T.parents_begin[l] : 0;
+            b.a0[r] = l < T.depth ? T.parents_begin[l] : 0;
+            b.a1[r] = np;
+            blk[r] = (mfma_tiles(int64_t(np) * b.vd[r], reqs[r].plan->nb2) + 3) / 4;
+        }
+        RCX(launch_batched(b, blk, [&](unsigned g) { k_mfma_pass<1><<<g, 256, 0, s>>>(b); }));
+    }
+    RCX(mark(5));
+    // e7+e8 L2P, near field and scatter to the caller's order; one launch per
+    // number of output components (blocks of the other group are empty)
+    for (int vdl : {1, 3}) {
+        bool any = false;
+        for (int r = 0; r < n; ++r) {
+            blk[r] = b.vd[r] == vdl ? reqs[r].plan->tt.nleaves : 0;
+            any = any || blk[r] > 0;
+        }
+        if (!any) continue;
+        if (vdl == 1)
+            RCX(launch_batched(b, blk, [&](unsigned g) { k_l2p<1><<<g, kL2PThreads, 0, s>>>(b); }));
+        else
+            RCX(launch_batched(b, blk, [&](unsigned g) { k_l2p<3><<<g, kL2PThreads, 0, s>>>(b); }));
+    }
+    RCX(mark(6));
+#undef RCX
     return CSFMM_OK;
 }
 
@@ -287,92 +461,84 @@ int timing_collect(csfmm_plan_s* P) {
     return CSFMM_OK;
 }
 
+int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** out) {
+    *out = nullptr;
+    csfmm_workspace_s* W = new (std::nothrow) csfmm_workspace_s();
+    if (!W) {
+        set_error("host allocation failed");
+        return CSFMM_E_OOM;
+    }
+    W->plan = P;
+    const Tree& T = P->tt;
+    const Tree& S = *P->st;
+    int rc = CSFMM_OK;
+    if (rc == CSFMM_OK) rc = W->arena.alloc(&W->ws, P->ns);
+    if (rc == CSFMM_OK) rc = W->arena.alloc(&W->wbar, int64_t(S.ncells) * P->KS);
+    if (rc == CSFMM_OK) rc = W->arena.alloc(&W->psi, int64_t(3) * T.ncells * P->KS);
+    if (rc == CSFMM_OK) rc = W->arena.alloc(&W->phinear, int64_t(3) * P->nt);
+    if (rc == CSFMM_OK) rc = W->arena.alloc(&W->dview, 1);
+    if (rc != CSFMM_OK) {
+        delete W;
+        return rc;
+    }
+    ReqView& v = W->dview_host;
+    v = ReqView{};
+    v.t_begin = T.begin; v.t_count = T.count; v.t_child0 = T.child0; v.t_leaves = T.leaves;
+    v.t_parents = T.parents; v.t_perm = T.perm;
+    v.t_x = T.x; v.t_y = T.y; v.t_z = T.z; v.t_u = T.u; v.t_v = T.v;
+    v.t_center = T.center; v.t_prox = T.prox;
+    v.s_begin = S.begin; v.s_count = S.count; v.s_child0 = S.child0; v.s_leaves = S.leaves;
+    v.s_parents = S.parents; v.s_perm = S.perm;
+    v.s_x = S.x; v.s_y = S.y; v.s_z = S.z; v.s_u = S.u; v.s_v = S.v; v.s_prox = S.prox;
+    for (int k = 0; k < 4; ++k) {
+        v.off[k] = P->lists.off[k];
+        v.src[k] = P->lists.src[k];
+    }
+    v.novl = P->lists.novl;
+    v.far_targets = P->lists.far_targets;
+    v.bm2m = P->bm2m;
+    v.bl2l = P->bl2l;
+    v.ws = W->ws; v.wbar = W->wbar; v.psi = W->psi; v.phinear = W->phinear;
+    v.nt = P->nt; v.ns = P->ns;
+    v.psi_stride = int64_t(T.ncells) * P->KS;
+    v.p = P->p; v.K = P->K; v.KS = P->KS; v.nb1 = P->nb1; v.nb2 = P->nb2;
+    k_set_view<<<1, 64, 0, stream>>>(W->dview, v);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        set_error("writing the request view failed: %s", hipGetErrorString(e));
+        delete W;
+        return CSFMM_E_HIP;
+    }
+    *out = W;
+    return CSFMM_OK;
+}
+
+int run_eval_batch(const EvalReq* reqs, int n, hipStream_t s) {
+    for (int r0 = 0; r0 < n; r0 += kMaxBatch) {
+        int rc = run_chunk(reqs + r0, std::min(kMaxBatch, n - r0), s);
+        if (rc != CSFMM_OK) return rc;
+    }
+    return CSFMM_OK;
+}
+
 int run_eval(csfmm_plan_s* P, int kernel, const double* weights, double* out, double* wbar_out,
              double* psi_out, double* near_out, hipStream_t s) {
-    Tree& T = P->tt;
-    Tree& S = *P->st;
+    EvalReq q{P, P->ws0, kernel, weights, out};
+    int rc = run_eval_batch(&q, 1, s);
+    if (rc != CSFMM_OK) return rc;
+    const Tree& T = P->tt;
+    const Tree& S = *P->st;
     const int vd = kernel == CSFMM_K_BIOT_SAVART ? 3 : 1;
-    const int64_t psi_stride = int64_t(T.ncells) * P->KS;
-    Timing& tm = P->timing;
-    hipEvent_t* ev = nullptr;
-    if (tm.on) {
-        const int slot = tm.next;
-        tm.next = (tm.next + 1) % Timing::kSlots;
-        int rc = drain_slot(tm, slot);
-        if (rc != CSFMM_OK) return rc;
-        ev = &tm.ev[size_t(slot) * (Timing::kStages + 1)];
-        tm.pending[slot] = 1;
-    }
-    auto mark = [&](int k) -> int {
-        if (ev) CSFMM_HIP_TRY(hipEventRecord(ev[k], s));
-        return CSFMM_OK;
-    };
-    int mrc = mark(0);
-    if (mrc != CSFMM_OK) return mrc;
-
-    // e1 gather weights into sorted order
-    k_gather_w<<<nblk(P->ns), 256, 0, s>>>(weights, S.perm, P->ns, P->ws);
-    CSFMM_LAUNCH_CHECK();
-    // e2 P2M at the source leaves
-    if (S.nleaves > 0) {
-        k_p2m<<<S.nleaves, kP2MThreads, 0, s>>>(S.leaves, S.begin, S.count, S.u, S.v, P->ws, P->p,
-                                                P->KS, P->wbar);
-        CSFMM_LAUNCH_CHECK();
-    }
-    if ((mrc = mark(1)) != CSFMM_OK) return mrc;
-    // e3 M2M, deepest parents first
-    for (int l = S.depth - 1; l >= 0; --l) {
-        const int pb = S.parents_begin[l], np = S.parents_begin[l + 1] - pb;
-        if (np <= 0) continue;
-        k_mfma_pass<0><<<mfma_blocks(0, np, P->nb1), 256, 0, s>>>(
-            S.parents + pb, np, 1, S.child0, P->wbar, P->wbar, 0, P->bm2m, P->nb1, P->KS);
-        CSFMM_LAUNCH_CHECK();
-    }
-    if ((mrc = mark(2)) != CSFMM_OK) return mrc;
-    // e4 near field: PP + PC
-    {
-        int rc = launch_near(P, kernel, s);
-        if (rc != CSFMM_OK) return rc;
-    }
-    if ((mrc = mark(3)) != CSFMM_OK) return mrc;
-    // e5 far field: CP + CC into the accumulated proxy potentials
-    k_fill_zero<<<nblk(vd * psi_stride), 256, 0, s>>>(P->psi, vd * psi_stride);
-    CSFMM_LAUNCH_CHECK();
-    {
-        int rc = launch_far(P, kernel, s);
-        if (rc != CSFMM_OK) return rc;
-    }
-    if ((mrc = mark(4)) != CSFMM_OK) return mrc;
-    // e6 L2L, root level first
-    for (int l = 0; l < T.depth; ++l) {
-        const int pb = T.parents_begin[l], np = T.parents_begin[l + 1] - pb;
-        if (np <= 0) continue;
-        k_mfma_pass<1><<<mfma_blocks(1, int64_t(np) * vd, P->nb2), 256, 0, s>>>(
-            T.parents + pb, np, vd, T.child0, P->psi, P->psi, psi_stride, P->bl2l, P->nb2, P->KS);
-        CSFMM_LAUNCH_CHECK();
-    }
-    if ((mrc = mark(5)) != CSFMM_OK) return mrc;
-    // e7+e8 L2P, near field and scatter to the caller's order
-    if (T.nleaves > 0) {
-        if (vd == 3)
-            k_l2p<3><<<T.nleaves, kL2PThreads, 0, s>>>(T.leaves, T.begin, T.count, T.u, T.v, P->psi,
-                                                       psi_stride, P->phinear, P->nt, T.perm, P->p,
-                                                       P->KS, out);
-        else
-            k_l2p<1><<<T.nleaves, kL2PThreads, 0, s>>>(T.leaves, T.begin, T.count, T.u, T.v, P->psi,
-                                                       psi_stride, P->phinear, P->nt, T.perm, P->p,
-                                                       P->KS, out);
-        CSFMM_LAUNCH_CHECK();
-    }
-    if ((mrc = mark(6)) != CSFMM_OK) return mrc;
     if (wbar_out)
-        CSFMM_HIP_TRY(hipMemcpyAsync(wbar_out, P->wbar, sizeof(double) * S.ncells * P->KS,
+        CSFMM_HIP_TRY(hipMemcpyAsync(wbar_out, P->ws0->wbar, sizeof(double) * S.ncells * P->KS,
                                      hipMemcpyDeviceToDevice, s));
     if (psi_out)
-        CSFMM_HIP_TRY(hipMemcpyAsync(psi_out, P->psi, sizeof(double) * vd * psi_stride,
+        CSFMM_HIP_TRY(hipMemcpyAsync(psi_out, P->ws0->psi,
+                                     sizeof(double) * vd * int64_t(T.ncells) * P->KS,
                                      hipMemcpyDeviceToDevice, s));
     if (near_out) {
-        k_scatter_near<<<nblk(P->nt), 256, 0, s>>>(P->phinear, P->nt, vd, T.perm, near_out);
+        k_scatter_near<<<nblk(P->nt), 256, 0, s>>>(P->ws0->phinear, P->nt, vd, T.perm, near_out);
         CSFMM_LAUNCH_CHECK();
     }
     return CSFMM_OK;

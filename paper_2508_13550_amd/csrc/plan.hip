@@ -849,12 +849,8 @@ int build_plan(csfmm_plan_s* P, const double* targets, const double* sources, hi
     k_build_ops<<<1, 256, 0, s>>>(P->p, P->KS, P->nb1, P->nb2, P->lag1d, P->bm2m, P->bl2l);
     CSFMM_LAUNCH_CHECK();
     RC(build_lists(P, s));
-    // eval workspace
-    const int vd = 3;
-    RC(A.alloc(&P->ws, P->ns));
-    RC(A.alloc(&P->wbar, int64_t(P->st->ncells) * P->KS));
-    RC(A.alloc(&P->psi, int64_t(vd) * P->tt.ncells * P->KS));
-    RC(A.alloc(&P->phinear, int64_t(vd) * P->nt));
+    // the plan's own eval workspace
+    RC(workspace_create(P, s, &P->ws0));
     CSFMM_HIP_TRY(hipStreamSynchronize(s));
     return CSFMM_OK;
 }

@@ -154,6 +154,39 @@ struct TileArgs {
     int64_t comp_stride;
 };
 
+// The near kernel (TPROX = false) takes target particles of leaves with the PP
+// and PC lists; the far kernel (TPROX = true) takes target proxies with CP, CC.
+template <bool TPROX>
+__device__ __forceinline__ TileArgs tile_args(const ReqView& V) {
+    TileArgs a;
+    a.tcells = TPROX ? V.far_targets : V.t_leaves;
+    a.tbegin = V.t_begin;
+    a.tcount = V.t_count;
+    a.tcenter = V.t_center;
+    a.tx = V.t_x;
+    a.ty = V.t_y;
+    a.tz = V.t_z;
+    a.tprox = V.t_prox;
+    a.off_a = V.off[TPROX ? kCP : kPP];
+    a.src_a = V.src[TPROX ? kCP : kPP];
+    a.off_b = V.off[TPROX ? kCC : kPC];
+    a.src_b = V.src[TPROX ? kCC : kPC];
+    a.novl = TPROX ? nullptr : V.novl;
+    a.sbegin = V.s_begin;
+    a.scount = V.s_count;
+    a.sx = V.s_x;
+    a.sy = V.s_y;
+    a.sz = V.s_z;
+    a.sw = V.ws;
+    a.sprox = V.s_prox;
+    a.swbar = V.wbar;
+    a.K = V.K;
+    a.KS = V.KS;
+    a.out = TPROX ? V.psi : V.phinear;
+    a.comp_stride = TPROX ? V.psi_stride : V.nt;
+    return a;
+}
+
 constexpr int kMaxG = 32;   // source groups per target
 constexpr int kUnroll = 4;
 constexpr int kLds = kChunk + kUnroll * kMaxG;
@@ -194,7 +227,7 @@ __device__ __forceinline__ void run_group(const Stage<F32>& L, int base, int nj,
 }
 
 template <int KERN, bool F32, bool TPROX>
-__global__ __launch_bounds__(kThreads) void k_tile(TileArgs a) {
+__global__ __launch_bounds__(kThreads) void k_tile(Batch b) {
     using R = Real<F32>;
     constexpr int VD = vdim<KERN>();
     constexpr double scale = coord_scale<KERN>();
@@ -204,7 +237,10 @@ __global__ __launch_bounds__(kThreads) void k_tile(TileArgs a) {
     __shared__ int lw[4];
     __shared__ double red[VD][kThreads];
 
-    const int T = a.tcells[xcd_logical_block(blockIdx.x, gridDim.x)];
+    int req, local;
+    batch_locate(b, xcd_logical_block(blockIdx.x, gridDim.x), req, local);
+    const TileArgs a = tile_args<TPROX>(*b.v[req]);
+    const int T = a.tcells[local];
     const int tid = threadIdx.x;
     const double cx = a.tcenter[3 * T], cy = a.tcenter[3 * T + 1], cz = a.tcenter[3 * T + 2];
     const int KS = a.KS;
@@ -544,53 +580,17 @@ __global__ void k_direct_reduce(const double* __restrict__ tgt, int64_t nt,
 }
 
 template <int KERN, bool F32, bool TPROX>
-int launch_tile_t(const TileArgs& a, int nblocks, hipStream_t s) {
+int launch_tile_t(const Batch& b, hipStream_t s) {
+    const int nblocks = b.prefix[b.n];
     if (nblocks <= 0) return CSFMM_OK;
-    k_tile<KERN, F32, TPROX><<<nblocks, kThreads, 0, s>>>(a);
+    k_tile<KERN, F32, TPROX><<<nblocks, kThreads, 0, s>>>(b);
     CSFMM_LAUNCH_CHECK();
     return CSFMM_OK;
 }
 
-template <bool TPROX>
-int launch_tile(int kernel, bool f32, const TileArgs& a, int nblocks, hipStream_t s) {
-    switch (kernel) {
-        case CSFMM_K_POISSON_LOG:
-            return f32 ? launch_tile_t<1, true, TPROX>(a, nblocks, s)
-                       : launch_tile_t<1, false, TPROX>(a, nblocks, s);
-        case CSFMM_K_BIOT_SAVART:
-            return f32 ? launch_tile_t<2, true, TPROX>(a, nblocks, s)
-                       : launch_tile_t<2, false, TPROX>(a, nblocks, s);
-        case CSFMM_K_INV_DIST:
-            return f32 ? launch_tile_t<3, true, TPROX>(a, nblocks, s)
-                       : launch_tile_t<3, false, TPROX>(a, nblocks, s);
-        default:
-            set_error("unknown kernel id %d", kernel);
-            return CSFMM_E_INVALID;
-    }
-}
-
-TileArgs common_args(csfmm_plan_s* P) {
-    TileArgs a{};
-    const Tree& T = P->tt;
-    const Tree& S = *P->st;
-    a.tbegin = T.begin;
-    a.tcount = T.count;
-    a.tcenter = T.center;
-    a.tx = T.x;
-    a.ty = T.y;
-    a.tz = T.z;
-    a.tprox = T.prox;
-    a.sbegin = S.begin;
-    a.scount = S.count;
-    a.sx = S.x;
-    a.sy = S.y;
-    a.sz = S.z;
-    a.sw = P->ws;
-    a.sprox = S.prox;
-    a.swbar = P->wbar;
-    a.K = P->K;
-    a.KS = P->KS;
-    return a;
+template <int KERN, bool F32>
+int launch_tile_k(const Batch& b, bool far, hipStream_t s) {
+    return far ? launch_tile_t<KERN, F32, true>(b, s) : launch_tile_t<KERN, F32, false>(b, s);
 }
 
 template <int KERN, bool F32>
@@ -621,31 +621,18 @@ int launch_direct_t(const double* tgt, int64_t nt, const double* src, int64_t ns
 
 }  // namespace
 
-int launch_near(csfmm_plan_s* P, int kernel, hipStream_t s) {
-    TileArgs a = common_args(P);
-    a.tcells = P->tt.leaves;
-    a.off_a = P->lists.off[kPP];
-    a.src_a = P->lists.src[kPP];
-    a.off_b = P->lists.off[kPC];
-    a.src_b = P->lists.src[kPC];
-    a.novl = P->lists.novl;
-    a.out = P->phinear;
-    a.comp_stride = P->nt;
-    return launch_tile<false>(kernel, (P->flags & CSFMM_FP32_FORM) != 0, a, P->tt.nleaves, s);
-}
-
-int launch_far(csfmm_plan_s* P, int kernel, hipStream_t s) {
-    TileArgs a = common_args(P);
-    a.tcells = P->lists.far_targets;
-    a.off_a = P->lists.off[kCP];
-    a.src_a = P->lists.src[kCP];
-    a.off_b = P->lists.off[kCC];
-    a.src_b = P->lists.src[kCC];
-    a.novl = nullptr;
-    a.out = P->psi;
-    a.comp_stride = int64_t(P->tt.ncells) * P->KS;
-    return launch_tile<true>(kernel, (P->flags & CSFMM_FP32_FORM) != 0, a,
-                             P->lists.n_far_targets, s);
+int launch_tile_batch(const Batch& b, int kernel, bool fp32, bool far, hipStream_t s) {
+    switch (kernel) {
+        case CSFMM_K_POISSON_LOG:
+            return fp32 ? launch_tile_k<1, true>(b, far, s) : launch_tile_k<1, false>(b, far, s);
+        case CSFMM_K_BIOT_SAVART:
+            return fp32 ? launch_tile_k<2, true>(b, far, s) : launch_tile_k<2, false>(b, far, s);
+        case CSFMM_K_INV_DIST:
+            return fp32 ? launch_tile_k<3, true>(b, far, s) : launch_tile_k<3, false>(b, far, s);
+        default:
+            set_error("unknown kernel id %d", kernel);
+            return CSFMM_E_INVALID;
+    }
 }
 
 int launch_direct(const double* tgt, int64_t nt, const double* src, int64_t ns, const double* w,
