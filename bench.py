@@ -59,7 +59,7 @@ def recorded_traffic():
     """HBM bytes per near-field launch from the committed counter record, or
     None when the tile kernel's source has changed since it was taken."""
     import hashlib
-    rec_path = os.path.join(ROOT, "profiles", "near_kernel_poisson_E256_p6_fp32_counters.json")
+    rec_path = os.path.join(ROOT, "profiles", "interactions_poisson_E256_p6_fp32_counters.json")
     src = os.path.join(ROOT, "paper_2508_13550_amd", "csrc", "tile.hip")
     try:
         rec = json.load(open(rec_path))
@@ -306,16 +306,17 @@ def main():
             direct_rate[form] = 3 * S.numel() * N / (time.perf_counter() - t0)
 
     st = head["stats"]
-    near_ms = head["stage"]["near"]
-    evals_near = st["evals_pp"] + st["evals_pc"]
-    achieved = evals_near * FLOP_PER_EVAL / (near_ms / 1e3) / 1e12
+    tile_ms = head["stage"]["interactions"]
+    evals_tile = st["evals_pp"] + st["evals_pc"] + st["evals_cp"] + st["evals_cc"]
+    achieved = evals_tile * FLOP_PER_EVAL / (tile_ms / 1e3) / 1e12
     peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
     roofline = {"bound": "alu",
-                "kernel": "k_tile<Poisson,%s,particle targets>: PP+PC near field" % args.form.upper(),
+                "kernel": "k_tile<Poisson,%s>: PP+PC near field and CP+CC far field in one launch"
+                          " (stage also holds the proxy-potential zero fill)" % args.form.upper(),
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": recorded_traffic() if (fp32 and head["p"] == 6) else None,
-                "flop_per_eval": FLOP_PER_EVAL, "evals_per_launch": evals_near,
-                "avg_launch_ms": near_ms}
+                "flop_per_eval": FLOP_PER_EVAL, "evals_per_launch": evals_tile,
+                "avg_launch_ms": tile_ms}
     line = {
         "metric": METRIC, "value": head["value"], "unit": UNIT, "n_gpus": 1,
         "steps": head["steps"], "warmup": args.warmup, "ms_per_step": head["ms"],

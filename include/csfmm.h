@@ -197,12 +197,12 @@ int csfmm_plan_stats(csfmm_plan_t plan, csfmm_stats* s);
  * Per-stage timing of csfmm_eval with HIP events recorded on the eval's
  * stream.  enable != 0 turns it on (and resets the sums), 0 turns it off.
  * csfmm_plan_timing_read waits for the recorded events and returns the summed
- * milliseconds of the 6 stages over the timed evals:
- *   [0] weight gather + P2M, [1] M2M, [2] near field (PP+PC, one kernel),
- *   [3] far field (CP+CC, one kernel, after zeroing), [4] L2L, [5] L2P+scatter.
+ * milliseconds of the 5 stages over the timed evals:
+ *   [0] weight gather + P2M, [1] M2M, [2] interactions: PP+PC and CP+CC in one
+ *   kernel launch (after zeroing the proxy potentials), [3] L2L, [4] L2P+scatter.
  */
 int csfmm_plan_timing(csfmm_plan_t plan, int enable);
-int csfmm_plan_timing_read(csfmm_plan_t plan, double* stage_ms /*[6]*/, int64_t* n_evals);
+int csfmm_plan_timing_read(csfmm_plan_t plan, double* stage_ms /*[5]*/, int64_t* n_evals);
 
 /* Upper estimate of the device bytes a plan of these sizes holds (for
  * admission control); -1 on bad arguments. */

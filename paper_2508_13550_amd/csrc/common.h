@@ -141,19 +141,29 @@ struct Batch {
     int32_t a0[kMaxBatch];          // M2M / L2L: first parent of the level in `parents`
     int32_t a1[kMaxBatch];          // M2M / L2L: number of parents at the level
     int32_t prefix[kMaxBatch + 1];
+    int32_t prefix2[kMaxBatch + 1];  // tile launches: far-field blocks after the near-field ones
 };
 
-__device__ __forceinline__ void batch_locate(const Batch& b, int blk, int& r, int& local) {
-    int lo = 0, hi = b.n - 1;
+__device__ __forceinline__ void prefix_locate(const int32_t* prefix, int n, int blk, int& r,
+                                              int& local) {
+    int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (b.prefix[mid] <= blk)
+        if (prefix[mid] <= blk)
             lo = mid;
         else
             hi = mid - 1;
     }
     r = lo;
-    local = blk - b.prefix[lo];
+    local = blk - prefix[lo];
+}
+
+__device__ __forceinline__ void batch_locate(const Batch& b, int blk, int& r, int& local) {
+    prefix_locate(b.prefix, b.n, blk, r, local);
+}
+
+__device__ __forceinline__ void batch_locate2(const Batch& b, int blk, int& r, int& local) {
+    prefix_locate(b.prefix2, b.n, blk, r, local);
 }
 
 }  // namespace csfmm
@@ -180,12 +190,12 @@ struct csfmm_plan_s {
     csfmm_workspace_s* ws0 = nullptr;
     // optional per-stage timing with HIP events (ring of event sets)
     struct Timing {
-        static constexpr int kStages = 6;  // P2M, M2M, near, far, L2L, L2P
+        static constexpr int kStages = 5;  // P2M, M2M, interactions (PP+PC+CP+CC), L2L, L2P
         static constexpr int kSlots = 32;
         bool on = false;
         std::vector<hipEvent_t> ev;  // [kSlots][kStages + 1]
         std::vector<int> pending;    // slot recorded and not yet read
-        double sum_ms[kStages] = {0, 0, 0, 0, 0, 0};
+        double sum_ms[kStages] = {0, 0, 0, 0, 0};
         int64_t n = 0;
         int next = 0;
     } timing;
@@ -243,7 +253,7 @@ int run_eval(csfmm_plan_s* P, int kernel, const double* weights, double* out, do
              double* psi_out, double* near_out, hipStream_t s);
 
 // ---- tile engine (tile.hip): b holds requests of one kernel and form
-int launch_tile_batch(const Batch& b, int kernel, bool fp32, bool far, hipStream_t s);
+int launch_tile_batch(const Batch& b, int kernel, bool fp32, hipStream_t s);
 int launch_direct(const double* tgt, int64_t nt, const double* src, int64_t ns, const double* w,
                   int kernel, bool fp32, double* out, hipStream_t s);
 

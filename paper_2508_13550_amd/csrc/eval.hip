@@ -49,25 +49,6 @@ __global__ __launch_bounds__(256) void k_zero_psi(Batch b) {
     if (k < int64_t(b.vd[r]) * V.psi_stride) V.psi[k] = 0.0;
 }
 
-// Barycentric values L_0..L_p at x (§4, eq. barycentric), exact hit -> delta.
-__device__ __forceinline__ void bary_row(int p, const double* s, const double* beta, double x,
-                                         double* L) {
-    int hit = -1;
-    double den = 0.0;
-    for (int k = 0; k <= p; ++k) {
-        const double d = x - s[k];
-        if (d == 0.0) hit = k;
-        L[k] = beta[k] / d;
-        den += L[k];
-    }
-    if (hit >= 0) {
-        for (int k = 0; k <= p; ++k) L[k] = (k == hit) ? 1.0 : 0.0;
-    } else {
-        const double inv = 1.0 / den;
-        for (int k = 0; k <= p; ++k) L[k] *= inv;
-    }
-}
-
 __device__ __forceinline__ void cheb_setup(int p, double* s, double* beta) {
     for (int k = threadIdx.x; k <= p; k += blockDim.x) {
         s[k] = cheb(k, p);
@@ -77,46 +58,103 @@ __device__ __forceinline__ void cheb_setup(int p, double* s, double* beta) {
     }
 }
 
-// e2 P2M: wbar_k(leaf) = sum_j L_k1(u_j) L_k2(v_j) w_j (eq. PC, §6); one source leaf per block
-constexpr int kP2MThreads = 128;
-__global__ __launch_bounds__(kP2MThreads) void k_p2m(Batch b) {
-    __shared__ double s[kMaxP1], beta[kMaxP1];
-    __shared__ double Lu[kP2MThreads][kMaxP1 + 1];
-    __shared__ double Lv[kP2MThreads][kMaxP1 + 1];
-    __shared__ double wv[kP2MThreads];
+// FP64 reciprocal: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Barycentric row L_0..L_{P1-1} at x in registers (§4, eq. barycentric);
+// an exact node hit gives the Kronecker delta.
+template <int P1>
+__device__ __forceinline__ void bary_regs(const double* s, const double* beta, double x,
+                                          double (&L)[P1]) {
+    int hit = -1;
+    double den = 0.0;
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+        const double d = x - s[k];
+        hit = (d == 0.0) ? k : hit;
+        L[k] = beta[k] * rcp64(d);
+        den += L[k];
+    }
+    const double inv = rcp64(den);
+#pragma unroll
+    for (int k = 0; k < P1; ++k) L[k] = hit >= 0 ? (k == hit ? 1.0 : 0.0) : L[k] * inv;
+}
+
+// e2 P2M: wbar_k(leaf) = sum_j L_k1(u_j) L_k2(v_j) w_j (eq. PC, §6), one wave
+// per source leaf.  Each lane builds the rows of one point in registers and
+// stores L1 and w L2 in LDS; then, as a matrix product over the points,
+//   Wbar[k1][k2] = sum_j L1[j][k1] (w_j L2[j][k2]),
+// runs on FP64 MFMA 16x16x4 (16-wide proxy-index tiles, 4 points per step).
+template <int P1>
+__global__ __launch_bounds__(64) void k_p2m(Batch b) {
+    constexpr int NT = (P1 + 15) / 16;
+    __shared__ double s[P1], beta[P1];
+    __shared__ double Lu[64][P1];
+    __shared__ double Lw[64][P1];
+    const int lane = threadIdx.x;
     int r, local;
     locate(b, r, local);
     const ReqView& V = *b.v[r];
     const int c = V.s_leaves[local];
     const int bgn = V.s_begin[c], m = V.s_count[c];
-    const int p = V.p, P1 = p + 1, K = P1 * P1, KS = V.KS;
-    cheb_setup(p, s, beta);
+    const int KS = V.KS;
+    cheb_setup(P1 - 1, s, beta);
+    double4_t acc[NT][NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+    const int kq = lane >> 4, l16 = lane & 15;
     __syncthreads();
-    double acc[3] = {0.0, 0.0, 0.0};  // K <= 3 * kP2MThreads
-    for (int j0 = 0; j0 < m; j0 += kP2MThreads) {
-        const int nj = min(kP2MThreads, m - j0);
-        if (threadIdx.x < nj) {
-            const int j = bgn + j0 + threadIdx.x;
-            bary_row(p, s, beta, V.s_u[j], Lu[threadIdx.x]);
-            bary_row(p, s, beta, V.s_v[j], Lv[threadIdx.x]);
-            wv[threadIdx.x] = V.ws[j];
+    for (int j0 = 0; j0 < m; j0 += 64) {
+        const int j = j0 + lane;
+        double L1[P1], L2[P1];
+        double wj = 0.0;
+        if (j < m) {
+            bary_regs<P1>(s, beta, V.s_u[bgn + j], L1);
+            bary_regs<P1>(s, beta, V.s_v[bgn + j], L2);
+            wj = V.ws[bgn + j];
+        } else {
+#pragma unroll
+            for (int k = 0; k < P1; ++k) L1[k] = L2[k] = 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < P1; ++k) {
+            Lu[lane][k] = L1[k];
+            Lw[lane][k] = wj * L2[k];
         }
         __syncthreads();
-        for (int q = 0; q < 3; ++q) {
-            const int k = threadIdx.x + q * kP2MThreads;
-            if (k < K) {
-                const int k1 = k / P1, k2 = k % P1;
-                double a = acc[q];
-                for (int j = 0; j < nj; ++j) a += Lu[j][k1] * Lv[j][k2] * wv[j];
-                acc[q] = a;
+        const int steps = min(64, m - j0);
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < NT; ++tj) {
+                const int ka = ti * 16 + l16, kb = tj * 16 + l16;
+                for (int kk = 0; kk < steps; kk += 4) {
+                    const double av = ka < P1 ? Lu[kk + kq][ka] : 0.0;
+                    const double bv = kb < P1 ? Lw[kk + kq][kb] : 0.0;
+                    acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ti][tj], 0, 0, 0);
+                }
             }
-        }
         __syncthreads();
     }
-    for (int q = 0; q < 3; ++q) {
-        const int k = threadIdx.x + q * kP2MThreads;
-        if (k < KS) V.wbar[int64_t(c) * KS + k] = (k < K) ? acc[q] : 0.0;
-    }
+    double* wb = V.wbar + int64_t(c) * KS;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k1 = ti * 16 + kq + 4 * i, k2 = tj * 16 + l16;
+                if (k1 < P1 && k2 < P1) wb[k1 * P1 + k2] = acc[ti][tj][i];
+            }
+    for (int k = P1 * P1 + lane; k < KS; k += 64) wb[k] = 0.0;
 }
 
 // Batched small GEMMs on FP64 MFMA (v_mfma_f64_16x16x4f64) for the fixed
@@ -209,55 +247,58 @@ __global__ __launch_bounds__(256) void k_mfma_pass(Batch b) {
     }
 }
 
-// e7+e8: L2P (eq. downward_1 at the leaves) + near field + scatter to caller
-// order; one target leaf per block; VD output components (every request of
-// the launch has the same VD).
-constexpr int kL2PThreads = 128;
-template <int VD>
-__global__ __launch_bounds__(kL2PThreads) void k_l2p(Batch b) {
-    __shared__ double s[kMaxP1], beta[kMaxP1];
-    __shared__ double ps[VD][kMaxP1 * kMaxP1 + 4];
-    __shared__ double Lu[kL2PThreads][kMaxP1 + 1];
-    __shared__ double Lv[kL2PThreads][kMaxP1 + 1];
+// e7+e8: L2P (eq. downward_1 at the leaves) + near field + scatter to the
+// caller's order; one target leaf per block, one point per thread, the
+// Lagrange rows in registers and the leaf's proxy potentials in LDS; VD output
+// components (all requests of a launch have the same VD).
+template <int VD, int P1>
+__global__ __launch_bounds__(64) void k_l2p(Batch b) {
+    __shared__ double s[P1], beta[P1];
+    __shared__ double ps[VD][P1 * P1];
     int r, local;
     locate(b, r, local);
     const ReqView& V = *b.v[r];
-    constexpr int vd = VD;
     double* out = b.out[r];
     const int c = V.t_leaves[local];
     const int bgn = V.t_begin[c], m = V.t_count[c];
-    if (m == 0) return;
-    const int p = V.p, P1 = p + 1, K = P1 * P1, KS = V.KS;
-    cheb_setup(p, s, beta);
-    for (int k = threadIdx.x; k < K; k += blockDim.x)
-        for (int d = 0; d < vd; ++d) ps[d][k] = V.psi[d * V.psi_stride + int64_t(c) * KS + k];
+    if (m == 0) return;  // the whole block leaves
+    const int KS = V.KS;
+    cheb_setup(P1 - 1, s, beta);
+    for (int k = threadIdx.x; k < P1 * P1; k += blockDim.x)
+#pragma unroll
+        for (int d = 0; d < VD; ++d) ps[d][k] = V.psi[d * V.psi_stride + int64_t(c) * KS + k];
     __syncthreads();
-    for (int j0 = 0; j0 < m; j0 += kL2PThreads) {
+    for (int j0 = 0; j0 < m; j0 += blockDim.x) {
         const int jj = j0 + threadIdx.x;
-        if (jj < m) {
-            const int j = bgn + jj;
-            double* L1 = Lu[threadIdx.x];
-            double* L2 = Lv[threadIdx.x];
-            bary_row(p, s, beta, V.t_u[j], L1);
-            bary_row(p, s, beta, V.t_v[j], L2);
-            double acc[VD];
+        if (jj >= m) continue;
+        const int j = bgn + jj;
+        double L1[P1], L2[P1];
+        bary_regs<P1>(s, beta, V.t_u[j], L1);
+        bary_regs<P1>(s, beta, V.t_v[j], L2);
+        double acc[VD];
 #pragma unroll
-            for (int d = 0; d < VD; ++d) acc[d] = 0.0;
-            for (int n1 = 0; n1 < P1; ++n1) {
-                double inner[VD];
+        for (int d = 0; d < VD; ++d) acc[d] = 0.0;
+#pragma unroll 1
+        for (int n1 = 0; n1 < P1; ++n1) {
+            double inner[VD];
 #pragma unroll
-                for (int d = 0; d < VD; ++d) inner[d] = 0.0;
-                for (int n2 = 0; n2 < P1; ++n2) {
-                    const double l2 = L2[n2];
-                    for (int d = 0; d < vd; ++d) inner[d] += ps[d][n1 * P1 + n2] * l2;
-                }
-                for (int d = 0; d < vd; ++d) acc[d] += L1[n1] * inner[d];
-            }
-            const int64_t o = V.t_perm[j];
-            for (int d = 0; d < vd; ++d) out[o * vd + d] = V.phinear[d * V.nt + j] + acc[d];
+            for (int d = 0; d < VD; ++d) inner[d] = 0.0;
+#pragma unroll
+            for (int n2 = 0; n2 < P1; ++n2)
+#pragma unroll
+                for (int d = 0; d < VD; ++d) inner[d] = fma(ps[d][n1 * P1 + n2], L2[n2], inner[d]);
+#pragma unroll
+            for (int d = 0; d < VD; ++d) acc[d] = fma(L1[n1], inner[d], acc[d]);
         }
+        const int64_t o = V.t_perm[j];
+#pragma unroll
+        for (int d = 0; d < VD; ++d) out[o * VD + d] = V.phinear[d * V.nt + j] + acc[d];
     }
 }
+
+// Degrees p = 1..16 as P1 = p + 1 template arguments.
+#define CSFMM_P1_CASES(X) \
+    X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17)
 
 __global__ void k_scatter_near(const double* __restrict__ near, int64_t nt, int vd,
                                const int32_t* __restrict__ perm, double* __restrict__ out) {
@@ -348,7 +389,24 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
     for (int r = 0; r < n; ++r) blk[r] = (reqs[r].plan->ns + 255) / 256;
     RCX(launch_batched(b, blk, [&](unsigned g) { k_gather_w<<<g, 256, 0, s>>>(b); }));
     for (int r = 0; r < n; ++r) blk[r] = reqs[r].plan->st->nleaves;
-    RCX(launch_batched(b, blk, [&](unsigned g) { k_p2m<<<g, kP2MThreads, 0, s>>>(b); }));
+    // grouped by degree (P1 is a template parameter)
+    for (int P1 = 2; P1 <= kMaxP1; ++P1) {
+        bool any = false;
+        for (int r = 0; r < n; ++r) {
+            blk[r] = reqs[r].plan->p + 1 == P1 ? reqs[r].plan->st->nleaves : 0;
+            any = any || blk[r] > 0;
+        }
+        if (!any) continue;
+        switch (P1) {
+#define X(Q)                                                                                   \
+    case Q:                                                                                    \
+        RCX(launch_batched(b, blk, [&](unsigned g) { k_p2m<Q><<<g, 64, 0, s>>>(b); }));    \
+        break;
+            CSFMM_P1_CASES(X)
+#undef X
+            default: break;
+        }
+    }
     RCX(mark(1));
     // e3 M2M, deepest parents first
     int maxd = 0;
@@ -363,41 +421,42 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         }
         RCX(launch_batched(b, blk, [&](unsigned g) { k_mfma_pass<0><<<g, 256, 0, s>>>(b); }));
     }
+    // zero the proxy potentials (CP + CC accumulate into them)
+    for (int r = 0; r < n; ++r)
+        blk[r] = (int64_t(b.vd[r]) * reqs[r].ws->dview_host.psi_stride + 255) / 256;
+    RCX(launch_batched(b, blk, [&](unsigned g) { k_zero_psi<<<g, 256, 0, s>>>(b); }));
     RCX(mark(2));
-    // e4 near field (PP + PC), one launch per (kernel, form) group
+    // e4+e5 interactions: PP + PC at the target particles and CP + CC into
+    // the proxy potentials, one launch per (kernel, form) group with the
+    // near-field blocks first and the far-field blocks after them
     std::map<std::pair<int, int>, std::vector<int>> groups;
     for (int r = 0; r < n; ++r)
         groups[{reqs[r].kernel, (reqs[r].plan->flags & CSFMM_FP32_FORM) ? 1 : 0}].push_back(r);
-    auto sub_batch = [&](const std::vector<int>& idx, bool far) -> int {
+    for (auto& kv : groups) {
+        const std::vector<int>& idx = kv.second;
         Batch g{};
         g.n = int(idx.size());
-        int64_t gb[kMaxBatch];
+        int64_t tn = 0, tf = 0;
         for (int q = 0; q < g.n; ++q) {
             const int r = idx[q];
             g.v[q] = b.v[r];
             g.w[q] = b.w[r];
             g.out[q] = b.out[r];
             g.vd[q] = b.vd[r];
-            gb[q] = far ? reqs[r].plan->lists.n_far_targets : reqs[r].plan->tt.nleaves;
+            g.prefix[q] = int32_t(tn);
+            g.prefix2[q] = int32_t(tf);
+            tn += reqs[r].plan->tt.nleaves;
+            tf += reqs[r].plan->lists.n_far_targets;
         }
-        int64_t tot = 0;
-        for (int q = 0; q < g.n; ++q) {
-            g.prefix[q] = int32_t(tot);
-            tot += gb[q];
+        g.prefix[g.n] = int32_t(tn);
+        g.prefix2[g.n] = int32_t(tf);
+        if (tn + tf > (int64_t(1) << 31) - 1) {
+            set_error("interaction launch too large");
+            return CSFMM_E_INVALID;
         }
-        g.prefix[g.n] = int32_t(tot);
-        const int kern = reqs[idx[0]].kernel;
-        const bool f32 = (reqs[idx[0]].plan->flags & CSFMM_FP32_FORM) != 0;
-        return launch_tile_batch(g, kern, f32, far, s);
-    };
-    for (auto& kv : groups) RCX(sub_batch(kv.second, false));
+        RCX(launch_tile_batch(g, kv.first.first, kv.first.second != 0, s));
+    }
     RCX(mark(3));
-    // e5 far field (CP + CC) into zeroed proxy potentials
-    for (int r = 0; r < n; ++r)
-        blk[r] = (int64_t(b.vd[r]) * reqs[r].ws->dview_host.psi_stride + 255) / 256;
-    RCX(launch_batched(b, blk, [&](unsigned g) { k_zero_psi<<<g, 256, 0, s>>>(b); }));
-    for (auto& kv : groups) RCX(sub_batch(kv.second, true));
-    RCX(mark(4));
     // e6 L2L, root level first
     int maxt = 0;
     for (int r = 0; r < n; ++r) maxt = std::max(maxt, int(reqs[r].plan->tt.depth));
@@ -411,22 +470,31 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         }
         RCX(launch_batched(b, blk, [&](unsigned g) { k_mfma_pass<1><<<g, 256, 0, s>>>(b); }));
     }
-    RCX(mark(5));
+    RCX(mark(4));
     // e7+e8 L2P, near field and scatter to the caller's order; one launch per
     // number of output components (blocks of the other group are empty)
-    for (int vdl : {1, 3}) {
-        bool any = false;
-        for (int r = 0; r < n; ++r) {
-            blk[r] = b.vd[r] == vdl ? reqs[r].plan->tt.nleaves : 0;
-            any = any || blk[r] > 0;
+    for (int vdl : {1, 3})
+        for (int P1 = 2; P1 <= kMaxP1; ++P1) {
+            bool any = false;
+            for (int r = 0; r < n; ++r) {
+                blk[r] = (b.vd[r] == vdl && reqs[r].plan->p + 1 == P1) ? reqs[r].plan->tt.nleaves : 0;
+                any = any || blk[r] > 0;
+            }
+            if (!any) continue;
+            switch (P1) {
+#define X(Q)                                                                                       \
+    case Q:                                                                                        \
+        if (vdl == 1)                                                                              \
+            RCX(launch_batched(b, blk, [&](unsigned g) { k_l2p<1, Q><<<g, 64, 0, s>>>(b); }));  \
+        else                                                                                       \
+            RCX(launch_batched(b, blk, [&](unsigned g) { k_l2p<3, Q><<<g, 64, 0, s>>>(b); }));  \
+        break;
+                CSFMM_P1_CASES(X)
+#undef X
+                default: break;
+            }
         }
-        if (!any) continue;
-        if (vdl == 1)
-            RCX(launch_batched(b, blk, [&](unsigned g) { k_l2p<1><<<g, kL2PThreads, 0, s>>>(b); }));
-        else
-            RCX(launch_batched(b, blk, [&](unsigned g) { k_l2p<3><<<g, kL2PThreads, 0, s>>>(b); }));
-    }
-    RCX(mark(6));
+    RCX(mark(5));
 #undef RCX
     return CSFMM_OK;
 }

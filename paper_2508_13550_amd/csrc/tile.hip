@@ -226,20 +226,27 @@ __device__ __forceinline__ void run_group(const Stage<F32>& L, int base, int nj,
     }
 }
 
+template <int KERN, bool F32>
+struct TileSmem {
+    Stage<F32> L[1];
+    int e_code[kMaxEntries];
+    int e_pref[kMaxEntries + 1];
+    int lw[4];
+    double red[vdim<KERN>()][kThreads];
+};
+
+// One target cell of one request: near field (TPROX = false) or far field.
 template <int KERN, bool F32, bool TPROX>
-__global__ __launch_bounds__(kThreads) void k_tile(Batch b) {
+__device__ __forceinline__ void tile_body(const ReqView& V, int local, TileSmem<KERN, F32>& sm) {
     using R = Real<F32>;
     constexpr int VD = vdim<KERN>();
     constexpr double scale = coord_scale<KERN>();
-    __shared__ Stage<F32> L[2];
-    __shared__ int e_code[kMaxEntries];
-    __shared__ int e_pref[kMaxEntries + 1];
-    __shared__ int lw[4];
-    __shared__ double red[VD][kThreads];
-
-    int req, local;
-    batch_locate(b, xcd_logical_block(blockIdx.x, gridDim.x), req, local);
-    const TileArgs a = tile_args<TPROX>(*b.v[req]);
+    Stage<F32>* L = sm.L;
+    int* e_code = sm.e_code;
+    int* e_pref = sm.e_pref;
+    int* lw = sm.lw;
+    auto& red = sm.red;
+    const TileArgs a = tile_args<TPROX>(V);
     const int T = a.tcells[local];
     const int tid = threadIdx.x;
     const double cx = a.tcenter[3 * T], cy = a.tcenter[3 * T + 1], cz = a.tcenter[3 * T + 2];
@@ -289,9 +296,7 @@ __global__ __launch_bounds__(kThreads) void k_tile(Batch b) {
 
         // Entries are processed in batches of up to kMaxEntries; inside a batch
         // the flattened sources split into the three forms (check, near, far)
-        // and each form into chunks of kChunk.  Chunks are double buffered in
-        // LDS: the global loads of chunk c+1 are in flight while chunk c is
-        // evaluated, with one barrier per chunk.
+        // and each form into chunks of at most kChunk staged through LDS.
         for (int ebase = 0; ebase < ne_all; ebase += kMaxEntries) {
             const int ne = min(kMaxEntries, ne_all - ebase);
             int sz = 0;
@@ -315,103 +320,73 @@ __global__ __launch_bounds__(kThreads) void k_tile(Batch b) {
             int bnd[4];
             bnd[0] = 0;
             bnd[3] = e_pref[kMaxEntries];
-            {
-                const int k1 = min(max(ph_hi[0] - ebase, 0), kMaxEntries);
-                const int k2 = min(max(ph_hi[1] - ebase, 0), kMaxEntries);
-                bnd[1] = e_pref[k1];
-                bnd[2] = e_pref[k2];
-            }
-            // chunk cursor: (form, start offset)
-            int ph = 0, q0 = 0;
-            while (ph < 3 && bnd[ph] >= bnd[ph + 1]) ++ph;
-            if (ph < 3) q0 = bnd[ph];
-            // prefetch registers: at most two real sources per thread per chunk
-            double ry[2][4];
-            auto fetch = [&](int cph, int cq0) {
-                const int nq = min(kChunk, bnd[cph + 1] - cq0);
-#pragma unroll
-                for (int r = 0; r < 2; ++r) {
-                    const int q = tid + r * kThreads;
-                    if (q < nq) {
-                        const int gq = cq0 + q;
-                        int lo = 0, hi = ne - 1;
-                        while (lo < hi) {
-                            const int mid = (lo + hi + 1) >> 1;
-                            if (e_pref[mid] <= gq)
-                                lo = mid;
-                            else
-                                hi = mid - 1;
+            bnd[1] = e_pref[min(max(ph_hi[0] - ebase, 0), kMaxEntries)];
+            bnd[2] = e_pref[min(max(ph_hi[1] - ebase, 0), kMaxEntries)];
+            for (int ph = 0; ph < 3; ++ph) {
+                for (int q0 = bnd[ph]; q0 < bnd[ph + 1]; q0 += kChunk) {
+                    const int nq = min(kChunk, bnd[ph + 1] - q0);
+                    const int Tj = (((nq + G - 1) / G) + kUnroll - 1) / kUnroll * kUnroll;
+                    const int npad = G * Tj;
+                    Stage<F32>& Lb = L[0];
+                    for (int q = tid; q < npad; q += kThreads) {
+                        double yx = 2.0, yy = 2.0, yz = 2.0, w = 0.0;  // padding: far, weightless
+                        if (q < nq) {
+                            const int gq = q0 + q;
+                            int lo = 0, hi = ne - 1;
+                            while (lo < hi) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if (e_pref[mid] <= gq)
+                                    lo = mid;
+                                else
+                                    hi = mid - 1;
+                            }
+                            const int o = gq - e_pref[lo];
+                            const int code = e_code[lo];
+                            if (code >= 0) {
+                                const int j = code + o;
+                                yx = a.sx[j];
+                                yy = a.sy[j];
+                                yz = a.sz[j];
+                                w = a.sw[j];
+                            } else {
+                                const int64_t sc = -(code + 1);
+                                const double* ps = a.sprox + sc * 3 * KS;
+                                yx = ps[o];
+                                yy = ps[KS + o];
+                                yz = ps[2 * KS + o];
+                                w = a.swbar[sc * KS + o];
+                            }
+                            yx = (yx - cx) * scale;
+                            yy = (yy - cy) * scale;
+                            yz = (yz - cz) * scale;
                         }
-                        const int o = gq - e_pref[lo];
-                        const int code = e_code[lo];
-                        if (code >= 0) {
-                            const int j = code + o;
-                            ry[r][0] = a.sx[j];
-                            ry[r][1] = a.sy[j];
-                            ry[r][2] = a.sz[j];
-                            ry[r][3] = a.sw[j];
+                        if constexpr (F32) {
+                            const float fx = float(yx), fy = float(yy), fz = float(yz);
+                            const float f2 =
+                                float(double(fx) * fx + double(fy) * fy + double(fz) * fz);
+                            Lb.p[q] = make_float4(fx, fy, fz, f2);
+                            Lb.w[q] = float(w);
                         } else {
-                            const int64_t sc = -(code + 1);
-                            const double* ps = a.sprox + sc * 3 * KS;
-                            ry[r][0] = ps[o];
-                            ry[r][1] = ps[KS + o];
-                            ry[r][2] = ps[2 * KS + o];
-                            ry[r][3] = a.swbar[sc * KS + o];
+                            Lb.p[q] = make_double4(yx, yy, yz, w);
                         }
                     }
-                }
-            };
-            if (ph < 3) fetch(ph, q0);
-            int buf = 0;
-            while (ph < 3) {
-                const int nq = min(kChunk, bnd[ph + 1] - q0);
-                const int Tj = (((nq + G - 1) / G) + kUnroll - 1) / kUnroll * kUnroll;
-                const int npad = G * Tj;
-                Stage<F32>& Lb = L[buf];
-                for (int q = tid; q < npad; q += kThreads) {
-                    double yx = 2.0, yy = 2.0, yz = 2.0, w = 0.0;  // padding: far, weightless
-                    if (q < nq) {
-                        const int r = q >= kThreads ? 1 : 0;
-                        yx = (ry[r][0] - cx) * scale;
-                        yy = (ry[r][1] - cy) * scale;
-                        yz = (ry[r][2] - cz) * scale;
-                        w = ry[r][3];
-                    }
-                    if constexpr (F32) {
-                        const float fx = float(yx), fy = float(yy), fz = float(yz);
-                        const float f2 = float(double(fx) * fx + double(fy) * fy + double(fz) * fz);
-                        Lb.p[q] = make_float4(fx, fy, fz, f2);
-                        Lb.w[q] = float(w);
-                    } else {
-                        Lb.p[q] = make_double4(yx, yy, yz, w);
-                    }
-                }
-                __syncthreads();
-                // advance the cursor and start the next chunk's loads
-                const int cph = ph;
-                q0 += nq;
-                if (q0 >= bnd[ph + 1]) {
-                    ++ph;
-                    while (ph < 3 && bnd[ph] >= bnd[ph + 1]) ++ph;
-                    if (ph < 3) q0 = bnd[ph];
-                }
-                if (ph < 3) fetch(ph, q0);
-                if (active) {
-                    R p[VD];
+                    __syncthreads();
+                    if (active) {
+                        R p[VD];
 #pragma unroll
-                    for (int v = 0; v < VD; ++v) p[v] = R(0);
-                    if (cph == 0)
-                        run_group<KERN, F32, FORM_CHECK>(Lb, g * Tj, Tj, TR, p);
-                    else if (cph == 1)
-                        run_group<KERN, F32, FORM_NEAR>(Lb, g * Tj, Tj, TR, p);
-                    else
-                        run_group<KERN, F32, FORM_FAR>(Lb, g * Tj, Tj, TR, p);
+                        for (int v = 0; v < VD; ++v) p[v] = R(0);
+                        if (ph == 0)
+                            run_group<KERN, F32, FORM_CHECK>(Lb, g * Tj, Tj, TR, p);
+                        else if (ph == 1)
+                            run_group<KERN, F32, FORM_NEAR>(Lb, g * Tj, Tj, TR, p);
+                        else
+                            run_group<KERN, F32, FORM_FAR>(Lb, g * Tj, Tj, TR, p);
 #pragma unroll
-                    for (int v = 0; v < VD; ++v) acc[v] += double(p[v]);
+                        for (int v = 0; v < VD; ++v) acc[v] += double(p[v]);
+                    }
+                    __syncthreads();
                 }
-                buf ^= 1;
             }
-            __syncthreads();
         }
 #pragma unroll
         for (int v = 0; v < VD; ++v) red[v][tid] = active ? acc[v] : 0.0;
@@ -429,6 +404,25 @@ __global__ __launch_bounds__(kThreads) void k_tile(Batch b) {
             for (int v = 0; v < VD; ++v) a.out[v * a.comp_stride + base] = o[v];
         }
         __syncthreads();
+    }
+}
+
+// Near-field blocks first (longest first), then far-field blocks, in one grid:
+// block b < prefix[n] is near-field work located by `prefix`, the others are
+// far-field work located by `prefix2`.  The occupancy hint keeps the FP32
+// instances at 80 VGPRs (6 waves per SIMD; measured faster than 5).
+template <int KERN, bool F32>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_tile(Batch b) {
+    __shared__ TileSmem<KERN, F32> sm;
+    const int blk = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int split = b.prefix[b.n];
+    int req, local;
+    if (blk < split) {
+        batch_locate(b, blk, req, local);
+        tile_body<KERN, F32, false>(*b.v[req], local, sm);
+    } else {
+        batch_locate2(b, blk - split, req, local);
+        tile_body<KERN, F32, true>(*b.v[req], local, sm);
     }
 }
 
@@ -579,18 +573,13 @@ __global__ void k_direct_reduce(const double* __restrict__ tgt, int64_t nt,
     for (int v = 0; v < VD; ++v) out[i * VD + v] = o[v];
 }
 
-template <int KERN, bool F32, bool TPROX>
+template <int KERN, bool F32>
 int launch_tile_t(const Batch& b, hipStream_t s) {
-    const int nblocks = b.prefix[b.n];
+    const int nblocks = b.prefix[b.n] + b.prefix2[b.n];
     if (nblocks <= 0) return CSFMM_OK;
-    k_tile<KERN, F32, TPROX><<<nblocks, kThreads, 0, s>>>(b);
+    k_tile<KERN, F32><<<nblocks, kThreads, 0, s>>>(b);
     CSFMM_LAUNCH_CHECK();
     return CSFMM_OK;
-}
-
-template <int KERN, bool F32>
-int launch_tile_k(const Batch& b, bool far, hipStream_t s) {
-    return far ? launch_tile_t<KERN, F32, true>(b, s) : launch_tile_t<KERN, F32, false>(b, s);
 }
 
 template <int KERN, bool F32>
@@ -621,14 +610,14 @@ int launch_direct_t(const double* tgt, int64_t nt, const double* src, int64_t ns
 
 }  // namespace
 
-int launch_tile_batch(const Batch& b, int kernel, bool fp32, bool far, hipStream_t s) {
+int launch_tile_batch(const Batch& b, int kernel, bool fp32, hipStream_t s) {
     switch (kernel) {
         case CSFMM_K_POISSON_LOG:
-            return fp32 ? launch_tile_k<1, true>(b, far, s) : launch_tile_k<1, false>(b, far, s);
+            return fp32 ? launch_tile_t<1, true>(b, s) : launch_tile_t<1, false>(b, s);
         case CSFMM_K_BIOT_SAVART:
-            return fp32 ? launch_tile_k<2, true>(b, far, s) : launch_tile_k<2, false>(b, far, s);
+            return fp32 ? launch_tile_t<2, true>(b, s) : launch_tile_t<2, false>(b, s);
         case CSFMM_K_INV_DIST:
-            return fp32 ? launch_tile_k<3, true>(b, far, s) : launch_tile_k<3, false>(b, far, s);
+            return fp32 ? launch_tile_t<3, true>(b, s) : launch_tile_t<3, false>(b, s);
         default:
             set_error("unknown kernel id %d", kernel);
             return CSFMM_E_INVALID;
