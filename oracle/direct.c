@@ -17,8 +17,21 @@
  *   1  Poisson log (paper eq. G_L):      -(1/4pi) ln(1 - x.y)
  *   2  Biot-Savart (paper eq. K_BS):     -(1/4pi) (x cross y) / (1 - x.y)   (3 outputs)
  *   3  inverse distance (the 1/gamma term of paper eq. G_SAL_approx): 1/|x-y|
+ *   4  biharmonic (paper eq. G_B):       (1/4pi) dilog((1 + x.y)/2)
+ *   5  SAL closed form (paper eq. G_SAL_approx):
+ *        (3 rw/(4 pi re)) ((1 - b0)/gamma - (a1 - b1) ln(gamma/2 + gamma^2/4)),
+ *        gamma = |x-y|, a1 = -2.7, b0 = -6.21196, b1 = 6.1 (§2.5), and the
+ *        density ratio rw/re = 1025/5514 (seawater over mean Earth density;
+ *        the paper names the ratio without a number).
  * 1 - x.y is evaluated as |x-y|^2/2, which is the same number on the sphere
- * and keeps its relative accuracy for close pairs.
+ * and keeps its relative accuracy for close pairs; likewise the dilogarithm's
+ * argument u = (1 + x.y)/2 is carried as 1 - u = |x-y|^2/4.
+ *
+ * dilog(u) = -int_0^u ln(1-t)/t dt (§2.4) is summed from its power series
+ * sum_k u^k/k^2 (integrate the series of -ln(1-t)/t term by term) when
+ * u <= 1/2, and through Euler's reflection formula
+ * dilog(u) = pi^2/6 - ln(u) ln(1-u) - dilog(1-u) when u > 1/2, so the series
+ * argument never exceeds 1/2.
  *
  * Loop: OpenMP over targets, sources in ascending order, one plain FP64 sum
  * per target.  No blocking, no reordering, no fast-math.
@@ -31,6 +44,34 @@
 #endif
 
 #define ORACLE_PI 3.14159265358979323846
+#define SAL_A1 (-2.7)
+#define SAL_B0 (-6.21196)
+#define SAL_B1 6.1
+#define SAL_RHO_RATIO (1025.0 / 5514.0)
+
+/* sum_{k>=1} x^k / k^2 for 0 <= x <= 1/2, summed until the terms stop
+ * changing the sum. */
+static double dilog_series(double x)
+{
+    double sum = 0.0, xk = 1.0;
+    for (int k = 1; k < 200; ++k) {
+        xk *= x;
+        double term = xk / ((double)k * (double)k);
+        double next = sum + term;
+        if (next == sum) break;
+        sum = next;
+    }
+    return sum;
+}
+
+/* dilog(u) for u = 1 - v, 0 <= v <= 1. */
+static double dilog_one_minus(double v)
+{
+    double u = 1.0 - v;
+    if (u <= 0.5) return dilog_series(u);
+    if (v == 0.0) return ORACLE_PI * ORACLE_PI / 6.0;
+    return ORACLE_PI * ORACLE_PI / 6.0 - log1p(-v) * log(v) - dilog_series(v);
+}
 
 static double half_dist2(const double* x, const double* y)
 {
@@ -57,7 +98,7 @@ int oracle_max_threads(void)
 int oracle_direct(int kernel, const double* tgt, int64_t nt, const double* src,
                   int64_t ns, const double* w, double* out, int nthreads)
 {
-    if (nt < 0 || ns < 0 || kernel < 1 || kernel > 3) return -1;
+    if (nt < 0 || ns < 0 || kernel < 1 || kernel > 5) return -1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -93,10 +134,19 @@ int oracle_direct(int kernel, const double* tgt, int64_t nt, const double* src,
                 if (same_point(x, y)) continue;
                 double d = half_dist2(x, y);
                 double k;
-                if (kernel == 1)
+                if (kernel == 1) {
                     k = -c * log(d);
-                else
+                } else if (kernel == 3) {
                     k = 1.0 / sqrt(2.0 * d);
+                } else if (kernel == 4) {
+                    double v = 0.5 * d; /* 1 - (1 + x.y)/2 */
+                    if (v > 1.0) v = 1.0;
+                    k = c * dilog_one_minus(v);
+                } else {
+                    double g = sqrt(2.0 * d); /* gamma = |x - y| */
+                    k = 3.0 * SAL_RHO_RATIO * c *
+                        ((1.0 - SAL_B0) / g - (SAL_A1 - SAL_B1) * log(0.5 * g + 0.25 * g * g));
+                }
                 acc += k * w[j];
             }
             out[i] = acc;

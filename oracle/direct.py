@@ -44,7 +44,8 @@ def oracle_threads():
 def direct(kernel, targets, sources, weights, nthreads=0):
     """phi_i = sum_j K(x_i, y_j) w_j in FP64, exact coincidences omitted.
 
-    kernel: 1 Poisson log, 2 Biot-Savart (returns [Nt,3]), 3 1/|x-y|.
+    kernel: 1 Poisson log, 2 Biot-Savart (returns [Nt,3]), 3 1/|x-y|,
+    4 biharmonic, 5 SAL closed form.
     """
     lib = _load()
     t = np.ascontiguousarray(targets, dtype=np.float64)

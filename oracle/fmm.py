@@ -67,6 +67,13 @@ FACE_FRAMES = np.array([
 KERNEL_POISSON = 1
 KERNEL_BIOT_SAVART = 2
 KERNEL_INV_DIST = 3
+KERNEL_BIHARMONIC = 4
+KERNEL_SAL = 5
+
+# eq. (G_SAL_approx): Load Love number fit k'_n ~ a1/n, h'_n ~ b0 + b1/n (§2.5)
+SAL_A1, SAL_B0, SAL_B1 = -2.7, -6.21196, 6.1
+# seawater over mean Earth density; the paper names the ratio, not its value
+SAL_RHO_RATIO = 1025.0 / 5514.0
 
 
 # ---------------------------------------------------------------- kernels
@@ -76,6 +83,10 @@ def kernel_matrix(kernel, X, Y):
 
     Poisson (eq. G_L): -(1/4pi) ln(1 - x.y).  Biot-Savart (eq. K_BS):
     -(1/4pi) (x cross y)/(1 - x.y), shape [M,N,3].  Inverse distance: 1/|x-y|.
+    Biharmonic (eq. G_B): (1/4pi) dilog((1 + x.y)/2), with SciPy's Spence
+    function spence(z) = dilog(1 - z) taken at z = 1 - (1 + x.y)/2 = |x-y|^2/4.
+    SAL (eq. G_SAL_approx): (3 rw/(4 pi re)) ((1 - b0)/g - (a1 - b1)
+    ln(g/2 + g^2/4)), g = |x-y|.
     """
     X = np.asarray(X, dtype=np.float64)
     Y = np.asarray(Y, dtype=np.float64)
@@ -88,6 +99,15 @@ def kernel_matrix(kernel, X, Y):
         K[same] = 0.0
     elif kernel == KERNEL_INV_DIST:
         K = 1.0 / np.sqrt(2.0 * dd)
+        K[same] = 0.0
+    elif kernel == KERNEL_BIHARMONIC:
+        from scipy.special import spence
+        K = spence(np.minimum(0.5 * d, 1.0)) / (4.0 * np.pi)
+        K[same] = 0.0
+    elif kernel == KERNEL_SAL:
+        g = np.sqrt(2.0 * dd)
+        K = (3.0 * SAL_RHO_RATIO / (4.0 * np.pi)) * (
+            (1.0 - SAL_B0) / g - (SAL_A1 - SAL_B1) * np.log(0.5 * g + 0.25 * g * g))
         K[same] = 0.0
     elif kernel == KERNEL_BIOT_SAVART:
         C = np.cross(X[:, None, :], Y[None, :, :])

@@ -165,17 +165,21 @@ def test_upward_moments():
 
 # --------------------------------------------------------------- whole method
 
-@pytest.mark.parametrize("kernel", [1, 2, 3])
+@pytest.mark.parametrize("kernel", [1, 2, 3, 4, 5])
 def test_degenerate_cases_equal_direct(kernel):
     P, A = cubed_sphere_grid(8)
     w = real_y41(P) * A
     ref = direct(kernel, P, P, w)
+    # the smooth biharmonic kernel against a zero-mean field cancels to about
+    # 1e-3 of sum |G w|, which magnifies rounding (and SciPy's dilogarithm
+    # against the C oracle's series) by as much
+    tol = 1e-13 if kernel == 4 else 1e-14
     # MAC -> 0: nothing is well separated, every pair is PP
     got = F.fmm(P, None, w, kernel, 4, 1e-9, 16)
-    assert rel_l2(got, ref) < 1e-14
+    assert rel_l2(got, ref) < tol
     # leaf size >= N: the six roots are leaves, every pair is PP
     got = F.fmm(P, None, w, kernel, 4, 0.7, P.shape[0])
-    assert rel_l2(got, ref) < 1e-14
+    assert rel_l2(got, ref) < tol
 
 
 def test_config1_against_direct_and_exact():
@@ -223,7 +227,7 @@ def test_cube_rotation_symmetry():
         assert rel_l2(b, a) < 1e-13           # and it is the same after the turn
 
 
-@pytest.mark.parametrize("kernel", [1, 2, 3])
+@pytest.mark.parametrize("kernel", [1, 2, 3, 4, 5])
 def test_distinct_sets_and_sampling(kernel):
     P, A = cubed_sphere_grid(16)
     X = random_sphere_points(1500, 12)
@@ -235,4 +239,6 @@ def test_distinct_sets_and_sampling(kernel):
     assert rel_l2(full, ref) < 1e-6
     sample = np.array([0, 3, 10, 999, 1499])
     part = fm.evaluate(w, sample=sample)
-    assert np.max(np.abs(part - full[sample])) <= 1e-15 * np.max(np.abs(full))
+    # (biharmonic: cancellation, as in test_degenerate_cases_equal_direct)
+    tol = 1e-14 if kernel == 4 else 1e-15
+    assert np.max(np.abs(part - full[sample])) <= tol * np.max(np.abs(full))

@@ -11,7 +11,14 @@ and the mathematics fix (no GPU).
   (kernel_Legendre) (Funk-Hecke), first order because of the omitted
   singular cell;
 * Biot-Savart: K_BS = grad G_L x x (§2.3) gives u = grad(psi) x x;
-* symmetry of the kernels; 50-digit brute force with the literal formulas.
+* symmetry of the kernels; 50-digit brute force with the literal formulas;
+* biharmonic (eq. G_B): Legendre coefficients 1/(n^2 (n+1)^2) (the
+  eigenvalues of the biharmonic operator, §2.4) and pi^2/6 - 1 for n = 0,
+  by Funk-Hecke quadrature of the oracle's kernel; closed-form dilogarithm
+  values; second order convergence of the eigenrelation on the grid;
+* SAL (eq. G_SAL_approx): Legendre coefficients (1 - b0) + (a1 - b1)/n of
+  the series eq. (G_SAL) with the Love number fit, i.e. the multipliers of
+  eq. (salsh), by the same quadrature.
 """
 
 import math
@@ -218,6 +225,13 @@ def _mp_direct(kernel, X, Y, w):
                 acc[0] += -mpmath.log(om) / (4 * mpmath.pi) * wm
             elif kernel == 3:
                 acc[0] += wm / mpmath.sqrt(2 * om)
+            elif kernel == 4:
+                acc[0] += mpmath.polylog(2, (1 + dot) / 2) / (4 * mpmath.pi) * wm
+            elif kernel == 5:
+                g = mpmath.sqrt(2 * om)
+                a1, b0, b1 = mpmath.mpf("-2.7"), mpmath.mpf("-6.21196"), mpmath.mpf("6.1")
+                c = 3 * mpmath.mpf(1025) / mpmath.mpf(5514) / (4 * mpmath.pi)
+                acc[0] += c * ((1 - b0) / g - (a1 - b1) * mpmath.log(g / 2 + g * g / 4)) * wm
             else:
                 cr = [xs[1] * ys[2] - xs[2] * ys[1], xs[2] * ys[0] - xs[0] * ys[2],
                       xs[0] * ys[1] - xs[1] * ys[0]]
@@ -228,7 +242,7 @@ def _mp_direct(kernel, X, Y, w):
     return out if kernel == 2 else out[:, 0]
 
 
-@pytest.mark.parametrize("kernel", [1, 2, 3])
+@pytest.mark.parametrize("kernel", [1, 2, 3, 4, 5])
 def test_P6_mpmath_brute_force(kernel):
     P, A = cubed_sphere_grid(2)
     X = random_sphere_points(40, 21)
@@ -245,3 +259,88 @@ def test_oracle_rejects_bad_kernel():
     P, A = cubed_sphere_grid(1)
     with pytest.raises(ValueError):
         direct(9, P, P, A)
+
+
+# ------------------------------------------- biharmonic and SAL kernels
+
+SAL_A1, SAL_B0, SAL_B1 = -2.7, -6.21196, 6.1
+SAL_RHO = 1025.0 / 5514.0
+
+
+def _kernel_profile(kernel, s):
+    """G(t) at t = 1 - 2 s^2 (|x - y| = 2 s) from the oracle, one pair per target."""
+    X = np.stack([2 * s * np.sqrt(1 - s * s), np.zeros_like(s), 1 - 2 * s * s], axis=1)
+    return direct(kernel, X, np.array([[0.0, 0.0, 1.0]]), np.ones(1))
+
+
+def _legendre_coeffs(kernel, nmax):
+    """lambda_n = 2 pi int_{-1}^{1} G(t) P_n(t) dt (Funk-Hecke), t = 1 - 2 s^2."""
+    xg, wg = np.polynomial.legendre.leggauss(40)
+    edges = [0.0, 1e-6, 1e-5, 1e-4, 1e-3, 1e-2, 0.05, 0.2, 0.5, 0.8, 1.0]
+    S, W = [], []
+    for a, b in zip(edges, edges[1:]):
+        S.append(0.5 * (b - a) * xg + 0.5 * (a + b))
+        W.append(0.5 * (b - a) * wg)
+    S, W = np.concatenate(S), np.concatenate(W)
+    G = _kernel_profile(kernel, S)
+    t = 1 - 2 * S * S
+    out = []
+    for n in range(nmax + 1):
+        Pn = np.polynomial.legendre.legval(t, [0] * n + [1])
+        out.append(2 * math.pi * np.sum(W * G * Pn * 4 * S))
+    return np.array(out)
+
+
+def test_P7_biharmonic_legendre_coefficients():
+    """Delta^2 Y_n = n^2 (n+1)^2 Y_n (§2.4): G_B has coefficients 1/(n^2 (n+1)^2)."""
+    lam = _legendre_coeffs(4, 8)
+    assert abs(lam[0] - (math.pi ** 2 / 6 - 1)) < 1e-13  # int_0^1 dilog(u) du
+    for n in range(1, 9):
+        ref = 1.0 / (n * n * (n + 1) ** 2)
+        assert abs(lam[n] - ref) <= 1e-11 * ref + 1e-15, (n, lam[n], ref)
+
+
+def test_P8_sal_legendre_coefficients():
+    """eq. (G_SAL) with k'_n = a1/n, h'_n = b0 + b1/n and eq. (Legendre):
+    coefficient of P_n is (3 rw/(4 pi re)) ((1 - b0) + (a1 - b1)/n), so the
+    convolution multiplier is (3 rw/re) ((1 - b0) + (a1 - b1)/n)/(2n + 1)
+    (eq. salsh with the fit), and (3 rw/re)(1 - b0) for n = 0."""
+    lam = _legendre_coeffs(5, 8)
+    assert abs(lam[0] - 3 * SAL_RHO * (1 - SAL_B0)) < 1e-12
+    for n in range(1, 9):
+        ref = 3 * SAL_RHO * ((1 - SAL_B0) + (SAL_A1 - SAL_B1) / n) / (2 * n + 1)
+        assert abs(lam[n] - ref) <= 1e-11 * abs(ref), (n, lam[n], ref)
+
+
+def test_P9_dilog_closed_form_values():
+    c = 1 / (4 * math.pi)
+    # x.y = 0: dilog(1/2) = pi^2/12 - ln(2)^2/2; antipodes: dilog(0) = 0
+    G = _kernel_profile(4, np.array([math.sqrt(0.5), 1.0]))
+    assert abs(G[0] - c * (math.pi ** 2 / 12 - math.log(2) ** 2 / 2)) < 1e-16
+    assert abs(G[1]) < 1e-17
+    # coincident limit pi^2/6 (continuous kernel), approached at |x-y| = 2e-8
+    G0 = _kernel_profile(4, np.array([1e-8]))
+    assert abs(G0[0] - c * math.pi ** 2 / 6) < 1e-14
+    # golden-ratio value dilog((3 - sqrt5)/2) = pi^2/15 - ln(phi)^2
+    phi = (1 + math.sqrt(5)) / 2
+    u = (3 - math.sqrt(5)) / 2          # (1 + t)/2 = u  ->  s^2 = 1 - u
+    Gu = _kernel_profile(4, np.array([math.sqrt(1 - u)]))
+    assert abs(Gu[0] - c * (math.pi ** 2 / 15 - math.log(phi) ** 2)) < 1e-15
+
+
+def test_P10_biharmonic_eigenrelation_on_grid():
+    """sum_j G_B(x_i, y_j) f_j A_j -> Y/(n^2(n+1)^2) for f = Y_2,1 (n = 2, 1/36),
+    second order: the omitted i = j term of a continuous kernel is O(A)."""
+    errs, fixed = [], []
+    for E in (8, 16, 32):
+        P, A = cubed_sphere_grid(E)
+        f = real_sph_harm_all(P, 2)[:, 5]   # a degree-2 harmonic
+        phi = direct(4, P, P, f * A)
+        ref = f / 36.0
+        errs.append(_rel_err(phi, ref, A, ref))
+        # adding back the omitted diagonal G_B(x,x) f_i A_i removes the leading term
+        fixed.append(_rel_err(phi + math.pi / 24 * f * A, ref, A, ref))
+    for a, b in zip(errs, errs[1:]):
+        assert 3.5 <= a / b <= 4.5, errs
+    assert all(x < 0.2 * e for x, e in zip(fixed, errs)), (fixed, errs)
+    assert fixed[-1] < 1e-3
