@@ -115,6 +115,34 @@ def run_form(cs, torch, T, W, N, p, fp32, theta, leaf, steps, warmup, S, ref_s):
                 stage={k: v / max(n, 1) for k, v in stage.items()}, stats=st, rel=rel, max=mx)
 
 
+KERNEL_NAMES = {1: "poisson", 2: "biot_savart", 3: "inv_dist", 4: "biharmonic", 5: "sal"}
+
+
+def kernel_table(cs, torch, T, W, N, p, theta, leaf, S, steps):
+    """Eval time and error of every kernel on the headline geometry (one plan
+    per form, kernel chosen per eval), like the paper's Table 3 rows; the
+    error is against the GPU FP64 direct sum on the 4,096-target sample."""
+    Ts = T[S].contiguous()
+    table = {}
+    for k, name in KERNEL_NAMES.items():
+        ref = cs.direct(Ts, T, W, kernel=k)
+        table[name] = {}
+        for fp32 in (True, False):
+            plan = cs.Plan(T, None, kernel=k, p=p, theta=theta, leaf_size=leaf, fp32=fp32)
+            out = plan.eval(W)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                plan.eval(W, out=out)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / steps
+            plan.close()
+            d = out[S] - ref
+            rel = float(torch.sqrt(torch.sum(d * d) / torch.sum(ref * ref)))
+            table[name]["fp32" if fp32 else "fp64"] = {"ms": ms, "rel_l2_err": rel}
+    return table
+
+
 def cpu_baseline(P, w, seconds):
     """The direct-sum oracle on the host cores, on a bounded sample of targets."""
     from oracle import direct, oracle_threads
@@ -344,6 +372,7 @@ def main():
         f32, f64 = (head, other) if fp32 else (other, head)
         line["fp32_over_fp64_speedup"] = f64["ms"] / f32["ms"]
         line["gpu_direct_rate"] = direct_rate
+        line["kernels"] = kernel_table(cs, torch, T, W, N, head["p"], theta, leaf, S, 10)
     if not args.no_cpu_baseline and not args.quick:
         line["cpu_baseline"] = cpu_baseline(P, w, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -55,7 +55,12 @@ enum csfmm_status {
 enum csfmm_kernel {
     CSFMM_K_POISSON_LOG = 1, /* -(1/4pi) ln(1 - x.y), eq. (G_L); one output */
     CSFMM_K_BIOT_SAVART = 2, /* -(1/4pi) (x cross y)/(1 - x.y), eq. (K_BS); three outputs */
-    CSFMM_K_INV_DIST = 3     /* 1/|x - y| = 1/gamma(x, y), the first term of eq. (G_SAL_approx) */
+    CSFMM_K_INV_DIST = 3,    /* 1/|x - y| = 1/gamma(x, y), the first term of eq. (G_SAL_approx) */
+    CSFMM_K_BIHARMONIC = 4,  /* (1/4pi) dilog((1 + x.y)/2), eq. (G_B); one output */
+    CSFMM_K_SAL = 5          /* eq. (G_SAL_approx): (3 rw/(4pi re)) ((1 - b0)/gamma
+                                - (a1 - b1) ln(gamma/2 + gamma^2/4)), gamma = |x - y|,
+                                a1 = -2.7, b0 = -6.21196, b1 = 6.1, rw/re = 1025/5514
+                                (the ratio is named, not given, in §2.5); one output */
 };
 
 /* Precision forms. */

@@ -18,7 +18,10 @@ import torch
 POISSON = 1
 BIOT_SAVART = 2
 INV_DIST = 3
-KERNELS = {"poisson": POISSON, "biot_savart": BIOT_SAVART, "inv_dist": INV_DIST}
+BIHARMONIC = 4
+SAL = 5
+KERNELS = {"poisson": POISSON, "biot_savart": BIOT_SAVART, "inv_dist": INV_DIST,
+           "biharmonic": BIHARMONIC, "sal": SAL}
 
 FP64 = 0
 FP32_FORM = 1

@@ -21,7 +21,7 @@ void set_error(const char* fmt, ...) {
 void clear_error() { g_err[0] = 0; }
 
 static bool valid_kernel(int k) {
-    return k == CSFMM_K_POISSON_LOG || k == CSFMM_K_BIOT_SAVART || k == CSFMM_K_INV_DIST;
+    return k >= CSFMM_K_POISSON_LOG && k <= CSFMM_K_SAL;
 }
 
 }  // namespace csfmm

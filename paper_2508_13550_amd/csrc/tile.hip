@@ -22,6 +22,11 @@
 //             squared distance is 1 - x.y; FP32 uses log2 and folds ln 2 in.
 //   Biot-Savart -(1/4pi) (x cross y)/(1 - x.y) = -(1/2pi) x cross sum (y-x) w/|x-y|^2.
 //   1/|x-y|   rsqrt of the squared distance.
+//   biharmonic (1/4pi) dilog((1 + x.y)/2): coordinates scaled by 1/2 so that
+//             the squared distance is v = 1 - (1 + x.y)/2; see dilog_1m below.
+//   SAL       (3 rw/(4pi re)) ((1-b0)/g - (a1-b1) ln(g/2 + g^2/4)), g = |x-y|:
+//             with the 1/2 scaling g/2 = sqrt(v), so the bracket is
+//             ((1-b0)/2) (1/sqrt(v) + q ln(sqrt(v) + v)), q = -2(a1-b1)/(1-b0).
 // The self term (squared distance exactly 0) contributes nothing.
 #include <type_traits>
 
@@ -47,12 +52,72 @@ constexpr int vdim() {
 
 template <int KERN>
 constexpr double coord_scale() {
-    return KERN == CSFMM_K_POISSON_LOG ? kInvSqrt2 : 1.0;
+    return KERN == CSFMM_K_POISSON_LOG ? kInvSqrt2
+           : (KERN == CSFMM_K_BIHARMONIC || KERN == CSFMM_K_SAL) ? 0.5
+                                                                  : 1.0;
 }
 
 __device__ __forceinline__ float dev_log2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float dev_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float dev_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// dilog(1 - v) for 0 < v (clamped to 1), dilog(u) = -int_0^u ln(1-t)/t dt.
+// With the substitution w = -ln(1 - z) the dilogarithm is the series
+// dilog(z) = sum_k B_k w^(k+1)/(k+1)!  (Bernoulli numbers B_k; only B_1 = -1/2
+// and the even ones are nonzero), whose radius is 2 pi.  Both branches keep
+// w <= ln 2:
+//   v <= 1/2:  dilog(1-v) = pi^2/6 - ln(v) ln(1-v) - dilog(v), w = -ln(1-v)
+//              (Euler's reflection formula);
+//   v >  1/2:  dilog(1-v) directly, w = -ln(v).
+// The odd part is w + w^2 (-1/4 + w sum_k c_k w^(2k-2)), c_k = B_2k/(2k+1)!;
+// eight terms reach FP64 rounding on w <= ln 2, three reach FP32 rounding.
+__device__ constexpr double kBern[8] = {
+    1.0 / 36.0,          -1.0 / 3600.0,     1.0 / 211680.0,
+    -1.0 / 10886400.0,   1.0 / 526901760.0, -691.0 / 16999766784000.0,
+    1.0 / 1120863744000.0, -3617.0 / 181400588328960000.0};
+constexpr double kPi2Over6 = 1.64493406684822643647;
+
+__device__ __forceinline__ double dilog_1m(double v) {
+    v = fmin(v, 1.0);
+    const double l1 = log(v), l2 = log1p(-v);
+    const bool refl = v <= 0.5;
+    const double w = refl ? -l2 : -l1;
+    const double w2 = w * w;
+    double c = kBern[7];
+#pragma unroll
+    for (int k = 6; k >= 0; --k) c = fma(c, w2, kBern[k]);
+    const double sr = fma(w2, fma(w, c, -0.25), w);
+    return refl ? (kPi2Over6 - l1 * l2) - sr : sr;
+}
+
+__device__ __forceinline__ float dilog_1m(float v) {
+    constexpr float ln2 = 0.69314718055994530942f;
+    v = fminf(v, 1.f);
+    const float a = dev_log2(v), b = dev_log2(1.f - v);
+    const bool refl = v <= 0.5f;
+    const float w = (refl ? b : a) * -ln2;
+    const float w2 = w * w;
+    const float c = fmaf(fmaf(float(kBern[2]), w2, float(kBern[1])), w2, float(kBern[0]));
+    const float sr = fmaf(w2, fmaf(w, c, -0.25f), w);
+    return refl ? fmaf(-ln2 * ln2, a * b, float(kPi2Over6)) - sr : sr;
+}
+
+// SAL closed form, eq. (G_SAL_approx), with the Love number fit of §2.5.
+constexpr double kSalA1 = -2.7, kSalB0 = -6.21196, kSalB1 = 6.1;
+constexpr double kSalRho = 1025.0 / 5514.0;  // seawater / mean Earth density
+constexpr double kSalQ = -2.0 * (kSalA1 - kSalB1) / (1.0 - kSalB0);
+constexpr double kSalScale = 3.0 * kSalRho / (4.0 * kPi) * 0.5 * (1.0 - kSalB0);
+
+// 1/sqrt(v) + q ln(sqrt(v) + v) for v = |x-y|^2/4 > 0
+__device__ __forceinline__ double sal_bracket(double v) {
+    const double rs = rsqrt(v);
+    return fma(kSalQ, log(fma(v, rs, v)), rs);
+}
+__device__ __forceinline__ float sal_bracket(float v) {
+    constexpr float q2 = float(kSalQ * kLn2);  // log2 in, natural log out
+    const float rs = dev_rsq(v);
+    return fmaf(q2, dev_log2(fmaf(v, rs, v)), rs);
+}
 
 // Evaluation forms of one (target, source) pair:
 //  FORM_CHECK  direct differences, a zero squared distance (coincident point)
@@ -84,6 +149,10 @@ __device__ __forceinline__ void eval_pair(const TargetRegs& T, Real<F32> sx, Rea
         const float d = fmaf(T.mx, sx, fmaf(T.my, sy, fmaf(T.mz, sz, s2 + T.f2)));
         if constexpr (KERN == CSFMM_K_POISSON_LOG)
             p[0] = fmaf(w, dev_log2(d), p[0]);
+        else if constexpr (KERN == CSFMM_K_BIHARMONIC)
+            p[0] = fmaf(w, dilog_1m(d), p[0]);
+        else if constexpr (KERN == CSFMM_K_SAL)
+            p[0] = fmaf(w, sal_bracket(d), p[0]);
         else
             p[0] = fmaf(w, dev_rsq(d), p[0]);
     } else {
@@ -109,6 +178,14 @@ __device__ __forceinline__ void eval_pair(const TargetRegs& T, Real<F32> sx, Rea
             p[0] = fma(dx, f, p[0]);
             p[1] = fma(dy, f, p[1]);
             p[2] = fma(dz, f, p[2]);
+        } else if constexpr (KERN == CSFMM_K_BIHARMONIC) {
+            R g = dilog_1m(r2);
+            if constexpr (FORM == FORM_CHECK) g = r2 > R(0) ? g : R(0);
+            p[0] = fma(w, g, p[0]);
+        } else if constexpr (KERN == CSFMM_K_SAL) {
+            R g = sal_bracket(r2);
+            if constexpr (FORM == FORM_CHECK) g = r2 > R(0) ? g : R(0);
+            p[0] = fma(w, g, p[0]);
         } else {
             R inv;
             if constexpr (F32)
@@ -132,6 +209,10 @@ __device__ __forceinline__ void epilogue(const double* acc, double x, double y, 
         out[0] = c * (y * acc[2] - z * acc[1]);
         out[1] = c * (z * acc[0] - x * acc[2]);
         out[2] = c * (x * acc[1] - y * acc[0]);
+    } else if constexpr (KERN == CSFMM_K_BIHARMONIC) {
+        out[0] = acc[0] / (4.0 * kPi);
+    } else if constexpr (KERN == CSFMM_K_SAL) {
+        out[0] = kSalScale * acc[0];
     } else {
         out[0] = acc[0];
     }
@@ -410,9 +491,10 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int local, TileSmem<
 // Near-field blocks first (longest first), then far-field blocks, in one grid:
 // block b < prefix[n] is near-field work located by `prefix`, the others are
 // far-field work located by `prefix2`.  The occupancy hint keeps the FP32
-// instances at 80 VGPRs (6 waves per SIMD; measured faster than 5).
+// instances at 80 VGPRs (6 waves per SIMD; measured faster than 5); the FP64
+// instances, whose transcendentals are longer, get 4 waves per SIMD.
 template <int KERN, bool F32>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_tile(Batch b) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 4))) void k_tile(Batch b) {
     __shared__ TileSmem<KERN, F32> sm;
     const int blk = xcd_logical_block(blockIdx.x, gridDim.x);
     const int split = b.prefix[b.n];
@@ -528,6 +610,12 @@ __global__ __launch_bounds__(kThreads) void k_direct(const double* __restrict__ 
                 p[0] = fma(dx, f, p[0]);
                 p[1] = fma(dy, f, p[1]);
                 p[2] = fma(dz, f, p[2]);
+            } else if constexpr (KERN == CSFMM_K_BIHARMONIC) {
+                const R g = r2 > R(0) ? dilog_1m(R(0.25) * r2) : R(0);
+                p[0] = fma(e.w, g, p[0]);
+            } else if constexpr (KERN == CSFMM_K_SAL) {
+                const R g = r2 > R(0) ? sal_bracket(R(0.25) * r2) : R(0);
+                p[0] = fma(e.w, g, p[0]);
             } else {
                 R inv;
                 if constexpr (F32)
@@ -618,6 +706,10 @@ int launch_tile_batch(const Batch& b, int kernel, bool fp32, hipStream_t s) {
             return fp32 ? launch_tile_t<2, true>(b, s) : launch_tile_t<2, false>(b, s);
         case CSFMM_K_INV_DIST:
             return fp32 ? launch_tile_t<3, true>(b, s) : launch_tile_t<3, false>(b, s);
+        case CSFMM_K_BIHARMONIC:
+            return fp32 ? launch_tile_t<4, true>(b, s) : launch_tile_t<4, false>(b, s);
+        case CSFMM_K_SAL:
+            return fp32 ? launch_tile_t<5, true>(b, s) : launch_tile_t<5, false>(b, s);
         default:
             set_error("unknown kernel id %d", kernel);
             return CSFMM_E_INVALID;
@@ -636,6 +728,12 @@ int launch_direct(const double* tgt, int64_t nt, const double* src, int64_t ns, 
         case CSFMM_K_INV_DIST:
             return fp32 ? launch_direct_t<3, true>(tgt, nt, src, ns, w, out, s)
                         : launch_direct_t<3, false>(tgt, nt, src, ns, w, out, s);
+        case CSFMM_K_BIHARMONIC:
+            return fp32 ? launch_direct_t<4, true>(tgt, nt, src, ns, w, out, s)
+                        : launch_direct_t<4, false>(tgt, nt, src, ns, w, out, s);
+        case CSFMM_K_SAL:
+            return fp32 ? launch_direct_t<5, true>(tgt, nt, src, ns, w, out, s)
+                        : launch_direct_t<5, false>(tgt, nt, src, ns, w, out, s);
         default:
             set_error("unknown kernel id %d", kernel);
             return CSFMM_E_INVALID;

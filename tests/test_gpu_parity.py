@@ -51,16 +51,25 @@ def _announce(msg):
 
 # ------------------------------------------------------------------ direct
 
-@pytest.mark.parametrize("kernel", [1, 2, 3])
+# The biharmonic kernel is smooth and nearly constant (pi^2/24 at coincidence),
+# so against the zero-mean field Y_4,3 its sum cancels to about 1/400 of
+# sum |G w|: rounding of the terms is magnified by that factor.
+CANCEL = {1: 1.0, 2: 1.0, 3: 1.0, 4: 20.0, 5: 1.0}
+
+
+@pytest.mark.parametrize("kernel", [1, 2, 3, 4, 5])
 def test_direct_matches_oracle(kernel):
     _announce("direct config-1 grid kernel %d" % kernel)
     P, A = cubed_sphere_grid(32)
     w = real_y43(P) * A
     ref = odirect(kernel, P, P, w)
     got = host(cs.direct(tdev(P), tdev(P), tdev(w), kernel=kernel))
-    assert rel_l2(got, ref) < 1e-13 and rel_max(got, ref) < 1e-12
+    c = CANCEL[kernel]
+    print("fp64 rel_l2 %.3e rel_max %.3e" % (rel_l2(got, ref), rel_max(got, ref)), flush=True)
+    assert rel_l2(got, ref) < 1e-13 * c and rel_max(got, ref) < 1e-12 * c
     got32 = host(cs.direct(tdev(P), tdev(P), tdev(w), kernel=kernel, fp32=True))
-    assert rel_l2(got32, ref) < 2e-6
+    print("fp32 rel_l2 %.3e" % rel_l2(got32, ref), flush=True)
+    assert rel_l2(got32, ref) < 2e-6 * c
 
 
 def test_direct_distinct_and_ragged():
@@ -69,10 +78,10 @@ def test_direct_distinct_and_ragged():
     X = random_sphere_points(1001, 5)
     X[:3] = S[[0, 7, 100]]  # exact coincidences are skipped
     w = np.random.default_rng(1).standard_normal(S.shape[0])
-    for k in (1, 2, 3):
+    for k in (1, 2, 3, 4, 5):
         ref = odirect(k, X, S, w)
         got = host(cs.direct(tdev(X), tdev(S), tdev(w), kernel=k))
-        assert rel_max(got, ref) < 1e-12
+        assert rel_max(got, ref) < 1e-12 * CANCEL[k]
     one = host(cs.direct(tdev(X[:1]), tdev(S[:1]), tdev(w[:1]), kernel=1))
     assert one[0] == 0.0  # the only source coincides with the target
 
@@ -125,6 +134,8 @@ CASES = {
     "distinct_random": lambda: (random_sphere_points(3000, 41), cubed_sphere_grid(16)[0], 2, 6, 0.6, 40),
     "clustered": lambda: (_clustered(), None, 1, 4, 0.5, 12),
     "tiny_p1_leaf1": lambda: (cubed_sphere_grid(2)[0], None, 1, 1, 0.5, 1),
+    "biharmonic_E32": lambda: (cubed_sphere_grid(32)[0], None, 4, 8, 0.7, 64),
+    "sal_distinct": lambda: (random_sphere_points(2000, 43), cubed_sphere_grid(16)[0], 5, 6, 0.6, 40),
 }
 
 
@@ -175,17 +186,18 @@ def test_stages_and_result(case):
     # (the library also interpolates into empty cells, which the oracle skips)
     vd = 3 if k == 2 else 1
     n1 = p + 1
+    c = CANCEL[k]
     op = np.zeros((vd, len(ofmm.ttree.cells), n1 * n1))
     for cid, val in stg["psi"].items():
         op[:, cid, :] = np.asarray(val).reshape(n1 * n1, vd).T
     full = np.array([C.count > 0 for C in ofmm.ttree.cells])
     if np.any(op[:, full] != 0):
-        assert rel_max(psi[:, full], op[:, full]) < 1e-12
+        assert rel_max(psi[:, full], op[:, full]) < 1e-12 * c
     # near field (PP + PC)
     onear = stg["near"]
-    assert rel_max(near, onear) < 1e-12
+    assert rel_max(near, onear) < 1e-12 * c
     # the whole result, vs the oracle FMM and vs the direct sum
-    assert rel_max(out, ref) < 1e-12
+    assert rel_max(out, ref) < 1e-12 * c
     d = odirect(k, T, src, w)
     assert rel_l2(out, d) < 1e-3
 
@@ -199,7 +211,8 @@ def test_fp32_form_close_to_fp64(case):
     a = host(plan.eval(tdev(w)))
     b = host(plan32.eval(tdev(w)))
     plan32.close()
-    assert rel_l2(b, a) < 5e-6
+    print("fp32 vs fp64 rel_l2 %.3e" % rel_l2(b, a), flush=True)
+    assert rel_l2(b, a) < 5e-6 * CANCEL[k]
 
 
 def test_deterministic(case):
@@ -213,7 +226,7 @@ def test_deterministic(case):
 
 # ------------------------------------------------------------------ whole method
 
-@pytest.mark.parametrize("kernel", [1, 2, 3])
+@pytest.mark.parametrize("kernel", [1, 2, 3, 4, 5])
 def test_degenerate_all_pp_equals_direct(kernel):
     _announce("degenerate theta->0 and leaf>=N, kernel %d" % kernel)
     P, A = cubed_sphere_grid(8)
@@ -225,7 +238,7 @@ def test_degenerate_all_pp_equals_direct(kernel):
         assert st["n_pc"] == st["n_cp"] == st["n_cc"] == 0
         got = host(pl.eval(tdev(w)))
         pl.close()
-        assert rel_l2(got, ref) < 1e-14
+        assert rel_l2(got, ref) < 1e-14 * CANCEL[kernel]
 
 
 def test_config1_gate_and_eigenrelation():

@@ -16,7 +16,8 @@ with E x E cells per face (N = 6 E^2); weights are w_j = f(x_j) A_j
      (seed 4005); p=10, theta=0.6, leaf 128; sampled targets: seed 4006.
   5  serving stream of 2,000 requests (see the serving module).
 
-Kernel ids follow the library: 1 Poisson log, 2 Biot-Savart, 3 1/|x-y|.
+Kernel ids follow the library: 1 Poisson log, 2 Biot-Savart, 3 1/|x-y|,
+4 biharmonic, 5 SAL closed form.
 """
 
 import numpy as np
