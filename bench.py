@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--serve", action="store_true", help="serving stream instead (2,000 requests)")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rho", type=float, nargs="*", default=[0.5, 0.8])
+    ap.add_argument("--sweep", action="store_true",
+                    help="runtime vs error over degree, MAC, leaf size and form (Fig. 7 analogue)")
+    ap.add_argument("--sweep-E", type=int, default=330)
+    ap.add_argument("--sweep-kernels", type=int, nargs="*", default=[1, 4])
     return ap.parse_args()
 
 
@@ -167,6 +171,83 @@ def cpu_baseline(P, w, seconds):
             "sample": "FP64 direct-sum oracle (C, OpenMP): %d seeded targets x all %d sources "
                       "in %.1f s; the direct method's pairs/s is its N^2-equiv rate" % (m, n, t),
             "host": platform.processor() or platform.machine()}
+
+
+SWEEP_TOLS = (1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12)
+
+
+def sweep_bench(args):
+    """Eval time vs approximation error over p = 2:2:14, MAC in {0.5, 0.7, 0.9},
+    leaf size in {64, 128, 256, 4p^2} (4p^2 is the paper's N0) and both forms,
+    for the Poisson and biharmonic kernels (the paper's Fig. 7 pair), on the
+    cubed-sphere grid closest to the paper's N = 655,362 (E = 330: 653,400
+    points) with the band-limited field of the headline workload.  Error:
+    relative L2 against the GPU FP64 direct sum on 4,096 seeded targets.
+    Prints every point, the Pareto front per kernel, and the fastest setting
+    per tolerance."""
+    import torch
+    import paper_2508_13550_amd as cs
+    from workloads import make_config, config_subset
+
+    cfg = make_config(2, E=args.sweep_E)
+    P, w = cfg["sources"], cfg["weights"]
+    N = P.shape[0]
+    dev = torch.device("cuda:0")
+    T = torch.tensor(P, dtype=torch.float64, device=dev)
+    W = torch.tensor(w, dtype=torch.float64, device=dev)
+    S = torch.tensor(config_subset(N, 4096, cfg["subset_seed"]), device=dev)
+    Ts = T[S].contiguous()
+    points = []
+    for k in args.sweep_kernels:
+        ref = cs.direct(Ts, T, W, kernel=k)
+        for theta in (0.5, 0.7, 0.9):
+            for p in range(2, 15, 2):
+                for leaf in sorted({64, 128, 256, 4 * p * p}):
+                    for fp32 in (True, False):
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        plan = cs.Plan(T, None, kernel=k, p=p, theta=theta, leaf_size=leaf,
+                                       fp32=fp32)
+                        torch.cuda.synchronize()
+                        plan_ms = 1e3 * (time.perf_counter() - t0)
+                        out = plan.eval(W)
+                        plan.eval(W, out=out)
+                        torch.cuda.synchronize()
+                        reps = 10
+                        t0 = time.perf_counter()
+                        for _ in range(reps):
+                            plan.eval(W, out=out)
+                        torch.cuda.synchronize()
+                        ms = 1e3 * (time.perf_counter() - t0) / reps
+                        plan.close()
+                        d = out[S] - ref
+                        rel = float(torch.sqrt(torch.sum(d * d) / torch.sum(ref * ref)))
+                        points.append({"kernel": KERNEL_NAMES[k], "theta": theta, "p": p,
+                                       "leaf": leaf, "form": "fp32" if fp32 else "fp64",
+                                       "ms": ms, "rel_l2_err": rel, "plan_ms": plan_ms})
+                    print("sweep %s theta %.1f p %d done" % (KERNEL_NAMES[k], theta, p),
+                          file=sys.stderr, flush=True)
+    fronts, best = {}, {}
+    for k in args.sweep_kernels:
+        name = KERNEL_NAMES[k]
+        pts = sorted((q for q in points if q["kernel"] == name), key=lambda q: q["ms"])
+        front, lo = [], float("inf")
+        for q in pts:
+            if q["rel_l2_err"] < lo:
+                front.append(q)
+                lo = q["rel_l2_err"]
+        fronts[name] = front
+        best[name] = {}
+        for tol in SWEEP_TOLS:
+            ok = [q for q in pts if q["rel_l2_err"] <= tol]
+            best[name]["%g" % tol] = ok[0] if ok else None
+    line = {"metric": "eval time vs relative L2 error (p, MAC, leaf, form sweep)",
+            "unit": "ms", "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": "equiangular cubed sphere %dx%d cells per face (N=%d), "
+                                   "band-limited n<=32 field (seed 2002)"
+                                   % (args.sweep_E, args.sweep_E, N), "n": N},
+            "points": points, "pareto": fronts, "fastest_within_tol": best}
+    print(json.dumps(line), flush=True)
 
 
 def serve_bench(args):
@@ -285,6 +366,9 @@ def main():
         return
     if args.serve:
         serve_bench(args)
+        return
+    if args.sweep:
+        sweep_bench(args)
         return
     import torch
     import paper_2508_13550_amd as cs
