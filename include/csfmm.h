@@ -113,7 +113,10 @@ int csfmm_plan(const double* targets, int64_t n_t, const double* sources, int64_
  *   weights [n_s] device (for a same-set plan n_s = n_t)
  *   out     [n_t] device, or [n_t][3] for Biot-Savart
  * Asynchronous on `stream`; weights must stay valid and out must not be read
- * until the stream work completes.  One eval in flight per plan.
+ * until the stream work completes.  One eval in flight per plan.  The PP near
+ * field runs on a side stream of the plan's workspace, forked from and joined
+ * back into `stream` with events, so work ordered after the eval on `stream`
+ * sees all of it (this also holds under stream capture).
  */
 int csfmm_eval(csfmm_plan_t plan, const double* weights, double* out, void* stream);
 
@@ -136,7 +139,9 @@ int csfmm_direct(const double* targets, int64_t n_t, const double* sources, int6
 /*
  * Serving: several requests evaluated together (continuous batching).
  * A workspace holds one request's eval buffers (sorted weights, proxy
- * weights, proxy potentials, near field) for a given plan, so one resident
+ * weights, proxy potentials, near field) and the side stream of its PP near
+ * field (a packed eval uses the side stream of workspaces[0]) for a given
+ * plan, so one resident
  * plan can serve several in-flight requests.  csfmm_eval_many runs the eval
  * phases of n_req requests with one packed launch per phase (per kernel id and
  * precision form for the near and far field): request r uses plans[r] with
@@ -202,12 +207,14 @@ int csfmm_plan_stats(csfmm_plan_t plan, csfmm_stats* s);
  * Per-stage timing of csfmm_eval with HIP events recorded on the eval's
  * stream.  enable != 0 turns it on (and resets the sums), 0 turns it off.
  * csfmm_plan_timing_read waits for the recorded events and returns the summed
- * milliseconds of the 5 stages over the timed evals:
- *   [0] weight gather + P2M, [1] M2M, [2] interactions: PP+PC and CP+CC in one
- *   kernel launch (after zeroing the proxy potentials), [3] L2L, [4] L2P+scatter.
+ * milliseconds of the 6 stages over the timed evals:
+ *   [0] weight gather + P2M, [1] M2M (and zeroing the proxy potentials),
+ *   [2] the PP near-field launch, which runs on the workspace's side stream
+ *   concurrently with [0]-[4], [3] PC near field and CP + CC far field in one
+ *   launch, [4] L2L, [5] L2P + scatter, including the wait for [2].
  */
 int csfmm_plan_timing(csfmm_plan_t plan, int enable);
-int csfmm_plan_timing_read(csfmm_plan_t plan, double* stage_ms /*[5]*/, int64_t* n_evals);
+int csfmm_plan_timing_read(csfmm_plan_t plan, double* stage_ms /*[6]*/, int64_t* n_evals);
 
 /* Upper estimate of the device bytes a plan of these sizes holds (for
  * admission control); -1 on bad arguments. */

@@ -70,7 +70,7 @@ EXPORTED = (
     "csfmm_workspace_destroy", "csfmm_workspace_bytes", "csfmm_eval_many",
 )
 
-STAGES = ("p2m", "m2m", "interactions", "l2l", "l2p")
+STAGES = ("p2m", "m2m", "near_pp", "pc_far", "l2l", "l2p")
 
 
 def load_library(path=LIB_PATH):

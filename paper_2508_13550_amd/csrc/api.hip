@@ -192,7 +192,7 @@ int64_t csfmm_estimate_bytes(int64_t n_t, int64_t n_s, int p, int leaf_size, uns
     auto cells = [&](int64_t n) { return 6 + (16 * n) / (3 * int64_t(leaf_size)) + 64; };
     const int64_t ct = cells(n_t), cs = n_s ? cells(n_s) : 0;
     int64_t b = 0;
-    b += n_t * (5 * 8 + 4) + 3 * 8 * n_t;        // sorted points, local coords, perm, near field
+    b += n_t * (5 * 8 + 4) + 6 * 8 * n_t;        // sorted points, local coords, perm, near field
     b += n_s * (5 * 8 + 4 + 8);                  // same for sources, sorted weights
     b += (ct + cs) * (7 * 4 + 4 * 8 + 3 * KS * 8);  // cell arrays, geometry, proxies
     b += cs * KS * 8 + 3 * ct * KS * 8;          // proxy weights, proxy potentials
@@ -222,7 +222,7 @@ int64_t csfmm_workspace_bytes(csfmm_plan_t plan) {
     if (!plan) return -1;
     return int64_t(sizeof(double)) *
            (plan->ns + int64_t(plan->st->ncells) * plan->KS +
-            int64_t(3) * plan->tt.ncells * plan->KS + int64_t(3) * plan->nt) +
+            int64_t(3) * plan->tt.ncells * plan->KS + int64_t(6) * plan->nt) +
            int64_t(sizeof(csfmm::ReqView));
 }
 

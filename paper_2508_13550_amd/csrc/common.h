@@ -124,7 +124,7 @@ struct ReqView {
     // fixed operators
     const double *bm2m, *bl2l;
     // workspace
-    double *ws, *wbar, *psi, *phinear;
+    double *ws, *wbar, *psi, *phinear, *phipc;
     int64_t nt, ns, psi_stride;
     int32_t p, K, KS, nb1, nb2;
 };
@@ -141,8 +141,14 @@ struct Batch {
     int32_t a0[kMaxBatch];          // M2M / L2L: first parent of the level in `parents`
     int32_t a1[kMaxBatch];          // M2M / L2L: number of parents at the level
     int32_t prefix[kMaxBatch + 1];
-    int32_t prefix2[kMaxBatch + 1];  // tile launches: far-field blocks after the near-field ones
+    int32_t prefix2[kMaxBatch + 1];  // tile launches: far-field blocks (prefix: near-field)
+    int32_t mode;                    // tile launches: kTileNearPP or kTilePCFar
 };
+
+// Tile launch modes.  The PP near field needs no proxy weights, so it runs on
+// a side stream while the upward pass runs; the PC near field (into its own
+// buffer) and the CP + CC far field follow the upward pass.
+enum TileMode { kTileNearPP = 1, kTilePCFar = 2 };
 
 __device__ __forceinline__ void prefix_locate(const int32_t* prefix, int n, int blk, int& r,
                                               int& local) {
@@ -190,12 +196,15 @@ struct csfmm_plan_s {
     csfmm_workspace_s* ws0 = nullptr;
     // optional per-stage timing with HIP events (ring of event sets)
     struct Timing {
-        static constexpr int kStages = 5;  // P2M, M2M, interactions (PP+PC+CP+CC), L2L, L2P
+        // P2M, M2M, PP (side stream), PC + CP + CC, L2L, L2P
+        static constexpr int kStages = 6;
+        static constexpr int kMain = 6;   // events on the eval stream per slot
+        static constexpr int kEvents = kMain + 2;  // + PP start/end on the side stream
         static constexpr int kSlots = 32;
         bool on = false;
-        std::vector<hipEvent_t> ev;  // [kSlots][kStages + 1]
+        std::vector<hipEvent_t> ev;  // [kSlots][kEvents]
         std::vector<int> pending;    // slot recorded and not yet read
-        double sum_ms[kStages] = {0, 0, 0, 0, 0};
+        double sum_ms[kStages] = {0, 0, 0, 0, 0, 0};
         int64_t n = 0;
         int next = 0;
     } timing;
@@ -210,10 +219,19 @@ struct csfmm_workspace_s {
     double* ws = nullptr;       // [ns]
     double* wbar = nullptr;     // [ncells_s][KS]
     double* psi = nullptr;      // [3][ncells_t][KS]
-    double* phinear = nullptr;  // [3][nt]
+    double* phinear = nullptr;  // [3][nt] PP near field
+    double* phipc = nullptr;    // [3][nt] PC near field
     csfmm::ReqView* dview = nullptr;  // device copy of dview_host
     csfmm::ReqView dview_host{};
-    ~csfmm_workspace_s() { arena.release(); }
+    // side stream of the PP near field, with its fork and join events
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    ~csfmm_workspace_s() {
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (side) (void)hipStreamDestroy(side);
+        arena.release();
+    }
 };
 
 inline csfmm_plan_s::~csfmm_plan_s() {

@@ -31,4 +31,18 @@ __device__ __forceinline__ int xcd_logical_block(int bid, int nb) {
     return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// The same for a grid of two kinds of work, nf blocks of the first kind and
+// nb - nf of the second: every XCD gets its share of each kind (a contiguous
+// range of each), first-kind blocks first.  Sets `first` and returns the
+// index within the kind.
+__device__ __forceinline__ int xcd_split_block(int bid, int nb, int nf, bool& first) {
+    const int q = nb >> 3, r = nb & 7;
+    const int qf = nf >> 3, rf = nf & 7;
+    const int x = bid & 7, k = bid >> 3;
+    const int fx = qf + (x < rf ? 1 : 0);
+    first = k < fx;
+    if (first) return x * qf + min(x, rf) + k;
+    return x * q + min(x, r) - (x * qf + min(x, rf)) + (k - fx);
+}
+
 }  // namespace csfmm

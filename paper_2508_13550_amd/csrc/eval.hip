@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void k_mfma_pass(Batch b) {
     }
 }
 
-// e7+e8: L2P (eq. downward_1 at the leaves) + near field + scatter to the
+// e7+e8: L2P (eq. downward_1 at the leaves) + near field (PP, PC) + scatter to the
 // caller's order; one target leaf per block, one point per thread, the
 // Lagrange rows in registers and the leaf's proxy potentials in LDS; VD output
 // components (all requests of a launch have the same VD).
@@ -292,7 +292,8 @@ __global__ __launch_bounds__(64) void k_l2p(Batch b) {
         }
         const int64_t o = V.t_perm[j];
 #pragma unroll
-        for (int d = 0; d < VD; ++d) out[o * VD + d] = V.phinear[d * V.nt + j] + acc[d];
+        for (int d = 0; d < VD; ++d)
+            out[o * VD + d] = (V.phinear[d * V.nt + j] + V.phipc[d * V.nt + j]) + acc[d];
     }
 }
 
@@ -300,12 +301,13 @@ __global__ __launch_bounds__(64) void k_l2p(Batch b) {
 #define CSFMM_P1_CASES(X) \
     X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17)
 
-__global__ void k_scatter_near(const double* __restrict__ near, int64_t nt, int vd,
-                               const int32_t* __restrict__ perm, double* __restrict__ out) {
+__global__ void k_scatter_near(const double* __restrict__ near, const double* __restrict__ pc,
+                               int64_t nt, int vd, const int32_t* __restrict__ perm,
+                               double* __restrict__ out) {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= nt) return;
     const int64_t o = perm[k];
-    for (int d = 0; d < vd; ++d) out[o * vd + d] = near[d * nt + k];
+    for (int d = 0; d < vd; ++d) out[o * vd + d] = near[d * nt + k] + pc[d * nt + k];
 }
 
 // Writes a request view to device memory (kernel argument instead of a copy,
@@ -318,14 +320,18 @@ inline unsigned nblk(int64_t n, int t = 256) { return unsigned((n + t - 1) / t);
 
 using Timing = csfmm_plan_s::Timing;
 
-// Adds the stage times of a finished slot to the sums.
+// Adds the stage times of a finished slot to the sums.  Events of a slot:
+// [0..5] on the eval stream (start, after P2M, after M2M, after PC + far,
+// after L2L, after L2P), [6, 7] around the PP launch on the side stream.
 int drain_slot(Timing& tm, int slot) {
     if (!tm.pending[slot]) return CSFMM_OK;
-    hipEvent_t* e = &tm.ev[size_t(slot) * (Timing::kStages + 1)];
-    CSFMM_HIP_TRY(hipEventSynchronize(e[Timing::kStages]));
+    hipEvent_t* e = &tm.ev[size_t(slot) * Timing::kEvents];
+    CSFMM_HIP_TRY(hipEventSynchronize(e[Timing::kMain - 1]));  // L2P waited for PP
+    static constexpr int from[Timing::kStages] = {0, 1, 6, 2, 3, 4};
+    static constexpr int to[Timing::kStages] = {1, 2, 7, 3, 4, 5};
     for (int k = 0; k < Timing::kStages; ++k) {
         float ms = 0.f;
-        CSFMM_HIP_TRY(hipEventElapsedTime(&ms, e[k], e[k + 1]));
+        CSFMM_HIP_TRY(hipEventElapsedTime(&ms, e[from[k]], e[to[k]]));
         tm.sum_ms[k] += ms;
     }
     tm.n += 1;
@@ -372,11 +378,14 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         tm.next = (tm.next + 1) % Timing::kSlots;
         int rc = drain_slot(tm, slot);
         if (rc != CSFMM_OK) return rc;
-        ev = &tm.ev[size_t(slot) * (Timing::kStages + 1)];
+        ev = &tm.ev[size_t(slot) * Timing::kEvents];
         tm.pending[slot] = 1;
     }
+    // the PP near field runs on the first workspace's side stream
+    csfmm_workspace_s* W0 = reqs[0].ws;
+    hipStream_t side = W0->side;
     auto mark = [&](int k) -> int {
-        if (ev) CSFMM_HIP_TRY(hipEventRecord(ev[k], s));
+        if (ev) CSFMM_HIP_TRY(hipEventRecord(ev[k], k < Timing::kMain ? s : side));
         return CSFMM_OK;
     };
 #define RCX(x)                              \
@@ -385,9 +394,53 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         if (rc_ != CSFMM_OK) return rc_;    \
     } while (0)
     RCX(mark(0));
-    // e1 gather, e2 P2M
+    // e1 gather
     for (int r = 0; r < n; ++r) blk[r] = (reqs[r].plan->ns + 255) / 256;
     RCX(launch_batched(b, blk, [&](unsigned g) { k_gather_w<<<g, 256, 0, s>>>(b); }));
+    // e4 PP near field on the side stream, concurrent with e2-e6: it needs
+    // the gathered weights only; one launch per (kernel, form) group
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    for (int r = 0; r < n; ++r)
+        groups[{reqs[r].kernel, (reqs[r].plan->flags & CSFMM_FP32_FORM) ? 1 : 0}].push_back(r);
+    auto tile_group = [&](const std::vector<int>& idx, int mode, Batch& g) -> int {
+        g = Batch{};
+        g.n = int(idx.size());
+        g.mode = mode;
+        int64_t tn = 0, tf = 0;
+        for (int q = 0; q < g.n; ++q) {
+            const int r = idx[q];
+            g.v[q] = b.v[r];
+            g.w[q] = b.w[r];
+            g.out[q] = b.out[r];
+            g.vd[q] = b.vd[r];
+            g.prefix[q] = int32_t(tn);
+            g.prefix2[q] = int32_t(tf);
+            tn += reqs[r].plan->tt.nleaves;
+            tf += mode == kTilePCFar ? reqs[r].plan->lists.n_far_targets : 0;
+        }
+        g.prefix[g.n] = int32_t(tn);
+        g.prefix2[g.n] = int32_t(tf);
+        if (tn + tf > (int64_t(1) << 31) - 1) {
+            set_error("interaction launch too large");
+            return CSFMM_E_INVALID;
+        }
+        return CSFMM_OK;
+    };
+    auto launch_pp = [&]() -> int {
+        CSFMM_HIP_TRY(hipEventRecord(W0->fork, s));
+        CSFMM_HIP_TRY(hipStreamWaitEvent(side, W0->fork, 0));
+        RCX(mark(6));
+        for (auto& kv : groups) {
+            Batch g;
+            RCX(tile_group(kv.second, kTileNearPP, g));
+            RCX(launch_tile_batch(g, kv.first.first, kv.first.second != 0, side));
+        }
+        RCX(mark(7));
+        CSFMM_HIP_TRY(hipEventRecord(W0->join, side));
+        return CSFMM_OK;
+    };
+    RCX(launch_pp());
+    // e2 P2M
     for (int r = 0; r < n; ++r) blk[r] = reqs[r].plan->st->nleaves;
     // grouped by degree (P1 is a template parameter)
     for (int P1 = 2; P1 <= kMaxP1; ++P1) {
@@ -426,34 +479,12 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         blk[r] = (int64_t(b.vd[r]) * reqs[r].ws->dview_host.psi_stride + 255) / 256;
     RCX(launch_batched(b, blk, [&](unsigned g) { k_zero_psi<<<g, 256, 0, s>>>(b); }));
     RCX(mark(2));
-    // e4+e5 interactions: PP + PC at the target particles and CP + CC into
+    // e4+e5 PC at the target particles (into its own buffer) and CP + CC into
     // the proxy potentials, one launch per (kernel, form) group with the
     // near-field blocks first and the far-field blocks after them
-    std::map<std::pair<int, int>, std::vector<int>> groups;
-    for (int r = 0; r < n; ++r)
-        groups[{reqs[r].kernel, (reqs[r].plan->flags & CSFMM_FP32_FORM) ? 1 : 0}].push_back(r);
     for (auto& kv : groups) {
-        const std::vector<int>& idx = kv.second;
-        Batch g{};
-        g.n = int(idx.size());
-        int64_t tn = 0, tf = 0;
-        for (int q = 0; q < g.n; ++q) {
-            const int r = idx[q];
-            g.v[q] = b.v[r];
-            g.w[q] = b.w[r];
-            g.out[q] = b.out[r];
-            g.vd[q] = b.vd[r];
-            g.prefix[q] = int32_t(tn);
-            g.prefix2[q] = int32_t(tf);
-            tn += reqs[r].plan->tt.nleaves;
-            tf += reqs[r].plan->lists.n_far_targets;
-        }
-        g.prefix[g.n] = int32_t(tn);
-        g.prefix2[g.n] = int32_t(tf);
-        if (tn + tf > (int64_t(1) << 31) - 1) {
-            set_error("interaction launch too large");
-            return CSFMM_E_INVALID;
-        }
+        Batch g;
+        RCX(tile_group(kv.second, kTilePCFar, g));
         RCX(launch_tile_batch(g, kv.first.first, kv.first.second != 0, s));
     }
     RCX(mark(3));
@@ -471,6 +502,8 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         RCX(launch_batched(b, blk, [&](unsigned g) { k_mfma_pass<1><<<g, 256, 0, s>>>(b); }));
     }
     RCX(mark(4));
+    // join the PP near field
+    CSFMM_HIP_TRY(hipStreamWaitEvent(s, W0->join, 0));
     // e7+e8 L2P, near field and scatter to the caller's order; one launch per
     // number of output components (blocks of the other group are empty)
     for (int vdl : {1, 3})
@@ -504,7 +537,7 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
 int timing_enable(csfmm_plan_s* P, bool on) {
     Timing& tm = P->timing;
     if (on && tm.ev.empty()) {
-        tm.ev.assign(size_t(Timing::kSlots) * (Timing::kStages + 1), nullptr);
+        tm.ev.assign(size_t(Timing::kSlots) * Timing::kEvents, nullptr);
         for (auto& e : tm.ev) CSFMM_HIP_TRY(hipEventCreate(&e));
         tm.pending.assign(Timing::kSlots, 0);
     }
@@ -544,10 +577,19 @@ int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** ou
     if (rc == CSFMM_OK) rc = W->arena.alloc(&W->wbar, int64_t(S.ncells) * P->KS);
     if (rc == CSFMM_OK) rc = W->arena.alloc(&W->psi, int64_t(3) * T.ncells * P->KS);
     if (rc == CSFMM_OK) rc = W->arena.alloc(&W->phinear, int64_t(3) * P->nt);
+    if (rc == CSFMM_OK) rc = W->arena.alloc(&W->phipc, int64_t(3) * P->nt);
     if (rc == CSFMM_OK) rc = W->arena.alloc(&W->dview, 1);
     if (rc != CSFMM_OK) {
         delete W;
         return rc;
+    }
+    hipError_t se = hipStreamCreateWithFlags(&W->side, hipStreamNonBlocking);
+    if (se == hipSuccess) se = hipEventCreateWithFlags(&W->fork, hipEventDisableTiming);
+    if (se == hipSuccess) se = hipEventCreateWithFlags(&W->join, hipEventDisableTiming);
+    if (se != hipSuccess) {
+        set_error("creating the side stream failed: %s", hipGetErrorString(se));
+        delete W;
+        return CSFMM_E_HIP;
     }
     ReqView& v = W->dview_host;
     v = ReqView{};
@@ -566,7 +608,7 @@ int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** ou
     v.far_targets = P->lists.far_targets;
     v.bm2m = P->bm2m;
     v.bl2l = P->bl2l;
-    v.ws = W->ws; v.wbar = W->wbar; v.psi = W->psi; v.phinear = W->phinear;
+    v.ws = W->ws; v.wbar = W->wbar; v.psi = W->psi; v.phinear = W->phinear; v.phipc = W->phipc;
     v.nt = P->nt; v.ns = P->ns;
     v.psi_stride = int64_t(T.ncells) * P->KS;
     v.p = P->p; v.K = P->K; v.KS = P->KS; v.nb1 = P->nb1; v.nb2 = P->nb2;
@@ -606,7 +648,8 @@ int run_eval(csfmm_plan_s* P, int kernel, const double* weights, double* out, do
                                      sizeof(double) * vd * int64_t(T.ncells) * P->KS,
                                      hipMemcpyDeviceToDevice, s));
     if (near_out) {
-        k_scatter_near<<<nblk(P->nt), 256, 0, s>>>(P->ws0->phinear, P->nt, vd, T.perm, near_out);
+        k_scatter_near<<<nblk(P->nt), 256, 0, s>>>(P->ws0->phinear, P->ws0->phipc, P->nt, vd,
+                                                   T.perm, near_out);
         CSFMM_LAUNCH_CHECK();
     }
     return CSFMM_OK;

@@ -5,8 +5,9 @@
 // set against a list of source sets (paper §5 notes they are all direct
 // sums).  One workgroup owns one target cell:
 //   near kernel: targets = the particles of a target leaf; sources = the
-//                particles of its PP cells, then the proxies (with proxy
-//                weights) of its PC cells;
+//                particles of its PP cells (one launch), or the proxies (with
+//                proxy weights) of its PC cells (a later launch, together
+//                with the far kernel's blocks);
 //   far kernel:  targets = the (p+1)^2 proxies of a target cell; sources =
 //                the particles of its CP cells, then the proxies of its CC
 //                cells; the result is its accumulated proxy potential
@@ -231,14 +232,16 @@ struct TileArgs {
     const double *sx, *sy, *sz, *sw;
     const double *sprox, *swbar;
     int K, KS;
+    bool use_a, use_b;  // which of the two lists this launch takes
     double* out;
     int64_t comp_stride;
 };
 
 // The near kernel (TPROX = false) takes target particles of leaves with the PP
-// and PC lists; the far kernel (TPROX = true) takes target proxies with CP, CC.
+// list (mode kTileNearPP, into phinear) or the PC list (mode kTilePCFar, into
+// phipc); the far kernel (TPROX = true) takes target proxies with CP and CC.
 template <bool TPROX>
-__device__ __forceinline__ TileArgs tile_args(const ReqView& V) {
+__device__ __forceinline__ TileArgs tile_args(const ReqView& V, int mode) {
     TileArgs a;
     a.tcells = TPROX ? V.far_targets : V.t_leaves;
     a.tbegin = V.t_begin;
@@ -263,7 +266,9 @@ __device__ __forceinline__ TileArgs tile_args(const ReqView& V) {
     a.swbar = V.wbar;
     a.K = V.K;
     a.KS = V.KS;
-    a.out = TPROX ? V.psi : V.phinear;
+    a.use_a = TPROX || mode == kTileNearPP;
+    a.use_b = TPROX || mode == kTilePCFar;
+    a.out = TPROX ? V.psi : (mode == kTileNearPP ? V.phinear : V.phipc);
     a.comp_stride = TPROX ? V.psi_stride : V.nt;
     return a;
 }
@@ -318,7 +323,8 @@ struct TileSmem {
 
 // One target cell of one request: near field (TPROX = false) or far field.
 template <int KERN, bool F32, bool TPROX>
-__device__ __forceinline__ void tile_body(const ReqView& V, int local, TileSmem<KERN, F32>& sm) {
+__device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
+                                          TileSmem<KERN, F32>& sm) {
     using R = Real<F32>;
     constexpr int VD = vdim<KERN>();
     constexpr double scale = coord_scale<KERN>();
@@ -327,16 +333,16 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int local, TileSmem<
     int* e_pref = sm.e_pref;
     int* lw = sm.lw;
     auto& red = sm.red;
-    const TileArgs a = tile_args<TPROX>(V);
+    const TileArgs a = tile_args<TPROX>(V, mode);
     const int T = a.tcells[local];
     const int tid = threadIdx.x;
     const double cx = a.tcenter[3 * T], cy = a.tcenter[3 * T + 1], cz = a.tcenter[3 * T + 2];
     const int KS = a.KS;
     const int nT = TPROX ? a.K : a.tcount[T];
     const int tb = TPROX ? 0 : a.tbegin[T];
-    const int ea0 = a.off_a[T], nea = a.off_a[T + 1] - ea0;
-    const int eb0 = a.off_b[T], neb = a.off_b[T + 1] - eb0;
-    const int nov = a.novl ? a.novl[T] : 0;
+    const int ea0 = a.off_a[T], nea = a.use_a ? a.off_a[T + 1] - ea0 : 0;
+    const int eb0 = a.off_b[T], neb = a.use_b ? a.off_b[T + 1] - eb0 : 0;
+    const int nov = (a.use_a && a.novl) ? a.novl[T] : 0;
     // entry ranges of the three forms: [0,nov) check, [nov,nea) near, [nea,nea+neb) far;
     // sources of the far kernel are all MAC separated
     const int ph_hi[3] = {TPROX ? 0 : nov, TPROX ? 0 : nea, nea + neb};
@@ -488,23 +494,25 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int local, TileSmem<
     }
 }
 
-// Near-field blocks first (longest first), then far-field blocks, in one grid:
-// block b < prefix[n] is near-field work located by `prefix`, the others are
-// far-field work located by `prefix2`.  The occupancy hint keeps the FP32
+// Far-field and near-field blocks in one grid: prefix2 locates far-field work
+// (none in a kTileNearPP launch), prefix near-field work.  Every XCD runs its
+// share of far-field blocks first and then its share of near-field blocks; in
+// a kTilePCFar launch the far-field blocks are the long ones and the short PC
+// blocks fill the tail.  The occupancy hint keeps the FP32
 // instances at 80 VGPRs (6 waves per SIMD; measured faster than 5); the FP64
 // instances, whose transcendentals are longer, get 4 waves per SIMD.
 template <int KERN, bool F32>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 4))) void k_tile(Batch b) {
     __shared__ TileSmem<KERN, F32> sm;
-    const int blk = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int split = b.prefix[b.n];
+    bool far;
+    const int blk = xcd_split_block(blockIdx.x, gridDim.x, b.prefix2[b.n], far);
     int req, local;
-    if (blk < split) {
-        batch_locate(b, blk, req, local);
-        tile_body<KERN, F32, false>(*b.v[req], local, sm);
+    if (far) {
+        batch_locate2(b, blk, req, local);
+        tile_body<KERN, F32, true>(*b.v[req], b.mode, local, sm);
     } else {
-        batch_locate2(b, blk - split, req, local);
-        tile_body<KERN, F32, true>(*b.v[req], local, sm);
+        batch_locate(b, blk, req, local);
+        tile_body<KERN, F32, false>(*b.v[req], b.mode, local, sm);
     }
 }
 

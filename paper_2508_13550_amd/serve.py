@@ -122,7 +122,7 @@ def workspace_bytes_estimate(n_t, n_s, p, leaf):
     K = (p + 1) ** 2
     KS = (K + 3) // 4 * 4
     return 8 * (n_s + estimate_cells(n_s, leaf) * KS + 3 * estimate_cells(n_t, leaf) * KS
-                + 3 * n_t) + 1024
+                + 6 * n_t) + 1024
 
 
 @dataclass
