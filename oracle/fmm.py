@@ -14,6 +14,7 @@ Steps and the passages they follow:
   * dual tree traversal ................. §8, Algorithm 2 and the MAC below it
   * accumulated proxy potentials ........ §8, eq. (CP_CC_accumulated)
   * downward pass ....................... §8.1, eqs. (downward_1), (downward_2)
+  * cubed sphere treecode (CSTC) ......... §7, Algorithm 1 (the comparison method)
 
 Readings taken where the paper is silent or ambiguous:
   * Cells are equiangular: a level-l cell of a face is a square of side
@@ -44,6 +45,12 @@ Readings taken where the paper is silent or ambiguous:
   * The singular self term: a source is skipped for a target exactly when
     their coordinates are equal bit for bit (the i=j rule for one point set).
   * 1 - x.y is evaluated as |x-y|^2/2 (equal on the unit sphere).
+  * CSTC: target x and source cluster C are well separated when
+    r_C^2 < MAC^2 R^2 (strict), R = chord distance from x to the centre of C.
+    A separated cluster with more than N0 points takes PC, a separated one
+    with at most N0 points takes PP; a cluster that is not separated is
+    opened into its children, and a leaf that is not separated takes PP
+    (it has no children to open).  Empty clusters are skipped.
 """
 
 import math
@@ -457,3 +464,56 @@ def fmm(targets, sources, weights, kernel, n, theta, N0, sample=None):
     """Convenience wrapper: build the trees and lists, then evaluate."""
     F = FMM(targets, sources, kernel, n, theta, N0)
     return F.evaluate(weights, sample=sample)
+
+
+# ------------------------------------------------------ CSTC (Alg. 1)
+
+def point_separated(x, S, theta):
+    """r/R < MAC for a target point x and a source cluster S (Algorithm 1)."""
+    d = x - S.center
+    R2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2]
+    return S.radius * S.radius < (theta * theta) * R2
+
+
+def treecode(targets, sources, weights, kernel, n, theta, N0, sample=None):
+    """Cubed sphere treecode (Algorithm 1): the source tree and its upward pass
+    (lines 4-5), then for every target particle a traversal from the six
+    source roots (lines 6-14): PC for separated clusters with more than N0
+    points, PP for separated small clusters and for leaves that are not
+    separated, children otherwise.  `kernel` is a kernel id or a function
+    (X, Y) -> matrix of kernel values (for tests).  Returns phi at every
+    target (or at the indices in `sample`).
+    """
+    X = np.asarray(targets, dtype=np.float64)
+    src = X if sources is None else np.asarray(sources, dtype=np.float64)
+    w = np.asarray(weights, dtype=np.float64)
+    st = Tree(src, N0, n)
+    wbar = upward_pass(st, w)
+    if callable(kernel):
+        kmat, vd = kernel, 1
+    else:
+        kmat = lambda A, B: kernel_matrix(int(kernel), A, B)  # noqa: E731
+        vd = 3 if int(kernel) == KERNEL_BIOT_SAVART else 1
+    rows = np.arange(X.shape[0]) if sample is None else np.asarray(sample)
+    out = np.zeros((rows.shape[0], vd))
+    for r, i in enumerate(rows):
+        x = X[i]
+        acc = np.zeros(vd)
+        stack = list(reversed(st.levels[0]))
+        while stack:
+            S = stack.pop()
+            if S.count == 0:
+                continue
+            sep = point_separated(x, S, theta)
+            if sep and S.count > st.N0:
+                K = kmat(x[None, :], S.proxies)
+                acc += np.tensordot(K[0], wbar[S.id].reshape(-1), axes=([0], [0])).reshape(vd)
+            elif sep or S.is_leaf:
+                K = kmat(x[None, :], st.points[S.idx])
+                acc += np.tensordot(K[0], w[S.idx], axes=([0], [0])).reshape(vd)
+            else:
+                for ch in reversed(S.children):
+                    stack.append(ch)
+        out[r] = acc
+    return out[:, 0] if vd == 1 else out
+
