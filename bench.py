@@ -147,6 +147,28 @@ def kernel_table(cs, torch, T, W, N, p, theta, leaf, S, steps):
     return table
 
 
+def treecode_line(cs, torch, T, W, N, p, theta, leaf, S, ref_s, steps=5):
+    """The cubed sphere treecode (Algorithm 1, FP64) on the headline geometry,
+    beside the FP64 CSFMM eval on the same plan (the paper compares the two)."""
+    plan = cs.Plan(T, None, kernel=cs.POISSON, p=p, theta=theta, leaf_size=leaf)
+    res = {}
+    for name, fn in (("cstc", plan.eval_treecode), ("csfmm", plan.eval)):
+        out = fn(W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn(W, out=out)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        d = out[S] - ref_s
+        res[name] = {"ms": ms, "rel_l2_err": float(torch.sqrt(torch.sum(d * d) /
+                                                              torch.sum(ref_s * ref_s)))}
+    plan.close()
+    res["form"] = "fp64"
+    res["csfmm_speedup"] = res["cstc"]["ms"] / res["csfmm"]["ms"]
+    return res
+
+
 def cpu_baseline(P, w, seconds):
     """The direct-sum oracle on the host cores, on a bounded sample of targets."""
     from oracle import direct, oracle_threads
@@ -465,6 +487,7 @@ def main():
         line["fp32_over_fp64_speedup"] = f64["ms"] / f32["ms"]
         line["gpu_direct_rate"] = direct_rate
         line["kernels"] = kernel_table(cs, torch, T, W, N, head["p"], theta, leaf, S, 10)
+        line["treecode"] = treecode_line(cs, torch, T, W, N, head["p"], theta, leaf, S, ref_s)
     if not args.no_cpu_baseline and not args.quick:
         line["cpu_baseline"] = cpu_baseline(P, w, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -126,6 +126,24 @@ int csfmm_eval_kernel(csfmm_plan_t plan, int kernel_id, const double* weights, d
                       void* stream);
 
 /*
+ * Cubed sphere treecode (paper §7, Algorithm 1), the paper's O(N log N)
+ * comparison method, on the plan's source tree: the upward pass (P2M, M2M)
+ * as in csfmm_eval, then for every target particle x a traversal of the
+ * source tree from the six roots: a cluster with r^2 < theta^2 R^2 (r its
+ * radius, R the chord distance from x to its centre) and more than leaf_size
+ * points interacts by PC (eq. PC, its proxies and proxy weights); a separated
+ * cluster with at most leaf_size points, or a leaf that is not separated, by
+ * PP (eq. PP, its particles, exact coincidences omitted); other clusters are
+ * opened into their children.  Always FP64, whatever the plan's flags.
+ *   weights [n_s] device, out [n_t] or [n_t][3] device (caller order).
+ * Asynchronous on `stream`; uses the plan's own workspace, so it must not
+ * overlap a csfmm_eval of the same plan.
+ * Errors: CSFMM_E_INVALID (NULL pointer, kernel id), CSFMM_E_HIP.
+ */
+int csfmm_eval_treecode(csfmm_plan_t plan, int kernel_id, const double* weights, double* out,
+                        void* stream);
+
+/*
  * Direct sum of paper eq. (nbodysum) over all pairs (the O(N^2) method of §1):
  * out[i] = sum_j K(x_i, y_j) w_j with exact coincidences omitted.
  *   targets [n_t][3], sources [n_s][3], weights [n_s], out [n_t] or [n_t][3].

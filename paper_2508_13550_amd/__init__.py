@@ -68,6 +68,7 @@ EXPORTED = (
     "csfmm_plan_proxies", "csfmm_plan_permutation", "csfmm_plan_list", "csfmm_eval_stages",
     "csfmm_plan_timing", "csfmm_plan_timing_read", "csfmm_workspace_create",
     "csfmm_workspace_destroy", "csfmm_workspace_bytes", "csfmm_eval_many",
+    "csfmm_eval_treecode",
 )
 
 STAGES = ("p2m", "m2m", "near_pp", "pc_far", "l2l", "l2p")
@@ -88,6 +89,7 @@ def load_library(path=LIB_PATH):
     L.csfmm_eval.argtypes = [vp, dp, dp, vp]
     L.csfmm_eval_kernel.argtypes = [vp, ctypes.c_int, dp, dp, vp]
     L.csfmm_eval_stages.argtypes = [vp, ctypes.c_int, dp, dp, dp, dp, dp, vp]
+    L.csfmm_eval_treecode.argtypes = [vp, ctypes.c_int, dp, dp, vp]
     L.csfmm_direct.argtypes = [dp, i64, dp, i64, dp, ctypes.c_int, ctypes.c_uint, dp, vp]
     L.csfmm_plan_destroy.argtypes = [vp]
     L.csfmm_plan_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -196,6 +198,14 @@ class Plan:
         w = _vec(weights, self.n_s, "weights")
         out = self._out(k, out)
         _check(_lib.csfmm_eval_kernel(self.handle, k, w.data_ptr(), out.data_ptr(), _stream()))
+        return out
+
+    def eval_treecode(self, weights, kernel=None, out=None):
+        """csfmm_eval_treecode: the cubed sphere treecode (Algorithm 1), FP64."""
+        k = self.kernel if kernel is None else int(kernel)
+        w = _vec(weights, self.n_s, "weights")
+        out = self._out(k, out)
+        _check(_lib.csfmm_eval_treecode(self.handle, k, w.data_ptr(), out.data_ptr(), _stream()))
         return out
 
     def eval_stages(self, weights, kernel=None):

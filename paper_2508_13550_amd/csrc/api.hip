@@ -123,6 +123,20 @@ int csfmm_eval(csfmm_plan_t plan, const double* weights, double* out, void* stre
     return csfmm_eval_stages(plan, plan->kernel, weights, out, nullptr, nullptr, nullptr, stream);
 }
 
+int csfmm_eval_treecode(csfmm_plan_t plan, int kernel_id, const double* weights, double* out,
+                        void* stream) {
+    clear_error();
+    if (!plan || !weights || !out) {
+        set_error("plan, weights and out must be non-NULL");
+        return CSFMM_E_INVALID;
+    }
+    if (!valid_kernel(kernel_id)) {
+        set_error("unknown kernel id %d", kernel_id);
+        return CSFMM_E_INVALID;
+    }
+    return run_treecode(plan, kernel_id, weights, out, static_cast<hipStream_t>(stream));
+}
+
 int csfmm_direct(const double* targets, int64_t n_t, const double* sources, int64_t n_s,
                  const double* weights, int kernel_id, unsigned flags, double* out, void* stream) {
     clear_error();

@@ -269,9 +269,27 @@ struct EvalReq {
 int run_eval_batch(const EvalReq* reqs, int n, hipStream_t s);
 int run_eval(csfmm_plan_s* P, int kernel, const double* weights, double* out, double* wbar_out,
              double* psi_out, double* near_out, hipStream_t s);
+// upward pass on the plan's source tree, then the treecode (Algorithm 1)
+int run_treecode(csfmm_plan_s* P, int kernel, const double* weights, double* out, hipStream_t s);
 
 // ---- tile engine (tile.hip): b holds requests of one kernel and form
 int launch_tile_batch(const Batch& b, int kernel, bool fp32, hipStream_t s);
+
+// Cubed sphere treecode (paper §7, Algorithm 1): one traversal of the source
+// tree per target particle, FP64.
+struct TcArgs {
+    const double *tx, *ty, *tz;  // targets (sorted order of the target tree)
+    const int32_t* tperm;        // sorted position -> caller index
+    int64_t nt;
+    const int32_t *sbegin, *scount, *schild0;  // source tree cells
+    const double *scenter, *sradius;
+    const double *sx, *sy, *sz, *sw;  // sorted source points and weights
+    const double *sprox, *swbar;      // proxies [cell][3][KS], proxy weights [cell][KS]
+    int K, KS, N0, nroots;            // roots are cells 0 .. nroots-1
+    double theta2;                    // MAC^2
+    double* out;                      // [nt] or [nt][3], caller order
+};
+int launch_treecode(const TcArgs& a, int kernel, hipStream_t s);
 int launch_direct(const double* tgt, int64_t nt, const double* src, int64_t ns, const double* w,
                   int kernel, bool fp32, double* out, hipStream_t s);
 

@@ -360,7 +360,61 @@ int launch_batched(Batch& b, const int64_t* blocks, F&& launch) {
 
 int64_t mfma_tiles(int64_t nrows, int nb) { return ((nrows + 15) / 16) * (nb / 16); }
 
-int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
+#define RCX(x)                              \
+    do {                                    \
+        int rc_ = (x);                      \
+        if (rc_ != CSFMM_OK) return rc_;    \
+    } while (0)
+
+// e1: sorted weights of every request of the batch
+int launch_gather(Batch& b, const EvalReq* reqs, int n, hipStream_t s) {
+    int64_t blk[kMaxBatch];
+    for (int r = 0; r < n; ++r) blk[r] = (reqs[r].plan->ns + 255) / 256;
+    return launch_batched(b, blk, [&](unsigned g) { k_gather_w<<<g, 256, 0, s>>>(b); });
+}
+
+// e2 P2M at the source leaves, grouped by degree (P1 is a template parameter)
+int launch_p2m(Batch& b, const EvalReq* reqs, int n, hipStream_t s) {
+    int64_t blk[kMaxBatch];
+    for (int P1 = 2; P1 <= kMaxP1; ++P1) {
+        bool any = false;
+        for (int r = 0; r < n; ++r) {
+            blk[r] = reqs[r].plan->p + 1 == P1 ? reqs[r].plan->st->nleaves : 0;
+            any = any || blk[r] > 0;
+        }
+        if (!any) continue;
+        switch (P1) {
+#define X(Q)                                                                                   \
+    case Q:                                                                                    \
+        RCX(launch_batched(b, blk, [&](unsigned g) { k_p2m<Q><<<g, 64, 0, s>>>(b); }));    \
+        break;
+            CSFMM_P1_CASES(X)
+#undef X
+            default: break;
+        }
+    }
+    return CSFMM_OK;
+}
+
+// e3 M2M by levels, deepest parents first
+int launch_m2m(Batch& b, const EvalReq* reqs, int n, hipStream_t s) {
+    int64_t blk[kMaxBatch];
+    int maxd = 0;
+    for (int r = 0; r < n; ++r) maxd = std::max(maxd, int(reqs[r].plan->st->depth));
+    for (int l = maxd - 1; l >= 0; --l) {
+        for (int r = 0; r < n; ++r) {
+            const Tree& S = *reqs[r].plan->st;
+            const int np = l < S.depth ? S.parents_begin[l + 1] - S.parents_begin[l] : 0;
+            b.a0[r] = l < S.depth ? S.parents_begin[l] : 0;
+            b.a1[r] = np;
+            blk[r] = mfma_tiles(np, reqs[r].plan->nb1);
+        }
+        RCX(launch_batched(b, blk, [&](unsigned g) { k_mfma_pass<0><<<g, 256, 0, s>>>(b); }));
+    }
+    return CSFMM_OK;
+}
+
+Batch batch_of(const EvalReq* reqs, int n) {
     Batch b{};
     b.n = n;
     for (int r = 0; r < n; ++r) {
@@ -369,6 +423,11 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         b.out[r] = reqs[r].out;
         b.vd[r] = reqs[r].kernel == CSFMM_K_BIOT_SAVART ? 3 : 1;
     }
+    return b;
+}
+
+int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
+    Batch b = batch_of(reqs, n);
     int64_t blk[kMaxBatch];
     // optional stage timing (single request)
     hipEvent_t* ev = nullptr;
@@ -388,15 +447,9 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         if (ev) CSFMM_HIP_TRY(hipEventRecord(ev[k], k < Timing::kMain ? s : side));
         return CSFMM_OK;
     };
-#define RCX(x)                              \
-    do {                                    \
-        int rc_ = (x);                      \
-        if (rc_ != CSFMM_OK) return rc_;    \
-    } while (0)
     RCX(mark(0));
     // e1 gather
-    for (int r = 0; r < n; ++r) blk[r] = (reqs[r].plan->ns + 255) / 256;
-    RCX(launch_batched(b, blk, [&](unsigned g) { k_gather_w<<<g, 256, 0, s>>>(b); }));
+    RCX(launch_gather(b, reqs, n, s));
     // e4 PP near field on the side stream, concurrent with e2-e6: it needs
     // the gathered weights only; one launch per (kernel, form) group
     std::map<std::pair<int, int>, std::vector<int>> groups;
@@ -440,40 +493,10 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         return CSFMM_OK;
     };
     RCX(launch_pp());
-    // e2 P2M
-    for (int r = 0; r < n; ++r) blk[r] = reqs[r].plan->st->nleaves;
-    // grouped by degree (P1 is a template parameter)
-    for (int P1 = 2; P1 <= kMaxP1; ++P1) {
-        bool any = false;
-        for (int r = 0; r < n; ++r) {
-            blk[r] = reqs[r].plan->p + 1 == P1 ? reqs[r].plan->st->nleaves : 0;
-            any = any || blk[r] > 0;
-        }
-        if (!any) continue;
-        switch (P1) {
-#define X(Q)                                                                                   \
-    case Q:                                                                                    \
-        RCX(launch_batched(b, blk, [&](unsigned g) { k_p2m<Q><<<g, 64, 0, s>>>(b); }));    \
-        break;
-            CSFMM_P1_CASES(X)
-#undef X
-            default: break;
-        }
-    }
+    // e2 P2M, e3 M2M
+    RCX(launch_p2m(b, reqs, n, s));
     RCX(mark(1));
-    // e3 M2M, deepest parents first
-    int maxd = 0;
-    for (int r = 0; r < n; ++r) maxd = std::max(maxd, int(reqs[r].plan->st->depth));
-    for (int l = maxd - 1; l >= 0; --l) {
-        for (int r = 0; r < n; ++r) {
-            const Tree& S = *reqs[r].plan->st;
-            const int np = l < S.depth ? S.parents_begin[l + 1] - S.parents_begin[l] : 0;
-            b.a0[r] = l < S.depth ? S.parents_begin[l] : 0;
-            b.a1[r] = np;
-            blk[r] = mfma_tiles(np, reqs[r].plan->nb1);
-        }
-        RCX(launch_batched(b, blk, [&](unsigned g) { k_mfma_pass<0><<<g, 256, 0, s>>>(b); }));
-    }
+    RCX(launch_m2m(b, reqs, n, s));
     // zero the proxy potentials (CP + CC accumulate into them)
     for (int r = 0; r < n; ++r)
         blk[r] = (int64_t(b.vd[r]) * reqs[r].ws->dview_host.psi_stride + 255) / 256;
@@ -528,7 +551,6 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
             }
         }
     RCX(mark(5));
-#undef RCX
     return CSFMM_OK;
 }
 
@@ -653,6 +675,40 @@ int run_eval(csfmm_plan_s* P, int kernel, const double* weights, double* out, do
         CSFMM_LAUNCH_CHECK();
     }
     return CSFMM_OK;
+}
+
+int run_treecode(csfmm_plan_s* P, int kernel, const double* weights, double* out, hipStream_t s) {
+    EvalReq q{P, P->ws0, kernel, weights, out};
+    Batch b = batch_of(&q, 1);
+    RCX(launch_gather(b, &q, 1, s));
+    RCX(launch_p2m(b, &q, 1, s));
+    RCX(launch_m2m(b, &q, 1, s));
+    const Tree& T = P->tt;
+    const Tree& S = *P->st;
+    TcArgs a{};
+    a.tx = T.x;
+    a.ty = T.y;
+    a.tz = T.z;
+    a.tperm = T.perm;
+    a.nt = P->nt;
+    a.sbegin = S.begin;
+    a.scount = S.count;
+    a.schild0 = S.child0;
+    a.scenter = S.center;
+    a.sradius = S.radius;
+    a.sx = S.x;
+    a.sy = S.y;
+    a.sz = S.z;
+    a.sw = P->ws0->ws;
+    a.sprox = S.prox;
+    a.swbar = P->ws0->wbar;
+    a.K = P->K;
+    a.KS = P->KS;
+    a.N0 = P->leaf;
+    a.nroots = S.level_begin.size() > 1 ? S.level_begin[1] : 0;
+    a.theta2 = P->theta * P->theta;
+    a.out = out;
+    return launch_treecode(a, kernel, s);
 }
 
 }  // namespace csfmm

@@ -669,6 +669,116 @@ __global__ void k_direct_reduce(const double* __restrict__ tgt, int64_t nt,
     for (int v = 0; v < VD; ++v) out[i * VD + v] = o[v];
 }
 
+// ---------------------------------------------------------------- treecode
+// Cubed sphere treecode (paper §7, Algorithm 1), FP64.  A wave owns 64
+// consecutive targets of the sorted target order (so its targets are close
+// together) and walks the source tree depth first from the six roots with a
+// stack of (cluster, lane mask) in LDS; the mask holds the lanes whose
+// traversal reaches the cluster.  At a cluster every lane decides for its own
+// target: separated (r^2 < MAC^2 R^2, R from the target to the centre) with
+// more than N0 points -> PC over the cluster's proxies; separated with at
+// most N0 points, or a leaf that is not separated -> PP over its points;
+// otherwise the cluster is opened and its non-empty children are pushed with
+// the mask of the lanes that opened it.  Each lane accumulates only its own
+// interactions, so the result is the per-target traversal of Algorithm 1.
+// Stack bound: at most 5 waiting roots and 3 waiting siblings per level below
+// them, plus 4 pushed children: 5 + 3 * 19 + 4 = 66 entries for 20 levels.
+constexpr int kTcStack = 72;
+
+__device__ __forceinline__ bool tc_separated(double x, double y, double z, const double* c,
+                                             double r, double theta2) {
+#pragma clang fp contract(off)
+    const double dx = x - c[0], dy = y - c[1], dz = z - c[2];
+    const double R2 = dx * dx + dy * dy + dz * dz;
+    return r * r < theta2 * R2;
+}
+
+template <int KERN>
+__global__ __launch_bounds__(256) void k_treecode(TcArgs a) {
+    // The coordinate scaling below must round before eval_pair subtracts: a
+    // multiply fused into the subtraction would leave the rounding residue of
+    // x * scale instead of an exact 0 for a coincident target and source.
+#pragma clang fp contract(off)
+    constexpr int VD = vdim<KERN>();
+    constexpr double scale = coord_scale<KERN>();
+    __shared__ int st_node[4][kTcStack];
+    __shared__ uint32_t st_lo[4][kTcStack], st_hi[4][kTcStack];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t i = (int64_t(blockIdx.x) * 4 + wv) * 64 + lane;
+    const bool valid = i < a.nt;
+    const double gx = valid ? a.tx[i] : 0.0, gy = valid ? a.ty[i] : 0.0,
+                 gz = valid ? a.tz[i] : 0.0;
+    TargetRegs T;
+    T.tx = gx * scale;
+    T.ty = gy * scale;
+    T.tz = gz * scale;
+    double acc[VD];
+#pragma unroll
+    for (int v = 0; v < VD; ++v) acc[v] = 0.0;
+    const uint64_t vmask = __ballot(valid);
+    int sp = 0;
+    if (vmask) {
+        for (int c = a.nroots - 1; c >= 0; --c)
+            if (a.scount[c] > 0) {
+                st_node[wv][sp] = c;
+                st_lo[wv][sp] = uint32_t(vmask);
+                st_hi[wv][sp] = uint32_t(vmask >> 32);
+                ++sp;
+            }
+    }
+    while (sp > 0) {
+        --sp;
+        const int c = __builtin_amdgcn_readfirstlane(st_node[wv][sp]);
+        // (through uint32_t: readfirstlane returns a signed int)
+        const uint64_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(st_hi[wv][sp])));
+        const uint64_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(st_lo[wv][sp])));
+        const uint64_t m = (hi << 32) | lo;
+        const bool mine = (m >> lane) & 1;
+        const int cnt = a.scount[c];
+        const int c0 = a.schild0[c];
+        const bool leaf = c0 < 0;
+        const bool sep = mine && tc_separated(gx, gy, gz, a.scenter + 3 * int64_t(c),
+                                              a.sradius[c], a.theta2);
+        const bool pc = sep && cnt > a.N0;
+        const bool pp = mine && !pc && (sep || leaf);
+        const bool op = mine && !sep && !leaf;
+        if (__ballot(pc)) {
+            const double* px = a.sprox + int64_t(c) * 3 * a.KS;
+            const double* pw = a.swbar + int64_t(c) * a.KS;
+            for (int k = 0; k < a.K; ++k) {
+                if (pc)
+                    eval_pair<KERN, false, FORM_FAR>(T, px[k] * scale, px[a.KS + k] * scale,
+                                                     px[2 * a.KS + k] * scale, 0.0, pw[k], acc);
+            }
+        }
+        if (__ballot(pp)) {
+            const int b0 = a.sbegin[c];
+            for (int j = b0; j < b0 + cnt; ++j) {
+                if (pp)
+                    eval_pair<KERN, false, FORM_CHECK>(T, a.sx[j] * scale, a.sy[j] * scale,
+                                                       a.sz[j] * scale, 0.0, a.sw[j], acc);
+            }
+        }
+        const uint64_t om = __ballot(op);
+        if (om) {
+            for (int q = 3; q >= 0; --q)
+                if (a.scount[c0 + q] > 0 && sp < kTcStack) {
+                    st_node[wv][sp] = c0 + q;
+                    st_lo[wv][sp] = uint32_t(om);
+                    st_hi[wv][sp] = uint32_t(om >> 32);
+                    ++sp;
+                }
+        }
+    }
+    if (valid) {
+        double o[VD];
+        epilogue<KERN, false>(acc, gx, gy, gz, o);
+        const int64_t dst = a.tperm[i];
+#pragma unroll
+        for (int v = 0; v < VD; ++v) a.out[dst * VD + v] = o[v];
+    }
+}
+
 template <int KERN, bool F32>
 int launch_tile_t(const Batch& b, hipStream_t s) {
     const int nblocks = b.prefix[b.n] + b.prefix2[b.n];
@@ -722,6 +832,23 @@ int launch_tile_batch(const Batch& b, int kernel, bool fp32, hipStream_t s) {
             set_error("unknown kernel id %d", kernel);
             return CSFMM_E_INVALID;
     }
+}
+
+int launch_treecode(const TcArgs& a, int kernel, hipStream_t s) {
+    const unsigned grid = unsigned((a.nt + 255) / 256);
+    if (grid == 0) return CSFMM_OK;
+    switch (kernel) {
+        case CSFMM_K_POISSON_LOG: k_treecode<1><<<grid, 256, 0, s>>>(a); break;
+        case CSFMM_K_BIOT_SAVART: k_treecode<2><<<grid, 256, 0, s>>>(a); break;
+        case CSFMM_K_INV_DIST: k_treecode<3><<<grid, 256, 0, s>>>(a); break;
+        case CSFMM_K_BIHARMONIC: k_treecode<4><<<grid, 256, 0, s>>>(a); break;
+        case CSFMM_K_SAL: k_treecode<5><<<grid, 256, 0, s>>>(a); break;
+        default:
+            set_error("unknown kernel id %d", kernel);
+            return CSFMM_E_INVALID;
+    }
+    CSFMM_LAUNCH_CHECK();
+    return CSFMM_OK;
 }
 
 int launch_direct(const double* tgt, int64_t nt, const double* src, int64_t ns, const double* w,
