@@ -56,6 +56,11 @@ def parse():
                     help="runtime vs error over degree, MAC, leaf size and form (Fig. 7 analogue)")
     ap.add_argument("--sweep-E", type=int, default=330)
     ap.add_argument("--sweep-kernels", type=int, nargs="*", default=[1, 4])
+    ap.add_argument("--table2", action="store_true",
+                    help="paper Table 2 on the icosahedral grid N=655,362 (error vs MAC, n)")
+    ap.add_argument("--table3", action="store_true",
+                    help="paper Table 3 on icosahedral grids (runtime vs N, four kernels)")
+    ap.add_argument("--table3-kmax", type=int, default=9)
     return ap.parse_args()
 
 
@@ -272,6 +277,126 @@ def sweep_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def _golden_rows(name):
+    rows = []
+    for line in open(os.path.join(ROOT, "tests", "golden", name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append(line.split())
+    return rows
+
+
+def table2_bench(args):
+    """The paper's Table 2 at its own setting: icosahedral grid N = 655,362,
+    N0 = 4 n^2, fields Y00, Y43, Y85, MAC 0.9/0.7/0.5, n = 2:2:14, FP64.
+    E(phi_FS, phi_DS) = ||phi_FS - phi_DS|| / ||phi_EX|| with area weights,
+    phi_EX = f/(n(n+1)) (Y00: its exact constant), phi_DS the GPU FP64 direct
+    sum at every point."""
+    import math
+    import torch
+    import paper_2508_13550_amd as cs
+    from workloads import icosahedral_grid, real_sph_harm_all
+
+    P, A = icosahedral_grid(8)
+    N = P.shape[0]
+    dev = torch.device("cuda:0")
+    T = torch.tensor(P, dtype=torch.float64, device=dev)
+    Y = real_sph_harm_all(P, 8)
+    y00 = 1.0 / (2.0 * math.sqrt(math.pi))
+    fields = {"Y00": (np.full(N, y00), (1.0 - math.log(2.0)) / (2.0 * math.sqrt(math.pi))),
+              "Y43": (Y[:, 4 * 4 + 4 + 3], 1.0 / 20.0),
+              "Y85": (Y[:, 8 * 8 + 8 + 5], 1.0 / 72.0)}
+    paper = {(r[0], float(r[1])): [float(v) for v in r[2:]] for r in _golden_rows("table2_full.txt")}
+    data = {}
+    for name, (f, lam) in fields.items():
+        W = torch.tensor(f * A, dtype=torch.float64, device=dev)
+        ds = cs.direct(T, T, W, kernel=cs.POISSON).cpu().numpy()
+        ex = (np.full(N, lam) if name == "Y00" else lam * f)
+        nex = math.sqrt(np.sum(ex * ex * A))
+        data[name] = (W, ds, nex, math.sqrt(np.sum((ds - ex) ** 2 * A)) / nex)
+        print("table2 direct %s done" % name, file=sys.stderr, flush=True)
+    rows = []
+    for theta in (0.9, 0.7, 0.5):
+        for n in range(2, 15, 2):
+            plan = cs.Plan(T, None, kernel=cs.POISSON, p=n, theta=theta, leaf_size=4 * n * n)
+            for name in fields:
+                W, ds, nex, _ = data[name]
+                out = plan.eval(W)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                plan.eval(W, out=out)
+                torch.cuda.synchronize()
+                ms = 1e3 * (time.perf_counter() - t0)
+                fs = out.cpu().numpy()
+                e = math.sqrt(np.sum((fs - ds) ** 2 * A)) / nex
+                pe = paper[(name, theta)][n // 2 - 1]
+                rows.append({"field": name, "theta": theta, "n": n, "leaf": 4 * n * n,
+                             "E": e, "paper_E": pe, "ratio": e / pe, "eval_ms": ms})
+            plan.close()
+            print("table2 theta %.1f n %d done" % (theta, n), file=sys.stderr, flush=True)
+    line = {"metric": "paper Table 2: E(phi_FS, phi_DS) vs MAC and degree (FP64)",
+            "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": "icosahedral grid k=8 (N=%d), N0=4n^2, Poisson kernel" % N},
+            "discretization_error": {k: v[3] for k, v in data.items()}, "rows": rows}
+    print(json.dumps(line), flush=True)
+
+
+def table3_bench(args):
+    """The paper's Table 3 on one MI355X: icosahedral grids N = 10*4^k + 2,
+    k = 4..9, MAC 0.7, n = 6, N0 = 4n^2 = 144, four kernels.  CSFMM: mean of
+    3 evals (FP64 and FP32 form); direct: the GPU direct sum timed on 8,192
+    targets against all N sources and scaled by N/8,192 (its cost is linear in
+    the number of targets)."""
+    import torch
+    import paper_2508_13550_amd as cs
+    from workloads import icosahedral_grid, real_y43
+
+    kernels = {"laplace": cs.POISSON, "biharmonic": cs.BIHARMONIC,
+               "biot_savart": cs.BIOT_SAVART, "sal": cs.SAL}
+    paper = {(r[0], r[1]): [float(v) for v in r[2:]] for r in _golden_rows("table3_runtimes.txt")}
+    dev = torch.device("cuda:0")
+    rows = []
+    for k in range(4, args.table3_kmax + 1):
+        P, A = icosahedral_grid(k)
+        N = P.shape[0]
+        T = torch.tensor(P, dtype=torch.float64, device=dev)
+        W = torch.tensor(real_y43(P) * A, dtype=torch.float64, device=dev)
+        nsub = min(N, 8192)
+        Ts = T[:nsub].contiguous()
+        for name, kid in kernels.items():
+            row = {"N": N, "kernel": name}
+            for fp32 in (False, True):
+                plan = cs.Plan(T, None, kernel=kid, p=6, theta=0.7, leaf_size=144, fp32=fp32)
+                out = plan.eval(W)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(3):
+                    plan.eval(W, out=out)
+                torch.cuda.synchronize()
+                row["csfmm_%s_s" % ("fp32" if fp32 else "fp64")] = (time.perf_counter() - t0) / 3
+                plan.close()
+                cs.direct(Ts, T, W, kernel=kid, fp32=fp32)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                cs.direct(Ts, T, W, kernel=kid, fp32=fp32)
+                torch.cuda.synchronize()
+                row["direct_%s_s" % ("fp32" if fp32 else "fp64")] = \
+                    (time.perf_counter() - t0) * N / nsub
+            col = k - 4
+            row["paper_direct_s"] = paper[("direct", name)][col]
+            row["paper_csfmm_s"] = paper[("csfmm", name)][col]
+            row["speedup_vs_paper_csfmm_fp64"] = row["paper_csfmm_s"] / row["csfmm_fp64_s"]
+            row["speedup_vs_paper_csfmm_fp32"] = row["paper_csfmm_s"] / row["csfmm_fp32_s"]
+            rows.append(row)
+            print("table3 N %d %s done" % (N, name), file=sys.stderr, flush=True)
+    line = {"metric": "paper Table 3: runtime (s) vs N, direct and CSFMM, four kernels",
+            "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": "icosahedral grids k=4..%d, MAC 0.7, n=6, N0=144, "
+                                   "f = Re Y_4^3" % args.table3_kmax},
+            "rows": rows}
+    print(json.dumps(line), flush=True)
+
+
 def serve_bench(args):
     """Serving stream: requests of mixed resolution, kernel and degree arriving
     as a Poisson process at rho x capacity; continuous batching on one GPU."""
@@ -391,6 +516,12 @@ def main():
         return
     if args.sweep:
         sweep_bench(args)
+        return
+    if args.table2:
+        table2_bench(args)
+        return
+    if args.table3:
+        table3_bench(args)
         return
     import torch
     import paper_2508_13550_amd as cs

@@ -7,12 +7,15 @@ GPU library's tests and the CPU oracle can take their inputs from here.
 """
 
 from .grid import cubed_sphere_grid, random_sphere_points
+from .meshes import icosahedral_grid, latlon_grid
 from .sph import real_sph_harm_all, real_y43, real_y41, bandlimited_field
 from .configs import CONFIGS, make_config, config_subset
 
 __all__ = [
     "cubed_sphere_grid",
     "random_sphere_points",
+    "icosahedral_grid",
+    "latlon_grid",
     "real_sph_harm_all",
     "real_y43",
     "real_y41",
