@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--table3", action="store_true",
                     help="paper Table 3 on icosahedral grids (runtime vs N, four kernels)")
     ap.add_argument("--table3-kmax", type=int, default=9)
+    ap.add_argument("--bve", action="store_true",
+                    help="barotropic vorticity equation, Rossby-Haurwitz wave, RK4 (paper §12)")
+    ap.add_argument("--bve-k", type=int, default=7)
     return ap.parse_args()
 
 
@@ -397,6 +400,54 @@ def table3_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def bve_bench(args):
+    """The paper's §12 Rossby-Haurwitz run: icosahedral particles (k = 7:
+    N = 163,842), RK4 with dt = 0.01 day to t = 1 day, velocity by CSFMM
+    (MAC 0.7, n = 6, leaf 4n^2; FP64 and the FP32 form) and by the FP64 direct
+    sum (timed over the first 10 steps, error after 100); every stage rebuilds
+    the plan.  Reports time per step and E_zeta at 1 day (eq. bveerr)."""
+    import torch
+    import paper_2508_13550_amd as cs
+    from workloads import icosahedral_grid, rh_vorticity
+
+    def vorticity_error(x, z):   # eq. (bveerr) against the stationary wave
+        z0 = rh_vorticity(x)
+        return float(np.sqrt(np.sum((z - z0) ** 2 * A) / np.sum(z0 ** 2 * A)))
+
+    P, A = icosahedral_grid(args.bve_k)
+    N = P.shape[0]
+    a = torch.tensor(A, dtype=torch.float64, device="cuda")
+    runs = {}
+    for name, kw in (("csfmm_fp64", dict(fp32=False, use_direct=False)),
+                     ("csfmm_fp32", dict(fp32=True, use_direct=False)),
+                     ("direct_fp64", dict(fp32=False, use_direct=True))):
+        x = torch.tensor(P, dtype=torch.float64, device="cuda")
+        z = torch.tensor(rh_vorticity(P), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t10 = None
+        for step in range(100):
+            cs.bve_rk4_step(x, z, a, 0.01, p=6, theta=0.7, leaf_size=144, **kw)
+            if step == 9:
+                torch.cuda.synchronize()
+                t10 = time.perf_counter() - t0
+            if (step + 1) % 20 == 0:
+                print("bve %s step %d" % (name, step + 1), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        e = vorticity_error(x.cpu().numpy(), z.cpu().numpy())
+        runs[name] = {"s_per_step": total / 100, "s_per_step_first10": t10 / 10,
+                      "E_zeta_1day": e}
+    line = {"metric": "BVE Rossby-Haurwitz wave: time per RK4 step and E_zeta at 1 day",
+            "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": "icosahedral k=%d (N=%d), dt=0.01 day, 100 steps, "
+                                   "MAC 0.7, n=6, leaf 144" % (args.bve_k, N)},
+            "runs": runs,
+            "csfmm_speedup_over_direct": runs["direct_fp64"]["s_per_step"] /
+            runs["csfmm_fp64"]["s_per_step"]}
+    print(json.dumps(line), flush=True)
+
+
 def serve_bench(args):
     """Serving stream: requests of mixed resolution, kernel and degree arriving
     as a Poisson process at rho x capacity; continuous batching on one GPU."""
@@ -522,6 +573,9 @@ def main():
         return
     if args.table3:
         table3_bench(args)
+        return
+    if args.bve:
+        bve_bench(args)
         return
     import torch
     import paper_2508_13550_amd as cs

@@ -144,6 +144,24 @@ int csfmm_eval_treecode(csfmm_plan_t plan, int kernel_id, const double* weights,
                         void* stream);
 
 /*
+ * One classical 4th order Runge-Kutta step of the barotropic vorticity
+ * equation on the rotating sphere by the Lagrangian vortex method (paper
+ * §2.3, eqs. BVE and BVE_ODEs; §12): dx_i/dt = sum_j K_BS(x_i, x_j) zeta_j A_j
+ * and dzeta_i/dt = -2 omega dz_i/dt.  Every stage builds a plan on the stage
+ * positions (kernel Biot-Savart, p, theta, leaf_size, flags as in csfmm_plan)
+ * and evaluates with it, or uses csfmm_direct when use_direct != 0; stage and
+ * final positions are projected back onto the sphere.
+ *   x [n][3] (unit vectors) and zeta [n]: device, updated in place;
+ *   area [n] device (the particles' fixed areas A_i); dt > 0; omega the
+ *   rotation rate (2 pi per day in the paper's units).
+ * Waits for `stream` after each stage eval (plans are rebuilt per stage).
+ * Errors: CSFMM_E_INVALID, CSFMM_E_NOT_ON_SPHERE, CSFMM_E_OOM, CSFMM_E_HIP.
+ */
+int csfmm_bve_rk4_step(double* x, double* zeta, const double* area, int64_t n, double dt,
+                       double omega, int p, double theta, int leaf_size, unsigned flags,
+                       int use_direct, void* stream);
+
+/*
  * Direct sum of paper eq. (nbodysum) over all pairs (the O(N^2) method of §1):
  * out[i] = sum_j K(x_i, y_j) w_j with exact coincidences omitted.
  *   targets [n_t][3], sources [n_s][3], weights [n_s], out [n_t] or [n_t][3].

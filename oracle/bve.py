@@ -5,12 +5,13 @@ eqs. BVE and BVE_ODEs; §12) by the Lagrangian vortex method, stepped with the
 classical 4th order Runge-Kutta method, the velocity from the FP64 direct-sum
 oracle.  Plain NumPy; shares no code with the GPU library.
 
+The Rossby-Haurwitz initial vorticity is an input and comes from the
+workloads package (with theta of eq. RH_initial read as the latitude: the
+solid-body term is then the rotation omega = pi/7 per day = Omega/14 that
+makes the degree-5 wave stationary for Omega = 2 pi per day, phase speed
+(n(n+1) omega - 2(Omega + omega))/(n(n+1)) = 0 for n = 5).
+
 Readings:
-  * In the Rossby-Haurwitz initial vorticity (eq. RH_initial) theta is the
-    latitude (z = sin theta): the solid-body term (2 pi/7) sin theta is then
-    the rotation rate omega = pi/7 per day = Omega/14 that makes the degree-5
-    wave stationary for Omega = 2 pi per day (phase speed
-    (n(n+1) omega - 2(Omega + omega))/(n(n+1)) = 0 for n = 5).
   * Particles stay on the sphere: after every Runge-Kutta stage and step the
     positions are projected back onto it (x / |x|).
   * No remeshing: the particles keep their areas A_j (the flow is
@@ -19,18 +20,12 @@ Readings:
 
 import numpy as np
 
+from workloads import rh_vorticity
+
 from .direct import direct
 
 KERNEL_BIOT_SAVART = 2
 OMEGA = 2.0 * np.pi  # per day
-
-
-def rh_vorticity(P):
-    """eq. (RH_initial): (2 pi/7) sin(lat) + 30 sin(lat) cos(lat)^4 cos(4 lon)."""
-    P = np.asarray(P, dtype=np.float64)
-    lat = np.arcsin(np.clip(P[:, 2], -1.0, 1.0))
-    lon = np.arctan2(P[:, 1], P[:, 0])
-    return (2.0 * np.pi / 7.0) * np.sin(lat) + 30.0 * np.sin(lat) * np.cos(lat) ** 4 * np.cos(4.0 * lon)
 
 
 def _project(x):

@@ -68,7 +68,7 @@ EXPORTED = (
     "csfmm_plan_proxies", "csfmm_plan_permutation", "csfmm_plan_list", "csfmm_eval_stages",
     "csfmm_plan_timing", "csfmm_plan_timing_read", "csfmm_workspace_create",
     "csfmm_workspace_destroy", "csfmm_workspace_bytes", "csfmm_eval_many",
-    "csfmm_eval_treecode",
+    "csfmm_eval_treecode", "csfmm_bve_rk4_step",
 )
 
 STAGES = ("p2m", "m2m", "near_pp", "pc_far", "l2l", "l2p")
@@ -90,6 +90,9 @@ def load_library(path=LIB_PATH):
     L.csfmm_eval_kernel.argtypes = [vp, ctypes.c_int, dp, dp, vp]
     L.csfmm_eval_stages.argtypes = [vp, ctypes.c_int, dp, dp, dp, dp, dp, vp]
     L.csfmm_eval_treecode.argtypes = [vp, ctypes.c_int, dp, dp, vp]
+    L.csfmm_bve_rk4_step.argtypes = [dp, dp, dp, i64, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_uint,
+                                     ctypes.c_int, vp]
     L.csfmm_direct.argtypes = [dp, i64, dp, i64, dp, ctypes.c_int, ctypes.c_uint, dp, vp]
     L.csfmm_plan_destroy.argtypes = [vp]
     L.csfmm_plan_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -361,6 +364,24 @@ def eval_many(requests, outs=None):
         OP[i] = o.data_ptr()
     _check(_lib.csfmm_eval_many(n, P, W, K, WP, OP, _stream()))
     return res
+
+
+def bve_rk4_step(x, zeta, area, dt, omega=2.0 * 3.141592653589793, p=6, theta=0.7,
+                 leaf_size=128, fp32=False, use_direct=False):
+    """csfmm_bve_rk4_step: one RK4 step of the barotropic vorticity equation;
+    x [n,3] and zeta [n] (float64, on the GPU) are updated in place."""
+    _require_gpu()
+    xp = _points(x, "x")
+    n = xp.shape[0]
+    z = _vec(zeta, n, "zeta")
+    a = _vec(area, n, "area")
+    if xp.data_ptr() != x.data_ptr() or z.data_ptr() != zeta.data_ptr():
+        raise ValueError("x and zeta must be contiguous float64 CUDA tensors (updated in place)")
+    _check(_lib.csfmm_bve_rk4_step(xp.data_ptr(), z.data_ptr(), a.data_ptr(), n, float(dt),
+                                   float(omega), int(p), float(theta), int(leaf_size),
+                                   FP32_FORM if fp32 else FP64, 1 if use_direct else 0,
+                                   _stream()))
+    return x, zeta
 
 
 def direct(targets, sources, weights, kernel=POISSON, fp32=False, out=None):

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcsfmm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "plan.hip", "eval.hip", "tile.hip", "sort_scan.hip", "sched.cpp"]
+SOURCES = ["api.hip", "plan.hip", "eval.hip", "tile.hip", "sort_scan.hip", "bve.hip", "sched.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

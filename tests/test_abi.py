@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     txt = open(os.path.join(ROOT, "include", "csfmm.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(csfmm_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(csfmm_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_header_declares_the_boundary():
@@ -72,3 +72,13 @@ def test_other_argument_errors():
     b1 = L.csfmm_estimate_bytes(393216, 0, 8, 128, 0)
     b2 = L.csfmm_estimate_bytes(6291456, 6291456, 10, 128, 1)
     assert 0 < b1 < b2 < 64 * 2 ** 30
+
+
+def test_bve_argument_errors():
+    L = cs.load_library()
+    f = L.csfmm_bve_rk4_step
+    assert f(None, None, None, 10, 0.01, 6.28, 6, 0.7, 64, 0, 0, None) == -1
+    assert f(1, 1, 1, 0, 0.01, 6.28, 6, 0.7, 64, 0, 0, None) == -1
+    assert f(1, 1, 1, 10, 0.0, 6.28, 6, 0.7, 64, 0, 0, None) == -1
+    assert f(1, 1, 1, 10, 0.01, 6.28, 6, 0.7, 64, 8, 0, None) == -1
+    assert "bve" in L.csfmm_last_error().decode() or "flags" in L.csfmm_last_error().decode()

@@ -8,6 +8,7 @@ GPU library's tests and the CPU oracle can take their inputs from here.
 
 from .grid import cubed_sphere_grid, random_sphere_points
 from .meshes import icosahedral_grid, latlon_grid
+from .flows import rh_vorticity
 from .sph import real_sph_harm_all, real_y43, real_y41, bandlimited_field
 from .configs import CONFIGS, make_config, config_subset
 
@@ -16,6 +17,7 @@ __all__ = [
     "random_sphere_points",
     "icosahedral_grid",
     "latlon_grid",
+    "rh_vorticity",
     "real_sph_harm_all",
     "real_y43",
     "real_y41",
