@@ -241,16 +241,19 @@ int csfmm_plan_stats(csfmm_plan_t plan, csfmm_stats* s);
 
 /*
  * Per-stage timing of csfmm_eval with HIP events recorded on the eval's
- * stream.  enable != 0 turns it on (and resets the sums), 0 turns it off.
+ * streams.  enable = 1 times every stage, 2 only the PP launch (its events
+ * are on the side stream, so the eval stream gets no extra work; the other
+ * sums stay 0), 0 turns timing off; turning it on resets the sums.
  * csfmm_plan_timing_read waits for the recorded events and returns the summed
- * milliseconds of the 6 stages over the timed evals:
+ * milliseconds of the 5 stages over the timed evals:
  *   [0] weight gather + P2M, [1] M2M (and zeroing the proxy potentials),
  *   [2] the PP near-field launch, which runs on the workspace's side stream
- *   concurrently with [0]-[4], [3] PC near field and CP + CC far field in one
- *   launch, [4] L2L, [5] L2P + scatter, including the wait for [2].
+ *   concurrently with [0], [1] and [3], [3] PC near field and CP + CC far
+ *   field in one launch, [4] L2L + L2P + scatter in one launch, including the
+ *   wait for [2].
  */
 int csfmm_plan_timing(csfmm_plan_t plan, int enable);
-int csfmm_plan_timing_read(csfmm_plan_t plan, double* stage_ms /*[6]*/, int64_t* n_evals);
+int csfmm_plan_timing_read(csfmm_plan_t plan, double* stage_ms /*[5]*/, int64_t* n_evals);
 
 /* Upper estimate of the device bytes a plan of these sizes holds (for
  * admission control); -1 on bad arguments. */
@@ -293,7 +296,10 @@ int csfmm_plan_list(csfmm_plan_t plan, int kind, int32_t* tgt, int32_t* src, int
 /* Eval that also copies the stage results to DEVICE buffers (NULL skips);
  * KS = (p+1)^2 rounded up to a multiple of 4 (the entries past (p+1)^2 are 0):
  *   wbar [n_cells_s][KS]        proxy weights after the upward pass
- *   psi  [vdim][n_cells_t][KS]  proxy potentials after the downward pass
+ *   psi  [vdim][n_cells_t][KS]  proxy potentials: at the target leaves after the
+ *                               downward pass (eq. downward_2 through all levels),
+ *                               at the other cells their own CP + CC sums
+ *                               (eq. CP_CC_accumulated)
  *   near [n_t][vdim] PP+PC part of phi in the caller's order
  * where vdim = 3 for Biot-Savart, else 1. */
 int csfmm_eval_stages(csfmm_plan_t plan, int kernel_id, const double* weights, double* out,

@@ -71,7 +71,7 @@ EXPORTED = (
     "csfmm_eval_treecode", "csfmm_bve_rk4_step",
 )
 
-STAGES = ("p2m", "m2m", "near_pp", "pc_far", "l2l", "l2p")
+STAGES = ("p2m", "m2m", "near_pp", "pc_far", "l2l_l2p")
 
 
 def load_library(path=LIB_PATH):
@@ -234,8 +234,10 @@ class Plan:
         return s.as_dict()
 
     def timing(self, enable=True):
-        """Turn per-stage event timing on (resetting the sums) or off."""
-        _check(_lib.csfmm_plan_timing(self.handle, 1 if enable else 0))
+        """Per-stage event timing: True/1 every stage, 2 the PP launch only
+        (nothing recorded on the eval stream), False/0 off; on resets the sums."""
+        level = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
+        _check(_lib.csfmm_plan_timing(self.handle, level))
 
     def timing_read(self):
         """(number of timed evals, {stage: summed ms}) for the evals since timing(True)."""

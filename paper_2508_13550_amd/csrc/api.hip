@@ -271,7 +271,11 @@ int csfmm_plan_timing(csfmm_plan_t plan, int enable) {
         set_error("plan is NULL");
         return CSFMM_E_INVALID;
     }
-    return timing_enable(plan, enable != 0);
+    if (enable < 0 || enable > 2) {
+        set_error("timing: enable must be 0, 1 or 2 (got %d)", enable);
+        return CSFMM_E_INVALID;
+    }
+    return timing_enable(plan, enable);
 }
 
 int csfmm_plan_timing_read(csfmm_plan_t plan, double* stage_ms, int64_t* n_evals) {

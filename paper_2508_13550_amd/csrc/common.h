@@ -88,6 +88,7 @@ struct Tree {
     // cells
     int32_t *level = nullptr, *face = nullptr, *ci = nullptr, *cj = nullptr;
     int32_t *begin = nullptr, *count = nullptr, *child0 = nullptr;
+    int32_t* parent = nullptr;  // -1 for the six roots
     double* center = nullptr;  // [ncells][3]
     double* radius = nullptr;  // [ncells]
     double* prox = nullptr;    // [ncells][3][KS] proxy coordinates (SoA per cell)
@@ -112,7 +113,7 @@ struct Lists {
 // size an eval kernel needs about one request.
 struct ReqView {
     // target tree
-    const int32_t *t_begin, *t_count, *t_child0, *t_leaves, *t_parents, *t_perm;
+    const int32_t *t_begin, *t_count, *t_child0, *t_parent, *t_leaves, *t_parents, *t_perm;
     const double *t_x, *t_y, *t_z, *t_u, *t_v, *t_center, *t_prox;
     // source tree
     const int32_t *s_begin, *s_count, *s_child0, *s_leaves, *s_parents, *s_perm;
@@ -122,11 +123,11 @@ struct ReqView {
     const int32_t* src[4];
     const int32_t *novl, *far_targets;
     // fixed operators
-    const double *bm2m, *bl2l;
+    const double *bm2m, *lag1d;
     // workspace
     double *ws, *wbar, *psi, *phinear, *phipc;
     int64_t nt, ns, psi_stride;
-    int32_t p, K, KS, nb1, nb2;
+    int32_t p, K, KS, nb1;
 };
 
 // Kernel argument of every eval launch: up to kMaxBatch requests; block b of
@@ -189,22 +190,21 @@ struct csfmm_plan_s {
     csfmm::Lists lists;
     // fixed interpolation operators (MFMA B operands)
     double* bm2m = nullptr;  // [4*KS][NB1], NB1 = roundup(KS,16)
-    double* bl2l = nullptr;  // [KS][NB2],   NB2 = roundup(4*KS,16)
-    double* lag1d = nullptr; // [2][p+1][p+1] 1-D parent-at-child-node values (for inspection)
-    int nb1 = 0, nb2 = 0;
+    double* lag1d = nullptr; // [2][p+1][p+1] 1-D parent-at-child-node values (L2L factors)
+    int nb1 = 0;
     // the plan's own workspace, used by csfmm_eval
     csfmm_workspace_s* ws0 = nullptr;
     // optional per-stage timing with HIP events (ring of event sets)
     struct Timing {
-        // P2M, M2M, PP (side stream), PC + CP + CC, L2L, L2P
-        static constexpr int kStages = 6;
-        static constexpr int kMain = 6;   // events on the eval stream per slot
+        // P2M, M2M, PP (side stream), PC + CP + CC, L2L + L2P
+        static constexpr int kStages = 5;
+        static constexpr int kMain = 5;   // events on the eval stream per slot
         static constexpr int kEvents = kMain + 2;  // + PP start/end on the side stream
         static constexpr int kSlots = 32;
-        bool on = false;
+        int on = 0;  // 0 off, 1 every stage, 2 the PP launch only (side stream)
         std::vector<hipEvent_t> ev;  // [kSlots][kEvents]
         std::vector<int> pending;    // slot recorded and not yet read
-        double sum_ms[kStages] = {0, 0, 0, 0, 0, 0};
+        double sum_ms[kStages] = {0, 0, 0, 0, 0};
         int64_t n = 0;
         int next = 0;
     } timing;
@@ -253,7 +253,7 @@ int radix_sort_u64(uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream
 int build_plan(csfmm_plan_s* P, const double* targets, const double* sources, hipStream_t s);
 
 // ---- stage timing (eval.hip)
-int timing_enable(csfmm_plan_s* P, bool on);
+int timing_enable(csfmm_plan_s* P, int level);
 int timing_collect(csfmm_plan_s* P);
 
 // ---- eval (eval.hip)

@@ -1,9 +1,9 @@
 // Evaluation of plans (paper §8, Algorithm 2 lines 3, 5 and 7-21):
-//   gather weights -> P2M (eq. PC proxy weights of the leaves) -> M2M by
-//   levels (eq. upwardpass2, FP64 MFMA) -> near field PP+PC and far field
-//   CP+CC (tile engine) -> L2L by levels (eq. downward_2, FP64 MFMA) ->
-//   L2P at the leaves (eq. downward_1) fused with the scatter to the caller's
-//   order.
+//   gather weights -> [PP near field on a side stream] -> P2M (eq. PC proxy
+//   weights of the leaves) -> M2M by levels (eq. upwardpass2, FP64 MFMA) ->
+//   PC near field and CP+CC far field (tile engine) -> join -> per leaf: L2L
+//   down its ancestors (eq. downward_2, two 1-D passes per level), L2P
+//   (eq. downward_1), near field and the scatter to the caller's order.
 //
 // Every launch is a batch of up to kMaxBatch requests (a request is a plan
 // with its own workspace, weights and output); block b works for the request
@@ -157,104 +157,86 @@ __global__ __launch_bounds__(64) void k_p2m(Batch b) {
     for (int k = P1 * P1 + lane; k < KS; k += 64) wb[k] = 0.0;
 }
 
-// Batched small GEMMs on FP64 MFMA (v_mfma_f64_16x16x4f64) for the fixed
-// parent-child operators at one tree level; request r's parents at the level
-// are parents[a0[r] .. a0[r] + a1[r]).
-//   MODE 0 (M2M, eq. upwardpass2): row = parent P; A = wbar of its 4 children
-//     (4*KS contiguous values), B = bm2m [4KS][nb1], C = wbar(P), written.
-//     One block per (16-row tile, 16-column tile); wave q takes the K-slice of
-//     child q (split-K) and the four partial tiles are summed in LDS.
-//   MODE 1 (L2L, eq. downward_2): row = (component, parent P); A = psi(P) (KS
-//     values), B = bl2l [KS][nb2], C = psi of the 4 children, accumulated.
-//     One wave per (16-row tile, 16-column tile).
+// e3 M2M (eq. upwardpass2) at one tree level as batched small GEMMs on FP64
+// MFMA (v_mfma_f64_16x16x4f64); request r's parents at the level are
+// parents[a0[r] .. a0[r] + a1[r]).  Row = parent P; A = wbar of its 4
+// children (4*KS contiguous values), B = bm2m [4KS][nb1], C = wbar(P).  One
+// block per (16-row tile, 16-column tile); wave q takes the K-slice of child q
+// (split-K) and the four partial tiles are summed in LDS.
 // MFMA f64 16x16x4 operand layout: lane l holds A[l%16][l/16], B[l/16][l%16]
 // and D[l/16 + 4*i][l%16], i = 0..3 (checked with a one-hot probe).
 // Operand loads are issued kAhead MFMA steps ahead of their use.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_mfma_pass(Batch b) {
+__global__ __launch_bounds__(256) void k_m2m(Batch b) {
     constexpr int kAhead = 16;
-    __shared__ double4_t part[MODE == 0 ? 3 : 1][64];
+    __shared__ double4_t part[3][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int r, local;
     locate(b, r, local);
     const ReqView& V = *b.v[r];
-    const int32_t* rows = (MODE == 0 ? V.s_parents : V.t_parents) + b.a0[r];
+    const int32_t* rows = V.s_parents + b.a0[r];
     const int np = b.a1[r];
-    const int32_t* child0 = MODE == 0 ? V.s_child0 : V.t_child0;
     const int KS = V.KS;
-    const int nb = MODE == 0 ? V.nb1 : V.nb2;
-    const double* B = MODE == 0 ? V.bm2m : V.bl2l;
-    double* Cbase = MODE == 0 ? V.wbar : V.psi;
-    const double* Abase = Cbase;
-    const int64_t comp_stride = MODE == 0 ? 0 : V.psi_stride;
-    const int ncomp = MODE == 0 ? 1 : b.vd[r];
+    const int nb = V.nb1;
     const int ntiles = nb / 16;
-    const int gw = MODE == 0 ? local : local * 4 + wave;
-    const int rt = gw / ntiles, tile = gw % ntiles;
-    const int nrows = np * ncomp;
+    const int rt = local / ntiles, tile = local % ntiles;
     const int r0 = rt * 16;
-    if (r0 >= nrows) return;  // uniform over the block in MODE 0, over the wave in MODE 1
-    const int Kd = KS;        // K-slice per wave: one child (MODE 0) or the parent (MODE 1)
-    const int koff = MODE == 0 ? wave * KS : 0;
-    const int Nw = MODE == 0 ? KS : 4 * KS;
+    if (r0 >= np) return;  // uniform over the block
+    const int koff = wave * KS;  // K-slice of this wave: child `wave`
     const int ra = r0 + (lane & 15);
-    const double* arow = nullptr;
-    if (ra < nrows) {
-        const int comp = ra / np, P = rows[ra % np];
-        const int cell = MODE == 0 ? child0[P] : P;
-        arow = Abase + comp * comp_stride + int64_t(cell) * KS + koff;
-    }
+    const double* arow = ra < np ? V.wbar + int64_t(V.s_child0[rows[ra]]) * KS + koff : nullptr;
     const int kq = lane >> 4;
-    const double* bcol = B + int64_t(koff) * nb + tile * 16 + (lane & 15);
+    const double* bcol = V.bm2m + int64_t(koff) * nb + tile * 16 + (lane & 15);
     double4_t acc = {0.0, 0.0, 0.0, 0.0};
-    for (int kk = 0; kk < Kd; kk += 4 * kAhead) {
+    for (int kk = 0; kk < KS; kk += 4 * kAhead) {
         double av[kAhead], bv[kAhead];
 #pragma unroll
         for (int u = 0; u < kAhead; ++u) {
             const int k = kk + 4 * u + kq;
-            const bool in = k < Kd;
+            const bool in = k < KS;
             av[u] = (arow && in) ? arow[k] : 0.0;
             bv[u] = in ? bcol[int64_t(k) * nb] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kAhead; ++u)
-            if (kk + 4 * u < Kd)
+            if (kk + 4 * u < KS)
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
     }
-    if constexpr (MODE == 0) {
-        if (wave > 0) part[wave - 1][lane] = acc;
-        __syncthreads();
-        if (wave > 0) return;
-        acc += part[0][lane];
-        acc += part[1][lane];
-        acc += part[2][lane];
-    }
+    if (wave > 0) part[wave - 1][lane] = acc;
+    __syncthreads();
+    if (wave > 0) return;
+    acc += part[0][lane];
+    acc += part[1][lane];
+    acc += part[2][lane];
     const int col = tile * 16 + (lane & 15);
-    if (col < Nw) {
+    if (col < KS) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int rr = r0 + kq + 4 * i;
-            if (rr < nrows) {
-                const int comp = rr / np, P = rows[rr % np];
-                const int cell = MODE == 0 ? P : child0[P];
-                double* crow = Cbase + comp * comp_stride + int64_t(cell) * KS;
-                if (MODE == 0)
-                    crow[col] = acc[i];
-                else
-                    crow[col] += acc[i];
-            }
+            if (rr < np) V.wbar[int64_t(rows[rr]) * KS + col] = acc[i];
         }
     }
 }
 
-// e7+e8: L2P (eq. downward_1 at the leaves) + near field (PP, PC) + scatter to the
-// caller's order; one target leaf per block, one point per thread, the
-// Lagrange rows in registers and the leaf's proxy potentials in LDS; VD output
-// components (all requests of a launch have the same VD).
+// e6-e8: L2L (eq. downward_2) down the leaf's ancestors, L2P (eq.
+// downward_1) at the leaf, near field (PP, PC) and scatter to the caller's
+// order; one target leaf per block, one point per thread.
+// The parent-to-child operator of eq. downward_2 is the Kronecker product of
+// two 1-D factors A_bi (n1, m1) and A_bj (n2, m2), child q = 2 bi + bj, so
+// each level is two 1-D passes over the (p+1) x (p+1) proxy array:
+//   t[n1][m2] = sum_m1 A_bi[n1][m1] psi[m1][m2],
+//   psi'[n1][n2] = own[n1][n2] + sum_m2 A_bj[n2][m2] t[n1][m2],
+// starting from the root's own proxy potential.  The block walks its leaf's
+// ancestors from the root (the upper levels are recomputed per leaf instead
+// of one launch per level).  The accumulated proxy potential of the leaf is
+// stored back into psi (other blocks never read a leaf's psi).
 template <int VD, int P1>
 __global__ __launch_bounds__(64) void k_l2p(Batch b) {
+    constexpr int K = P1 * P1;
     __shared__ double s[P1], beta[P1];
-    __shared__ double ps[VD][P1 * P1];
+    __shared__ double A1[2][P1][P1];
+    __shared__ double ps[VD][K], tb[VD][K];
+    __shared__ int anc[kMaxLevel + 1];
+    __shared__ int nanc;
     int r, local;
     locate(b, r, local);
     const ReqView& V = *b.v[r];
@@ -263,13 +245,49 @@ __global__ __launch_bounds__(64) void k_l2p(Batch b) {
     const int bgn = V.t_begin[c], m = V.t_count[c];
     if (m == 0) return;  // the whole block leaves
     const int KS = V.KS;
+    const int tid = threadIdx.x;
     cheb_setup(P1 - 1, s, beta);
-    for (int k = threadIdx.x; k < P1 * P1; k += blockDim.x)
-#pragma unroll
-        for (int d = 0; d < VD; ++d) ps[d][k] = V.psi[d * V.psi_stride + int64_t(c) * KS + k];
+    for (int k = tid; k < 2 * K; k += blockDim.x) (&A1[0][0][0])[k] = V.lag1d[k];
+    if (tid == 0) {
+        int d = 0;
+        for (int x = c; x >= 0 && d <= kMaxLevel; x = V.t_parent[x]) anc[d++] = x;
+        nanc = d;  // anc[nanc-1] is the root, anc[0] the leaf
+    }
     __syncthreads();
+    const int na = nanc;
+    {
+        const int root = anc[na - 1];
+        for (int k = tid; k < K; k += blockDim.x)
+#pragma unroll
+            for (int d = 0; d < VD; ++d) ps[d][k] = V.psi[d * V.psi_stride + int64_t(root) * KS + k];
+    }
+    __syncthreads();
+    for (int l = na - 2; l >= 0; --l) {
+        const int ch = anc[l], par = anc[l + 1];
+        const int q = ch - V.t_child0[par];
+        const int bi = q >> 1, bj = q & 1;
+        for (int k = tid; k < VD * K; k += blockDim.x) {
+            const int d = k / K, e = k % K, n1 = e / P1, m2 = e % P1;
+            double t = 0.0;
+#pragma unroll
+            for (int m1 = 0; m1 < P1; ++m1) t = fma(A1[bi][n1][m1], ps[d][m1 * P1 + m2], t);
+            tb[d][e] = t;
+        }
+        __syncthreads();
+        for (int k = tid; k < VD * K; k += blockDim.x) {
+            const int d = k / K, e = k % K, n1 = e / P1, n2 = e % P1;
+            double t = V.psi[d * V.psi_stride + int64_t(ch) * KS + e];
+#pragma unroll
+            for (int m2 = 0; m2 < P1; ++m2) t = fma(A1[bj][n2][m2], tb[d][n1 * P1 + m2], t);
+            ps[d][e] = t;
+        }
+        __syncthreads();
+    }
+    for (int k = tid; k < K; k += blockDim.x)
+#pragma unroll
+        for (int d = 0; d < VD; ++d) V.psi[d * V.psi_stride + int64_t(c) * KS + k] = ps[d][k];
     for (int j0 = 0; j0 < m; j0 += blockDim.x) {
-        const int jj = j0 + threadIdx.x;
+        const int jj = j0 + tid;
         if (jj >= m) continue;
         const int j = bgn + jj;
         double L1[P1], L2[P1];
@@ -321,15 +339,18 @@ inline unsigned nblk(int64_t n, int t = 256) { return unsigned((n + t - 1) / t);
 using Timing = csfmm_plan_s::Timing;
 
 // Adds the stage times of a finished slot to the sums.  Events of a slot:
-// [0..5] on the eval stream (start, after P2M, after M2M, after PC + far,
-// after L2L, after L2P), [6, 7] around the PP launch on the side stream.
+// [0..4] on the eval stream (start, after P2M, after M2M, after PC + far,
+// after L2L + L2P), [5, 6] around the PP launch on the side stream.
+// With timing level 2 only [5, 6] are recorded (no events on the eval stream).
 int drain_slot(Timing& tm, int slot) {
     if (!tm.pending[slot]) return CSFMM_OK;
     hipEvent_t* e = &tm.ev[size_t(slot) * Timing::kEvents];
-    CSFMM_HIP_TRY(hipEventSynchronize(e[Timing::kMain - 1]));  // L2P waited for PP
-    static constexpr int from[Timing::kStages] = {0, 1, 6, 2, 3, 4};
-    static constexpr int to[Timing::kStages] = {1, 2, 7, 3, 4, 5};
+    const bool all = tm.pending[slot] == 1;
+    CSFMM_HIP_TRY(hipEventSynchronize(e[all ? Timing::kMain - 1 : Timing::kMain + 1]));
+    static constexpr int from[Timing::kStages] = {0, 1, 5, 2, 3};
+    static constexpr int to[Timing::kStages] = {1, 2, 6, 3, 4};
     for (int k = 0; k < Timing::kStages; ++k) {
+        if (!all && from[k] < Timing::kMain) continue;
         float ms = 0.f;
         CSFMM_HIP_TRY(hipEventElapsedTime(&ms, e[from[k]], e[to[k]]));
         tm.sum_ms[k] += ms;
@@ -409,7 +430,7 @@ int launch_m2m(Batch& b, const EvalReq* reqs, int n, hipStream_t s) {
             b.a1[r] = np;
             blk[r] = mfma_tiles(np, reqs[r].plan->nb1);
         }
-        RCX(launch_batched(b, blk, [&](unsigned g) { k_mfma_pass<0><<<g, 256, 0, s>>>(b); }));
+        RCX(launch_batched(b, blk, [&](unsigned g) { k_m2m<<<g, 256, 0, s>>>(b); }));
     }
     return CSFMM_OK;
 }
@@ -438,13 +459,15 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         int rc = drain_slot(tm, slot);
         if (rc != CSFMM_OK) return rc;
         ev = &tm.ev[size_t(slot) * Timing::kEvents];
-        tm.pending[slot] = 1;
+        tm.pending[slot] = tm.on;  // 1 every stage, 2 the PP launch only
     }
+    const bool main_marks = ev && reqs[0].plan->timing.on == 1;
     // the PP near field runs on the first workspace's side stream
     csfmm_workspace_s* W0 = reqs[0].ws;
     hipStream_t side = W0->side;
     auto mark = [&](int k) -> int {
-        if (ev) CSFMM_HIP_TRY(hipEventRecord(ev[k], k < Timing::kMain ? s : side));
+        if (ev && (k >= Timing::kMain || main_marks))
+            CSFMM_HIP_TRY(hipEventRecord(ev[k], k < Timing::kMain ? s : side));
         return CSFMM_OK;
     };
     RCX(mark(0));
@@ -482,13 +505,13 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
     auto launch_pp = [&]() -> int {
         CSFMM_HIP_TRY(hipEventRecord(W0->fork, s));
         CSFMM_HIP_TRY(hipStreamWaitEvent(side, W0->fork, 0));
-        RCX(mark(6));
+        RCX(mark(Timing::kMain));
         for (auto& kv : groups) {
             Batch g;
             RCX(tile_group(kv.second, kTileNearPP, g));
             RCX(launch_tile_batch(g, kv.first.first, kv.first.second != 0, side));
         }
-        RCX(mark(7));
+        RCX(mark(Timing::kMain + 1));
         CSFMM_HIP_TRY(hipEventRecord(W0->join, side));
         return CSFMM_OK;
     };
@@ -511,20 +534,6 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         RCX(launch_tile_batch(g, kv.first.first, kv.first.second != 0, s));
     }
     RCX(mark(3));
-    // e6 L2L, root level first
-    int maxt = 0;
-    for (int r = 0; r < n; ++r) maxt = std::max(maxt, int(reqs[r].plan->tt.depth));
-    for (int l = 0; l < maxt; ++l) {
-        for (int r = 0; r < n; ++r) {
-            const Tree& T = reqs[r].plan->tt;
-            const int np = l < T.depth ? T.parents_begin[l + 1] - T.parents_begin[l] : 0;
-            b.a0[r] = l < T.depth ? T.parents_begin[l] : 0;
-            b.a1[r] = np;
-            blk[r] = (mfma_tiles(int64_t(np) * b.vd[r], reqs[r].plan->nb2) + 3) / 4;
-        }
-        RCX(launch_batched(b, blk, [&](unsigned g) { k_mfma_pass<1><<<g, 256, 0, s>>>(b); }));
-    }
-    RCX(mark(4));
     // join the PP near field
     CSFMM_HIP_TRY(hipStreamWaitEvent(s, W0->join, 0));
     // e7+e8 L2P, near field and scatter to the caller's order; one launch per
@@ -550,13 +559,13 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
                 default: break;
             }
         }
-    RCX(mark(5));
+    RCX(mark(4));
     return CSFMM_OK;
 }
 
 }  // namespace
 
-int timing_enable(csfmm_plan_s* P, bool on) {
+int timing_enable(csfmm_plan_s* P, int on) {
     Timing& tm = P->timing;
     if (on && tm.ev.empty()) {
         tm.ev.assign(size_t(Timing::kSlots) * Timing::kEvents, nullptr);
@@ -615,7 +624,8 @@ int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** ou
     }
     ReqView& v = W->dview_host;
     v = ReqView{};
-    v.t_begin = T.begin; v.t_count = T.count; v.t_child0 = T.child0; v.t_leaves = T.leaves;
+    v.t_begin = T.begin; v.t_count = T.count; v.t_child0 = T.child0; v.t_parent = T.parent;
+    v.t_leaves = T.leaves;
     v.t_parents = T.parents; v.t_perm = T.perm;
     v.t_x = T.x; v.t_y = T.y; v.t_z = T.z; v.t_u = T.u; v.t_v = T.v;
     v.t_center = T.center; v.t_prox = T.prox;
@@ -629,11 +639,11 @@ int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** ou
     v.novl = P->lists.novl;
     v.far_targets = P->lists.far_targets;
     v.bm2m = P->bm2m;
-    v.bl2l = P->bl2l;
+    v.lag1d = P->lag1d;
     v.ws = W->ws; v.wbar = W->wbar; v.psi = W->psi; v.phinear = W->phinear; v.phipc = W->phipc;
     v.nt = P->nt; v.ns = P->ns;
     v.psi_stride = int64_t(T.ncells) * P->KS;
-    v.p = P->p; v.K = P->K; v.KS = P->KS; v.nb1 = P->nb1; v.nb2 = P->nb2;
+    v.p = P->p; v.K = P->K; v.KS = P->KS; v.nb1 = P->nb1;
     k_set_view<<<1, 64, 0, stream>>>(W->dview, v);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(stream);

@@ -218,6 +218,16 @@ __global__ void k_leaf_flags(const int32_t* __restrict__ child0, int n, int32_t*
     parent[k] = child0[k] < 0 ? 0 : 1;
 }
 
+// parent[c] = the cell whose four children include c; -1 for the roots
+__global__ void k_parent_of(const int32_t* __restrict__ child0, int n, int32_t* __restrict__ parent) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    if (k < 6) parent[k] = -1;
+    const int c0 = child0[k];
+    if (c0 >= 0)
+        for (int q = 0; q < 4; ++q) parent[c0 + q] = k;
+}
+
 __global__ void k_compact(const int32_t* __restrict__ flag, const int32_t* __restrict__ off, int n,
                           int32_t* __restrict__ out) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -316,10 +326,11 @@ __device__ double lagrange1(int p, int k, double x) {
 // Fixed operators of eq. (upwardpass2) and eq. (downward_2): with
 // A_s[m][k] = L_k((s_m + s)/2) (parent polynomial k at child node m, s = -1, +1),
 // child q = 2*bi + bj has T_q[k][m] = A_{2bi-1}[m1][k1] A_{2bj-1}[m2][k2].
+//   A1d[bi][m][k] = A_{2bi-1}[m][k]  (the 1-D factors; L2L applies them as two
+//                                     1-D passes in the leaf kernel)
 //   bm2m[q*KS + m][k] = T_q[k][m]   (M2M: parent = rows of children x bm2m)
-//   bl2l[m][q*KS + n] = T_q[m][n]   (L2L: children += parent x bl2l)
-__global__ void k_build_ops(int p, int KS, int nb1, int nb2, double* __restrict__ A1d,
-                            double* __restrict__ bm2m, double* __restrict__ bl2l) {
+__global__ void k_build_ops(int p, int KS, int nb1, double* __restrict__ A1d,
+                            double* __restrict__ bm2m) {
     const int P1 = p + 1, K = P1 * P1;
     for (int t = threadIdx.x; t < 2 * P1 * P1; t += blockDim.x) {
         const int sgn = t / (P1 * P1), r = t % (P1 * P1);
@@ -337,16 +348,6 @@ __global__ void k_build_ops(int p, int KS, int nb1, int nb2, double* __restrict_
             val = A1d[bi * K + (m / P1) * P1 + (k / P1)] * A1d[bj * K + (m % P1) * P1 + (k % P1)];
         }
         bm2m[t] = val;
-    }
-    for (int64_t t = threadIdx.x; t < int64_t(KS) * nb2; t += blockDim.x) {
-        const int m = int(t / nb2), col = int(t % nb2);
-        const int q = col / KS, nn = col % KS;
-        double val = 0.0;
-        if (m < K && nn < K && q < 4) {
-            const int bi = q >> 1, bj = q & 1;
-            val = A1d[bi * K + (nn / P1) * P1 + (m / P1)] * A1d[bj * K + (nn % P1) * P1 + (m % P1)];
-        }
-        bl2l[t] = val;
     }
 }
 
@@ -641,6 +642,9 @@ int build_tree(csfmm_plan_s* P, Tree& T, const double* pts, int64_t n, hipStream
     RC(S.get(&po, nc));
     k_leaf_flags<<<nblk(nc), kT, 0, s>>>(T.child0, nc, lf, pf);
     CSFMM_LAUNCH_CHECK();
+    RC(A.alloc(&T.parent, nc));
+    k_parent_of<<<nblk(nc), kT, 0, s>>>(T.child0, nc, T.parent);
+    CSFMM_LAUNCH_CHECK();
     RC(scan_exclusive_i32(lf, lo, nc, dtot, s));
     int32_t nleaves = 0;
     RC(read_i32(dtot, &nleaves, s));
@@ -842,11 +846,9 @@ int build_plan(csfmm_plan_s* P, const double* targets, const double* sources, hi
     }
     // fixed interpolation operators
     P->nb1 = int(round_up(P->KS, 16));
-    P->nb2 = int(round_up(4 * P->KS, 16));
     RC(A.alloc(&P->lag1d, 2 * (P->p + 1) * (P->p + 1)));
     RC(A.alloc(&P->bm2m, int64_t(4) * P->KS * P->nb1));
-    RC(A.alloc(&P->bl2l, int64_t(P->KS) * P->nb2));
-    k_build_ops<<<1, 256, 0, s>>>(P->p, P->KS, P->nb1, P->nb2, P->lag1d, P->bm2m, P->bl2l);
+    k_build_ops<<<1, 256, 0, s>>>(P->p, P->KS, P->nb1, P->lag1d, P->bm2m);
     CSFMM_LAUNCH_CHECK();
     RC(build_lists(P, s));
     // the plan's own eval workspace

@@ -182,15 +182,15 @@ def test_stages_and_result(case):
     # proxy weights after the upward pass
     ow = np.array([stg["wbar"][C.id].reshape(-1) for C in ofmm.stree.cells])
     assert rel_max(wbar, ow) < 1e-13
-    # proxy potentials after the downward pass, on the cells that hold targets
-    # (the library also interpolates into empty cells, which the oracle skips)
+    # proxy potentials after the downward pass at the leaves that hold targets
+    # (the library accumulates them per leaf; other cells keep their own sums)
     vd = 3 if k == 2 else 1
     n1 = p + 1
     c = CANCEL[k]
     op = np.zeros((vd, len(ofmm.ttree.cells), n1 * n1))
     for cid, val in stg["psi"].items():
         op[:, cid, :] = np.asarray(val).reshape(n1 * n1, vd).T
-    full = np.array([C.count > 0 for C in ofmm.ttree.cells])
+    full = np.array([C.count > 0 and C.is_leaf for C in ofmm.ttree.cells])
     if np.any(op[:, full] != 0):
         assert rel_max(psi[:, full], op[:, full]) < 1e-12 * c
     # near field (PP + PC)
