@@ -123,9 +123,14 @@ __device__ __forceinline__ float sal_bracket(float v) {
 // Evaluation forms of one (target, source) pair:
 //  FORM_CHECK  direct differences, a zero squared distance (coincident point)
 //              contributes nothing; for entries whose cells overlap the target
-//  FORM_NEAR   direct differences, no check (cells do not overlap)
-//  FORM_FAR    MAC-separated entries; in the FP32 form Poisson and 1/|x-y| use
-//              |t-s|^2 = |t|^2 + |s|^2 - 2 t.s (no cancellation at separation)
+//  FORM_NEAR   cells that do not overlap the target (no check)
+//  FORM_FAR    MAC-separated entries
+// In the FP32 form the scalar kernels take |t-s|^2 = |t|^2 + |s|^2 - 2 t.s for
+// FORM_NEAR and FORM_FAR (4 operations instead of 6; coordinates are recentred
+// at the target cell, so |t|^2 + |s|^2 stays within a small multiple of the
+// squared distance of two points in different cells and the relative error of
+// the result stays near FP32 rounding); FORM_CHECK keeps exact differences so
+// that a coincident point gives exactly 0.
 enum { FORM_CHECK = 0, FORM_NEAR = 1, FORM_FAR = 2 };
 
 struct TargetRegs {
@@ -145,7 +150,7 @@ __device__ __forceinline__ void eval_pair(const TargetRegs& T, Real<F32> sx, Rea
     } else {
         tx = T.tx; ty = T.ty; tz = T.tz;
     }
-    constexpr bool expanded = F32 && FORM == FORM_FAR && KERN != CSFMM_K_BIOT_SAVART;
+    constexpr bool expanded = F32 && FORM != FORM_CHECK && KERN != CSFMM_K_BIOT_SAVART;
     if constexpr (expanded) {
         const float d = fmaf(T.mx, sx, fmaf(T.my, sy, fmaf(T.mz, sz, s2 + T.f2)));
         if constexpr (KERN == CSFMM_K_POISSON_LOG)
