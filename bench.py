@@ -71,7 +71,7 @@ def recorded_traffic():
     """HBM bytes per near-field launch from the committed counter record, or
     None when the tile kernel's source has changed since it was taken."""
     import hashlib
-    rec_path = os.path.join(ROOT, "profiles", "interactions_poisson_E256_p6_fp32_counters.json")
+    rec_path = os.path.join(ROOT, "profiles", "near_pp_poisson_E256_p6_fp32_counters.json")
     src = os.path.join(ROOT, "paper_2508_13550_amd", "csrc", "tile.hip")
     try:
         rec = json.load(open(rec_path))
