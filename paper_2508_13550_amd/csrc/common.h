@@ -16,6 +16,7 @@ namespace csfmm {
 // level.
 constexpr int kMaxLevel = 20;
 constexpr int kMaxDegree = 16;
+constexpr int kAncStride = kMaxLevel + 2;
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kPi4 = 0.78539816339744830962;  // pi/4
@@ -89,6 +90,9 @@ struct Tree {
     int32_t *level = nullptr, *face = nullptr, *ci = nullptr, *cj = nullptr;
     int32_t *begin = nullptr, *count = nullptr, *child0 = nullptr;
     int32_t* parent = nullptr;  // -1 for the six roots
+    // per leaf (in `leaves` order): [0] = number of cells on the path from the
+    // root to the leaf, then those cells, root first; stride kAncStride
+    int32_t* leaf_anc = nullptr;
     double* center = nullptr;  // [ncells][3]
     double* radius = nullptr;  // [ncells]
     double* prox = nullptr;    // [ncells][3][KS] proxy coordinates (SoA per cell)
@@ -113,7 +117,7 @@ struct Lists {
 // size an eval kernel needs about one request.
 struct ReqView {
     // target tree
-    const int32_t *t_begin, *t_count, *t_child0, *t_parent, *t_leaves, *t_parents, *t_perm;
+    const int32_t *t_begin, *t_count, *t_child0, *t_leaf_anc, *t_leaves, *t_parents, *t_perm;
     const double *t_x, *t_y, *t_z, *t_u, *t_v, *t_center, *t_prox;
     // source tree
     const int32_t *s_begin, *s_count, *s_child0, *s_leaves, *s_parents, *s_perm;

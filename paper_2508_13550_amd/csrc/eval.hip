@@ -226,17 +226,18 @@ __global__ __launch_bounds__(256) void k_m2m(Batch b) {
 //   t[n1][m2] = sum_m1 A_bi[n1][m1] psi[m1][m2],
 //   psi'[n1][n2] = own[n1][n2] + sum_m2 A_bj[n2][m2] t[n1][m2],
 // starting from the root's own proxy potential.  The block walks its leaf's
-// ancestors from the root (the upper levels are recomputed per leaf instead
-// of one launch per level).  The accumulated proxy potential of the leaf is
-// stored back into psi (other blocks never read a leaf's psi).
+// path from the root (a table built with the plan; the upper levels are
+// recomputed per leaf instead of one launch per level) and loads each level's
+// own proxy potential one level ahead.  The accumulated proxy potential of the
+// leaf is stored back into psi (other blocks never read a leaf's psi).
 template <int VD, int P1>
 __global__ __launch_bounds__(64) void k_l2p(Batch b) {
     constexpr int K = P1 * P1;
+    constexpr int kRegs = (VD * K + 63) / 64;  // elements per thread in the 1-D passes
     __shared__ double s[P1], beta[P1];
     __shared__ double A1[2][P1][P1];
     __shared__ double ps[VD][K], tb[VD][K];
-    __shared__ int anc[kMaxLevel + 1];
-    __shared__ int nanc;
+    __shared__ int anc[kAncStride];
     int r, local;
     locate(b, r, local);
     const ReqView& V = *b.v[r];
@@ -248,38 +249,56 @@ __global__ __launch_bounds__(64) void k_l2p(Batch b) {
     const int tid = threadIdx.x;
     cheb_setup(P1 - 1, s, beta);
     for (int k = tid; k < 2 * K; k += blockDim.x) (&A1[0][0][0])[k] = V.lag1d[k];
-    if (tid == 0) {
-        int d = 0;
-        for (int x = c; x >= 0 && d <= kMaxLevel; x = V.t_parent[x]) anc[d++] = x;
-        nanc = d;  // anc[nanc-1] is the root, anc[0] the leaf
-    }
+    const int32_t* path = V.t_leaf_anc + int64_t(local) * kAncStride;
+    for (int k = tid; k < kAncStride; k += blockDim.x) anc[k] = path[k];
     __syncthreads();
-    const int na = nanc;
-    {
-        const int root = anc[na - 1];
-        for (int k = tid; k < K; k += blockDim.x)
+    const int na = anc[0];  // anc[1] is the root, anc[na] the leaf
+    // own proxy potential of a cell, this thread's elements (k = tid + 64 i)
+    auto load_own = [&](int cell, double (&dst)[kRegs]) {
 #pragma unroll
-            for (int d = 0; d < VD; ++d) ps[d][k] = V.psi[d * V.psi_stride + int64_t(root) * KS + k];
+        for (int i = 0; i < kRegs; ++i) {
+            const int k = tid + 64 * i;
+            dst[i] = k < VD * K ? V.psi[(k / K) * V.psi_stride + int64_t(cell) * KS + k % K] : 0.0;
+        }
+    };
+    double cur[kRegs], nxt[kRegs];
+    load_own(anc[1], cur);
+#pragma unroll
+    for (int i = 0; i < kRegs; ++i) {
+        const int k = tid + 64 * i;
+        if (k < VD * K) ps[k / K][k % K] = cur[i];
     }
+    if (na >= 2) load_own(anc[2], nxt);
     __syncthreads();
-    for (int l = na - 2; l >= 0; --l) {
-        const int ch = anc[l], par = anc[l + 1];
+    for (int l = 2; l <= na; ++l) {
+        const int ch = anc[l], par = anc[l - 1];
         const int q = ch - V.t_child0[par];
         const int bi = q >> 1, bj = q & 1;
-        for (int k = tid; k < VD * K; k += blockDim.x) {
-            const int d = k / K, e = k % K, n1 = e / P1, m2 = e % P1;
-            double t = 0.0;
 #pragma unroll
-            for (int m1 = 0; m1 < P1; ++m1) t = fma(A1[bi][n1][m1], ps[d][m1 * P1 + m2], t);
-            tb[d][e] = t;
+        for (int i = 0; i < kRegs; ++i) cur[i] = nxt[i];
+        if (l < na) load_own(anc[l + 1], nxt);  // one level ahead
+#pragma unroll
+        for (int i = 0; i < kRegs; ++i) {
+            const int k = tid + 64 * i;
+            if (k < VD * K) {
+                const int d = k / K, e = k % K, n1 = e / P1, m2 = e % P1;
+                double t = 0.0;
+#pragma unroll
+                for (int m1 = 0; m1 < P1; ++m1) t = fma(A1[bi][n1][m1], ps[d][m1 * P1 + m2], t);
+                tb[d][e] = t;
+            }
         }
         __syncthreads();
-        for (int k = tid; k < VD * K; k += blockDim.x) {
-            const int d = k / K, e = k % K, n1 = e / P1, n2 = e % P1;
-            double t = V.psi[d * V.psi_stride + int64_t(ch) * KS + e];
 #pragma unroll
-            for (int m2 = 0; m2 < P1; ++m2) t = fma(A1[bj][n2][m2], tb[d][n1 * P1 + m2], t);
-            ps[d][e] = t;
+        for (int i = 0; i < kRegs; ++i) {
+            const int k = tid + 64 * i;
+            if (k < VD * K) {
+                const int d = k / K, e = k % K, n1 = e / P1, n2 = e % P1;
+                double t = cur[i];
+#pragma unroll
+                for (int m2 = 0; m2 < P1; ++m2) t = fma(A1[bj][n2][m2], tb[d][n1 * P1 + m2], t);
+                ps[d][e] = t;
+            }
         }
         __syncthreads();
     }
@@ -624,7 +643,7 @@ int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** ou
     }
     ReqView& v = W->dview_host;
     v = ReqView{};
-    v.t_begin = T.begin; v.t_count = T.count; v.t_child0 = T.child0; v.t_parent = T.parent;
+    v.t_begin = T.begin; v.t_count = T.count; v.t_child0 = T.child0; v.t_leaf_anc = T.leaf_anc;
     v.t_leaves = T.leaves;
     v.t_parents = T.parents; v.t_perm = T.perm;
     v.t_x = T.x; v.t_y = T.y; v.t_z = T.z; v.t_u = T.u; v.t_v = T.v;

@@ -218,6 +218,31 @@ __global__ void k_leaf_flags(const int32_t* __restrict__ child0, int n, int32_t*
     parent[k] = child0[k] < 0 ? 0 : 1;
 }
 
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+    if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
+}
+
+// Kernel evaluations of list `kind` for target cell t: sum over its entries of
+// (targets) x (sources), targets = particles (PP, PC) or K proxies (CP, CC),
+// sources = particles (PP, CP) or K proxies (PC, CC); a same-set PP self entry
+// omits the i = j pairs.  Integer sums, so the atomic total is exact.
+__global__ void k_count_evals(int kind, const int32_t* __restrict__ off,
+                              const int32_t* __restrict__ src, const int32_t* __restrict__ tcount,
+                              const int32_t* __restrict__ scount, int ncells, int K, int same,
+                              unsigned long long* __restrict__ total) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ncells) return;
+    const bool tpart = kind == 0 || kind == 1, spart = kind == 0 || kind == 2;
+    const long long nt = tpart ? tcount[t] : K;
+    long long ev = 0;
+    for (int e = off[t]; e < off[t + 1]; ++e) {
+        const int sc = src[e];
+        ev += nt * (spart ? scount[sc] : K);
+        if (kind == 0 && same && sc == t) ev -= tcount[t];
+    }
+    if (ev) atomicAdd(total, (unsigned long long)ev);
+}
+
 // parent[c] = the cell whose four children include c; -1 for the roots
 __global__ void k_parent_of(const int32_t* __restrict__ child0, int n, int32_t* __restrict__ parent) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -226,6 +251,19 @@ __global__ void k_parent_of(const int32_t* __restrict__ child0, int n, int32_t* 
     const int c0 = child0[k];
     if (c0 >= 0)
         for (int q = 0; q < 4; ++q) parent[c0 + q] = k;
+}
+
+// Path from the root to every leaf (see Tree::leaf_anc).
+__global__ void k_leaf_paths(const int32_t* __restrict__ leaves, int nleaves,
+                             const int32_t* __restrict__ parent, int32_t* __restrict__ anc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nleaves) return;
+    int32_t tmp[kMaxLevel + 1];
+    int d = 0;
+    for (int x = leaves[i]; x >= 0 && d <= kMaxLevel; x = parent[x]) tmp[d++] = x;
+    int32_t* a = anc + int64_t(i) * kAncStride;
+    a[0] = d;
+    for (int k = 0; k < d; ++k) a[1 + k] = tmp[d - 1 - k];
 }
 
 __global__ void k_compact(const int32_t* __restrict__ flag, const int32_t* __restrict__ off, int n,
@@ -657,6 +695,9 @@ int build_tree(csfmm_plan_s* P, Tree& T, const double* pts, int64_t n, hipStream
     k_compact<<<nblk(nc), kT, 0, s>>>(lf, lo, nc, T.leaves);
     k_compact<<<nblk(nc), kT, 0, s>>>(pf, po, nc, T.parents);
     CSFMM_LAUNCH_CHECK();
+    RC(A.alloc(&T.leaf_anc, int64_t(nleaves) * kAncStride));
+    k_leaf_paths<<<nblk(nleaves), kT, 0, s>>>(T.leaves, nleaves, T.parent, T.leaf_anc);
+    CSFMM_LAUNCH_CHECK();
     // per-level offsets into `parents`: exclusive-scan value at each level start
     std::vector<int32_t> hpo(nc);
     CSFMM_HIP_TRY(hipMemcpyAsync(hpo.data(), po, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
@@ -790,27 +831,20 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
     k_compact<<<nblk(T.ncells), kT, 0, s>>>(ff, fo, T.ncells, P->lists.far_targets);
     CSFMM_LAUNCH_CHECK();
 
-    // evaluation counts (host arithmetic on copies of the lists)
-    std::vector<int32_t> tc(T.ncells), sc(Sx.ncells);
-    CSFMM_HIP_TRY(hipMemcpyAsync(tc.data(), T.count, sizeof(int32_t) * T.ncells, hipMemcpyDeviceToHost, s));
-    CSFMM_HIP_TRY(hipMemcpyAsync(sc.data(), Sx.count, sizeof(int32_t) * Sx.ncells, hipMemcpyDeviceToHost, s));
+    // evaluation counts of the four lists (integer sums on the device)
+    unsigned long long* dev_ev;
+    RC(S.get(&dev_ev, 4));
+    k_zero_u64<<<1, 4, 0, s>>>(dev_ev, 4);
     for (int k = 0; k < 4; ++k) {
-        const int64_t cnt = P->lists.cnt[k];
-        std::vector<int32_t> off(T.ncells + 1), src(std::max<int64_t>(cnt, 1));
-        CSFMM_HIP_TRY(hipMemcpyAsync(off.data(), P->lists.off[k], sizeof(int32_t) * (T.ncells + 1), hipMemcpyDeviceToHost, s));
-        if (cnt > 0)
-            CSFMM_HIP_TRY(hipMemcpyAsync(src.data(), P->lists.src[k], sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, s));
-        CSFMM_HIP_TRY(hipStreamSynchronize(s));
-        int64_t ev = 0;
-        for (int t = 0; t < T.ncells; ++t)
-            for (int e = off[t]; e < off[t + 1]; ++e) {
-                const int64_t nt = (k == kPP || k == kPC) ? tc[t] : P->K;
-                const int64_t nsrc = (k == kPP || k == kCP) ? sc[src[e]] : P->K;
-                ev += nt * nsrc;
-                if (k == kPP && P->same && src[e] == t) ev -= tc[t];
-            }
-        P->lists.evals[k] = ev;
+        k_count_evals<<<nblk(T.ncells), kT, 0, s>>>(k, P->lists.off[k], P->lists.src[k], T.count,
+                                                     Sx.count, T.ncells, P->K, P->same ? 1 : 0,
+                                                     dev_ev + k);
     }
+    CSFMM_LAUNCH_CHECK();
+    unsigned long long hev[4];
+    CSFMM_HIP_TRY(hipMemcpyAsync(hev, dev_ev, sizeof(hev), hipMemcpyDeviceToHost, s));
+    CSFMM_HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < 4; ++k) P->lists.evals[k] = int64_t(hev[k]);
     return CSFMM_OK;
 }
 

@@ -169,6 +169,20 @@ def test_lists(case):
     _compare_lists(plan, ofmm)
     st = plan.stats()
     assert st["n_pp"] == len(ofmm.lists["PP"]) and st["n_cc"] == len(ofmm.lists["CC"])
+    # kernel evaluations per list, counted from the oracle's lists
+    K = (p + 1) ** 2
+    want = {}
+    for kind in ("PP", "PC", "CP", "CC"):
+        ev = 0
+        for Tc, Sc in ofmm.lists[kind]:
+            nt = Tc.count if kind in ("PP", "PC") else K
+            ns = Sc.count if kind in ("PP", "CP") else K
+            ev += nt * ns
+            if kind == "PP" and S is None and Tc.id == Sc.id:
+                ev -= Tc.count
+        want[kind] = ev
+    assert (st["evals_pp"], st["evals_pc"], st["evals_cp"], st["evals_cc"]) == \
+        (want["PP"], want["PC"], want["CP"], want["CC"])
 
 
 def test_stages_and_result(case):
