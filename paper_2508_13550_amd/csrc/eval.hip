@@ -436,12 +436,16 @@ int launch_p2m(Batch& b, const EvalReq* reqs, int n, hipStream_t s) {
     return CSFMM_OK;
 }
 
-// e3 M2M by levels, deepest parents first
-int launch_m2m(Batch& b, const EvalReq* reqs, int n, hipStream_t s) {
-    int64_t blk[kMaxBatch];
+int max_source_depth(const EvalReq* reqs, int n) {
     int maxd = 0;
     for (int r = 0; r < n; ++r) maxd = std::max(maxd, int(reqs[r].plan->st->depth));
-    for (int l = maxd - 1; l >= 0; --l) {
+    return maxd;
+}
+
+// e3 M2M by levels, deepest parents first: parent levels lhi down to llo
+int launch_m2m(Batch& b, const EvalReq* reqs, int n, hipStream_t s, int lhi, int llo) {
+    int64_t blk[kMaxBatch];
+    for (int l = lhi; l >= std::max(llo, 0); --l) {
         for (int r = 0; r < n; ++r) {
             const Tree& S = *reqs[r].plan->st;
             const int np = l < S.depth ? S.parents_begin[l + 1] - S.parents_begin[l] : 0;
@@ -492,8 +496,9 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
     RCX(mark(0));
     // e1 gather
     RCX(launch_gather(b, reqs, n, s));
-    // e4 PP near field on the side stream, concurrent with e2-e6: it needs
-    // the gathered weights only; one launch per (kernel, form) group
+    // e4 PP near field on the side stream, concurrent with the upward pass
+    // (all of it or its upper levels, see below), the zero fill and e5: it
+    // needs the gathered weights only; one launch per (kernel, form) group
     std::map<std::pair<int, int>, std::vector<int>> groups;
     for (int r = 0; r < n; ++r)
         groups[{reqs[r].kernel, (reqs[r].plan->flags & CSFMM_FP32_FORM) ? 1 : 0}].push_back(r);
@@ -534,11 +539,28 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         CSFMM_HIP_TRY(hipEventRecord(W0->join, side));
         return CSFMM_OK;
     };
-    RCX(launch_pp());
-    // e2 P2M, e3 M2M
+    // Where to fork: when the far field is light (PC + CP + CC evaluations
+    // below kLateFork of the PP ones) the eval stream's critical path is the
+    // latency-bound upward pass, so PP starts right after the gather; when it
+    // is heavy, P2M and the deepest (largest) M2M level first run without PP
+    // waves beside them and PP starts after them (measured on the Poisson
+    // workload N = 393,216: p = 6 (0.28) early fork 0.337 vs 0.368 ms; p = 8
+    // (0.61) 0.453 vs 0.435; p = 10 (1.19) 0.588 vs 0.544).
+    constexpr double kLateFork = 0.45;
+    int64_t ev_pp = 0, ev_far = 0;
+    for (int r = 0; r < n; ++r) {
+        const Lists& Ls = reqs[r].plan->lists;
+        ev_pp += Ls.evals[kPP];
+        ev_far += Ls.evals[kPC] + Ls.evals[kCP] + Ls.evals[kCC];
+    }
+    const bool late = double(ev_far) > kLateFork * double(ev_pp);
+    const int maxd = max_source_depth(reqs, n);
+    if (!late) RCX(launch_pp());
     RCX(launch_p2m(b, reqs, n, s));
     RCX(mark(1));
-    RCX(launch_m2m(b, reqs, n, s));
+    RCX(launch_m2m(b, reqs, n, s, maxd - 1, maxd - 1));
+    if (late) RCX(launch_pp());
+    RCX(launch_m2m(b, reqs, n, s, maxd - 2, 0));
     // zero the proxy potentials (CP + CC accumulate into them)
     for (int r = 0; r < n; ++r)
         blk[r] = (int64_t(b.vd[r]) * reqs[r].ws->dview_host.psi_stride + 255) / 256;
@@ -711,7 +733,7 @@ int run_treecode(csfmm_plan_s* P, int kernel, const double* weights, double* out
     Batch b = batch_of(&q, 1);
     RCX(launch_gather(b, &q, 1, s));
     RCX(launch_p2m(b, &q, 1, s));
-    RCX(launch_m2m(b, &q, 1, s));
+    RCX(launch_m2m(b, &q, 1, s, max_source_depth(&q, 1) - 1, 0));
     const Tree& T = P->tt;
     const Tree& S = *P->st;
     TcArgs a{};
