@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--bve", action="store_true",
                     help="barotropic vorticity equation, Rossby-Haurwitz wave, RK4 (paper §12)")
     ap.add_argument("--bve-k", type=int, default=7)
+    ap.add_argument("--configs", action="store_true",
+                    help="the other workloads: Poisson E=32, Biot-Savart E=512, 1/|x-y| 6.3M x 1M")
     return ap.parse_args()
 
 
@@ -458,6 +460,77 @@ def bve_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def configs_bench(args):
+    """Throughput of the workloads beside the headline one, each in the form
+    and parameters it is specified with: Poisson E=32 (FP64, p=8, theta 0.7,
+    leaf 64; 100 evals), Biot-Savart E=512 (FP32 form, p=8, theta 0.6, leaf 128;
+    30 evals), 1/|x-y| with 6,291,456 sources and 1,000,000 random targets
+    (FP32 form, p=10, theta 0.6, leaf 128; 10 evals).  Plan time is reported
+    apart; the error is relative L2 on 4,096 seeded targets (all 6,144 for the
+    small one) against the GPU FP64 direct sum."""
+    import torch
+    import paper_2508_13550_amd as cs
+    from workloads import make_config, config_subset
+
+    rows = []
+    for cid, fp32, reps in ((1, False, 100), (3, True, 30), (4, True, 10)):
+        c = make_config(cid)
+        print("configs: inputs of workload %d ready" % cid, file=sys.stderr, flush=True)
+        S = c["sources"]
+        T = S if c["targets"] is None else c["targets"]
+        dev = torch.device("cuda:0")
+        Sd = torch.tensor(S, dtype=torch.float64, device=dev)
+        Td = Sd if c["targets"] is None else torch.tensor(T, dtype=torch.float64, device=dev)
+        W = torch.tensor(c["weights"], dtype=torch.float64, device=dev)
+        nt, ns = T.shape[0], S.shape[0]
+        samp = np.arange(nt) if cid == 1 else config_subset(nt, 4096, c["subset_seed"])
+        sd = torch.tensor(samp, device=dev)
+        ref = cs.direct(Td[sd].contiguous(), Sd, W, kernel=c["kernel"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = cs.Plan(Td, None if c["targets"] is None else Sd, kernel=c["kernel"], p=c["p"],
+                       theta=c["theta"], leaf_size=c["leaf"], fp32=fp32)
+        torch.cuda.synchronize()
+        plan_ms = 1e3 * (time.perf_counter() - t0)
+        out = plan.eval(W)
+        for _ in range(3):
+            plan.eval(W, out=out)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record()
+            plan.eval(W, out=out)
+            b.record()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        lat = np.array([a.elapsed_time(b) for a, b in ev])
+        st = plan.stats()
+        plan.close()
+        d = (out[sd] - ref).reshape(len(samp), -1)
+        r = ref.reshape(len(samp), -1)
+        if cid == 1 or cid == 3:
+            a_w = torch.tensor(c["areas"][samp], dtype=torch.float64, device=dev)[:, None]
+        else:
+            a_w = torch.ones((len(samp), 1), dtype=torch.float64, device=dev)
+        rel = float(torch.sqrt(torch.sum(a_w * d * d) / torch.sum(a_w * r * r)))
+        rows.append({"workload": c["name"], "n_targets": nt, "n_sources": ns,
+                     "form": "fp32" if fp32 else "fp64", "p": c["p"], "theta": c["theta"],
+                     "leaf": c["leaf"], "evals_timed": reps, "ms_per_eval": ms,
+                     "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                                    "p99": float(np.percentile(lat, 99))},
+                     "n2eq_per_s": float(nt) * ns / (ms / 1e3), "plan_ms": plan_ms,
+                     "rel_l2_err": rel, "evals": {k: st["evals_" + k] for k in ("pp", "pc", "cp", "cc")},
+                     "device_bytes": st["device_bytes"]})
+        print("configs: workload %d done" % cid, file=sys.stderr, flush=True)
+        del Sd, Td, W, out, ref
+        torch.cuda.empty_cache()
+    line = {"metric": "N^2-equiv interactions/s per FMM eval, other workloads", "n_gpus": 1,
+            "data": "synthetic", "rows": rows}
+    print(json.dumps(line), flush=True)
+
+
 def serve_bench(args):
     """Serving stream: requests of mixed resolution, kernel and degree arriving
     as a Poisson process at rho x capacity; continuous batching on one GPU."""
@@ -586,6 +659,9 @@ def main():
         return
     if args.bve:
         bve_bench(args)
+        return
+    if args.configs:
+        configs_bench(args)
         return
     import torch
     import paper_2508_13550_amd as cs
