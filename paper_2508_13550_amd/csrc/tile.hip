@@ -279,7 +279,7 @@ __device__ __forceinline__ TileArgs tile_args(const ReqView& V, int mode) {
 }
 
 constexpr int kMaxG = 32;   // source groups per target
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 4;  // run_group reads the weights of kUnroll sources as one float4
 constexpr int kLds = kChunk + kUnroll * kMaxG;
 
 // Staged sources: FP32 form (x, y, z, |s|^2) and weights; FP64 form (x, y, z, w).
@@ -298,6 +298,9 @@ struct Stage<false> {
 template <int KERN, bool F32, int FORM>
 __device__ __forceinline__ void run_group(const Stage<F32>& L, int base, int nj,
                                           const TargetRegs& T, Real<F32>* p) {
+    // nj is the same for every thread of the block: a scalar trip count keeps
+    // the loop control off the vector unit
+    nj = __builtin_amdgcn_readfirstlane(nj);
     for (int j = 0; j < nj; j += kUnroll) {
         if constexpr (F32) {
             const float4 w4 = *reinterpret_cast<const float4*>(&L.w[base + j]);
