@@ -83,6 +83,9 @@ typedef struct csfmm_stats {
     int64_t n_pp, n_pc, n_cp, n_cc;        /* (target cell, source cell) pairs */
     int64_t evals_pp, evals_pc, evals_cp, evals_cc; /* kernel evaluations per eval */
     int64_t device_bytes;                  /* device memory the plan holds */
+    int64_t max_leaf_t;                    /* most points in a target leaf; leaves of at
+                                              most 64 take the one-wave-per-leaf
+                                              near-field path */
 } csfmm_stats;
 
 /*

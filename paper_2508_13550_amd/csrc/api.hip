@@ -185,6 +185,7 @@ int csfmm_plan_stats(csfmm_plan_t plan, csfmm_stats* s) {
     s->n_cells_s = plan->st->ncells;
     s->n_leaves_t = plan->tt.nleaves;
     s->n_leaves_s = plan->st->nleaves;
+    s->max_leaf_t = plan->tt.max_leaf;
     s->n_pp = plan->lists.cnt[kPP];
     s->n_pc = plan->lists.cnt[kPC];
     s->n_cp = plan->lists.cnt[kCP];

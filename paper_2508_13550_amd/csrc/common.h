@@ -80,6 +80,7 @@ struct DevArena {
 struct Tree {
     int64_t n = 0;
     int32_t ncells = 0, nleaves = 0, depth = 0;
+    int32_t max_leaf = 0;  // largest number of points in a leaf
     std::vector<int32_t> level_begin;   // host: first cell of each level, + end
     std::vector<int32_t> parents_begin; // host: first entry of each level in `parents`
     // sorted points (SoA) and their caller indices
@@ -132,7 +133,12 @@ struct ReqView {
     double *ws, *wbar, *psi, *phinear, *phipc;
     int64_t nt, ns, psi_stride;
     int32_t p, K, KS, nb1;
+    int32_t nleaves_t, pad_;
 };
+
+// Target leaves of at most this many points take the one-wave-per-leaf path of
+// the near-field tile kernel.
+constexpr int kWaveLeaf = 64;
 
 // Kernel argument of every eval launch: up to kMaxBatch requests; block b of
 // the grid belongs to request r with prefix[r] <= b < prefix[r+1].
@@ -148,6 +154,8 @@ struct Batch {
     int32_t prefix[kMaxBatch + 1];
     int32_t prefix2[kMaxBatch + 1];  // tile launches: far-field blocks (prefix: near-field)
     int32_t mode;                    // tile launches: kTileNearPP or kTilePCFar
+    int32_t leaf_wave[kMaxBatch];    // tile launches: request r's near field takes one wave per leaf
+    int32_t wave_kernel;  // tile launches: near field only, all one wave per leaf: k_tile_wave
 };
 
 // Tile launch modes.  The PP near field needs no proxy weights, so it runs on

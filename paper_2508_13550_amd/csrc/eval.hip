@@ -507,6 +507,12 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         g.n = int(idx.size());
         g.mode = mode;
         int64_t tn = 0, tf = 0;
+        // a PP launch whose requests all have leaves of <= kWaveLeaf points runs
+        // k_tile_wave; k_tile takes the rest (far-field blocks on its block path,
+        // near-field blocks of such requests on the one-wave-per-leaf path)
+        g.wave_kernel = mode == kTileNearPP ? 1 : 0;
+        for (int q = 0; q < g.n; ++q)
+            if (reqs[idx[q]].plan->tt.max_leaf > kWaveLeaf) g.wave_kernel = 0;
         for (int q = 0; q < g.n; ++q) {
             const int r = idx[q];
             g.v[q] = b.v[r];
@@ -515,7 +521,11 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
             g.vd[q] = b.vd[r];
             g.prefix[q] = int32_t(tn);
             g.prefix2[q] = int32_t(tf);
-            tn += reqs[r].plan->tt.nleaves;
+            // near-field blocks: four target leaves each (one a wave) on the
+            // one-wave-per-leaf path, else one
+            const Tree& tt = reqs[r].plan->tt;
+            g.leaf_wave[q] = tt.max_leaf <= kWaveLeaf ? 1 : 0;
+            tn += g.leaf_wave[q] ? (int64_t(tt.nleaves) + 3) / 4 : tt.nleaves;
             tf += mode == kTilePCFar ? reqs[r].plan->lists.n_far_targets : 0;
         }
         g.prefix[g.n] = int32_t(tn);
@@ -685,6 +695,7 @@ int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** ou
     v.nt = P->nt; v.ns = P->ns;
     v.psi_stride = int64_t(T.ncells) * P->KS;
     v.p = P->p; v.K = P->K; v.KS = P->KS; v.nb1 = P->nb1;
+    v.nleaves_t = T.nleaves;
     k_set_view<<<1, 64, 0, stream>>>(W->dview, v);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(stream);

@@ -222,6 +222,14 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
     if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
 }
 
+// Largest point count over the leaves of a tree.
+__global__ void k_max_leaf(const int32_t* __restrict__ leaves, int nleaves,
+                           const int32_t* __restrict__ count, unsigned long long* __restrict__ mx) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nleaves) return;
+    atomicMax(mx, (unsigned long long)count[leaves[i]]);
+}
+
 // Kernel evaluations of list `kind` for target cell t: sum over its entries of
 // (targets) x (sources), targets = particles (PP, PC) or K proxies (CP, CC),
 // sources = particles (PP, CP) or K proxies (PC, CC); a same-set PP self entry
@@ -833,18 +841,21 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
 
     // evaluation counts of the four lists (integer sums on the device)
     unsigned long long* dev_ev;
-    RC(S.get(&dev_ev, 4));
-    k_zero_u64<<<1, 4, 0, s>>>(dev_ev, 4);
+    RC(S.get(&dev_ev, 5));
+    k_zero_u64<<<1, 5, 0, s>>>(dev_ev, 5);
     for (int k = 0; k < 4; ++k) {
         k_count_evals<<<nblk(T.ncells), kT, 0, s>>>(k, P->lists.off[k], P->lists.src[k], T.count,
                                                      Sx.count, T.ncells, P->K, P->same ? 1 : 0,
                                                      dev_ev + k);
     }
+    // and the largest target leaf (selects the near-field tile path)
+    k_max_leaf<<<nblk(T.nleaves), kT, 0, s>>>(T.leaves, T.nleaves, T.count, dev_ev + 4);
     CSFMM_LAUNCH_CHECK();
-    unsigned long long hev[4];
+    unsigned long long hev[5];
     CSFMM_HIP_TRY(hipMemcpyAsync(hev, dev_ev, sizeof(hev), hipMemcpyDeviceToHost, s));
     CSFMM_HIP_TRY(hipStreamSynchronize(s));
     for (int k = 0; k < 4; ++k) P->lists.evals[k] = int64_t(hev[k]);
+    T.max_leaf = int32_t(hev[4]);
     return CSFMM_OK;
 }
 

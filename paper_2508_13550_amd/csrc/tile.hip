@@ -139,6 +139,22 @@ struct TargetRegs {
     float mx, my, mz;           // -2 t
 };
 
+// Target registers of a target at offset (dx, dy, dz) from its cell centre.
+__device__ __forceinline__ TargetRegs target_regs(double dx, double dy, double dz, double scale) {
+    TargetRegs TR;
+    TR.tx = dx * scale;
+    TR.ty = dy * scale;
+    TR.tz = dz * scale;
+    TR.fx = float(TR.tx);
+    TR.fy = float(TR.ty);
+    TR.fz = float(TR.tz);
+    TR.f2 = float(double(TR.fx) * TR.fx + double(TR.fy) * TR.fy + double(TR.fz) * TR.fz);
+    TR.mx = -2.f * TR.fx;
+    TR.my = -2.f * TR.fy;
+    TR.mz = -2.f * TR.fz;
+    return TR;
+}
+
 template <int KERN, bool F32, int FORM>
 __device__ __forceinline__ void eval_pair(const TargetRegs& T, Real<F32> sx, Real<F32> sy,
                                           Real<F32> sz, Real<F32> s2, Real<F32> w,
@@ -279,35 +295,73 @@ __device__ __forceinline__ TileArgs tile_args(const ReqView& V, int mode) {
 }
 
 constexpr int kMaxG = 32;   // source groups per target
-constexpr int kUnroll = 4;  // run_group reads the weights of kUnroll sources as one float4
-constexpr int kLds = kChunk + kUnroll * kMaxG;
+constexpr int kUnroll = 4;  // one staged group of four sources per unrolled step
+static_assert(kUnroll == 4, "Stage<true> packs sources in groups of four");
+// Sources staged per step of the tile kernel.  The staging buffer (20 bytes a
+// source in the FP32 form) and the block's other LDS arrays fit six blocks of
+// four waves in a CU's 160 KB, the occupancy the FP32 instances run at.
+constexpr int kTileChunk = 1024;
+constexpr int kLds = kTileChunk + kUnroll * kMaxG;
 
-// Staged sources: FP32 form (x, y, z, |s|^2) and weights; FP64 form (x, y, z, w).
+// Staged sources, recentred at the target cell, for CAP sources.  FP32 form:
+// groups of four sources, (x, y, z, |s|^2) each and then the four weights, so
+// that one LDS address serves a whole unrolled step; FP64 form: (x, y, z, w).
+template <bool F32, int CAP>
+struct StageT;
+template <int CAP>
+struct StageT<true, CAP> {
+    static_assert(CAP % 4 == 0, "groups of four");
+    struct Quad {
+        float4 p[4];
+        float4 w;
+    };
+    Quad b[CAP / 4];
+    __device__ __forceinline__ void put(int q, double x, double y, double z, double w) {
+        const float fx = float(x), fy = float(y), fz = float(z);
+        const float f2 = float(double(fx) * fx + double(fy) * fy + double(fz) * fz);
+        b[q >> 2].p[q & 3] = make_float4(fx, fy, fz, f2);
+        reinterpret_cast<float*>(&b[q >> 2].w)[q & 3] = float(w);
+    }
+};
+template <int CAP>
+struct StageT<false, CAP> {
+    struct Quad;
+    double4 p[CAP];
+    __device__ __forceinline__ void put(int q, double x, double y, double z, double w) {
+        p[q] = make_double4(x, y, z, w);
+    }
+};
 template <bool F32>
-struct Stage;
-template <>
-struct Stage<true> {
-    float4 p[kLds];
-    float w[kLds];
-};
-template <>
-struct Stage<false> {
-    double4 p[kLds];
-};
+using Stage = StageT<F32, kLds>;
 
-template <int KERN, bool F32, int FORM>
-__device__ __forceinline__ void run_group(const Stage<F32>& L, int base, int nj,
+// One-wave-per-leaf path: each wave stages up to kWaveChunk sources of its
+// own leaf at a time (padded to a multiple of four).
+constexpr int kWaveChunk = 256;
+template <bool F32>
+using WaveStage = StageT<F32, kWaveChunk + kUnroll>;
+
+// Sources per group when nq staged sources are split over G groups, a multiple
+// of the unroll (the tail is padded with weightless sources).
+__device__ __forceinline__ int group_len(int nq, int G) {
+    return (((nq + G - 1) / G) + kUnroll - 1) / kUnroll * kUnroll;
+}
+
+template <int KERN, bool F32, int FORM, int CAP>
+__device__ __forceinline__ void run_group(const StageT<F32, CAP>& L, int base, int nj,
                                           const TargetRegs& T, Real<F32>* p) {
     // nj is the same for every thread of the block: a scalar trip count keeps
     // the loop control off the vector unit
     nj = __builtin_amdgcn_readfirstlane(nj);
+    [[maybe_unused]] const typename StageT<F32, CAP>::Quad* Qp = nullptr;
+    if constexpr (F32) Qp = &L.b[base >> 2];  // base is a multiple of four
     for (int j = 0; j < nj; j += kUnroll) {
         if constexpr (F32) {
-            const float4 w4 = *reinterpret_cast<const float4*>(&L.w[base + j]);
+            const auto& Q = *Qp++;
+            const float4 w4 = Q.w;
             const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const float4 s = L.p[base + j + u];
+                const float4 s = Q.p[u];
                 eval_pair<KERN, true, FORM>(T, s.x, s.y, s.z, s.w, ws[u], p);
             }
         } else {
@@ -320,13 +374,72 @@ __device__ __forceinline__ void run_group(const Stage<F32>& L, int base, int nj,
     }
 }
 
+// Point o of a list entry (stage_source: recentred and scaled, into stage slot
+// q).  code >= 0: the entry is the particles of a leaf starting at sorted
+// position code; code < 0: the KS-strided proxies of cell -(code + 1) with
+// their weights.
+// Element i of a global array read through the global address space (a load
+// with a wave-uniform address then gives a wave-uniform value).
+template <class T>
+__device__ __forceinline__ T gload(const T* base, int64_t i) {
+    return ((const __attribute__((address_space(1))) T*)base)[i];
+}
+// A request view read word by word through the global address space, so that
+// its fields are wave-uniform values.
+__device__ __forceinline__ ReqView load_view(const ReqView* p) {
+    static_assert(sizeof(ReqView) % 8 == 0, "whole words");
+    ReqView v;
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(p);
+    uint64_t* dst = reinterpret_cast<uint64_t*>(&v);
+#pragma unroll
+    for (int i = 0; i < int(sizeof(ReqView) / 8); ++i) dst[i] = gload(src, i);
+    return v;
+}
+// The same for a wave-uniform base and a per-lane index i with i * sizeof(T)
+// below 2^32: a 32-bit byte offset on a scalar base address.
+template <class T>
+__device__ __forceinline__ T gload_near(const T* base, unsigned i) {
+    const unsigned byte = i * unsigned(sizeof(T));
+    return *(const __attribute__((address_space(1))) T*)(
+        (const __attribute__((address_space(1))) char*)base + byte);
+}
+
+__device__ __forceinline__ void load_source(const TileArgs& a, int code, int o, double& yx,
+                                            double& yy, double& yz, double& w) {
+    // o is below the entry's size (a leaf's points or KS proxies)
+    if (code >= 0) {
+        yx = gload_near(a.sx + code, o);
+        yy = gload_near(a.sy + code, o);
+        yz = gload_near(a.sz + code, o);
+        w = gload_near(a.sw + code, o);
+    } else {
+        const int64_t sc = -(code + 1);
+        const double* ps = a.sprox + sc * 3 * a.KS;
+        yx = gload_near(ps, o);
+        yy = gload_near(ps + a.KS, o);
+        yz = gload_near(ps + 2 * a.KS, o);
+        w = gload_near(a.swbar + sc * a.KS, o);
+    }
+}
+template <class St>
+__device__ __forceinline__ void stage_source(const TileArgs& a, int code, int o, double cx,
+                                             double cy, double cz, double scale, St& L, int q) {
+    double yx, yy, yz, w;
+    load_source(a, code, o, yx, yy, yz, w);
+    L.put(q, (yx - cx) * scale, (yy - cy) * scale, (yz - cz) * scale, w);
+}
+
 template <int KERN, bool F32>
 struct TileSmem {
     Stage<F32> L[1];
     int e_code[kMaxEntries];
     int e_pref[kMaxEntries + 1];
     int lw[4];
-    double red[vdim<KERN>()][kThreads];
+    // the per-target reduction over source groups reuses the staging buffer
+    static_assert(sizeof(Stage<F32>) >= sizeof(double) * vdim<KERN>() * kThreads, "red");
+    __device__ __forceinline__ double (*red())[kThreads] {
+        return reinterpret_cast<double (*)[kThreads]>(&L[0]);
+    }
 };
 
 // One target cell of one request: near field (TPROX = false) or far field.
@@ -340,10 +453,11 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
     int* e_code = sm.e_code;
     int* e_pref = sm.e_pref;
     int* lw = sm.lw;
-    auto& red = sm.red;
+    auto red = sm.red();
     const TileArgs a = tile_args<TPROX>(V, mode);
     const int T = a.tcells[local];
     const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const double cx = a.tcenter[3 * T], cy = a.tcenter[3 * T + 1], cz = a.tcenter[3 * T + 2];
     const int KS = a.KS;
     const int nT = TPROX ? a.K : a.tcount[T];
@@ -361,6 +475,7 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
         const int G = min(kThreads / TC, kMaxG);
         const int t = tid % TC, g = tid / TC;
         const bool active = g < G;
+        const int Tj_full = group_len(kTileChunk, G);
         double gx = cx, gy = cy, gz = cz;
         if (active) {
             if constexpr (TPROX) {
@@ -374,24 +489,14 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
                 gz = a.tz[tb + t0 + t];
             }
         }
-        TargetRegs TR;
-        TR.tx = (gx - cx) * scale;
-        TR.ty = (gy - cy) * scale;
-        TR.tz = (gz - cz) * scale;
-        TR.fx = float(TR.tx);
-        TR.fy = float(TR.ty);
-        TR.fz = float(TR.tz);
-        TR.f2 = float(double(TR.fx) * TR.fx + double(TR.fy) * TR.fy + double(TR.fz) * TR.fz);
-        TR.mx = -2.f * TR.fx;
-        TR.my = -2.f * TR.fy;
-        TR.mz = -2.f * TR.fz;
+        const TargetRegs TR = target_regs(gx - cx, gy - cy, gz - cz, scale);
         double acc[VD];
 #pragma unroll
         for (int v = 0; v < VD; ++v) acc[v] = 0.0;
 
         // Entries are processed in batches of up to kMaxEntries; inside a batch
         // the flattened sources split into the three forms (check, near, far)
-        // and each form into chunks of at most kChunk staged through LDS.
+        // and each form into chunks of at most kTileChunk staged through LDS.
         for (int ebase = 0; ebase < ne_all; ebase += kMaxEntries) {
             const int ne = min(kMaxEntries, ne_all - ebase);
             int sz = 0;
@@ -418,52 +523,36 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
             bnd[1] = e_pref[min(max(ph_hi[0] - ebase, 0), kMaxEntries)];
             bnd[2] = e_pref[min(max(ph_hi[1] - ebase, 0), kMaxEntries)];
             for (int ph = 0; ph < 3; ++ph) {
-                for (int q0 = bnd[ph]; q0 < bnd[ph + 1]; q0 += kChunk) {
-                    const int nq = min(kChunk, bnd[ph + 1] - q0);
-                    const int Tj = (((nq + G - 1) / G) + kUnroll - 1) / kUnroll * kUnroll;
+                for (int q0 = bnd[ph]; q0 < bnd[ph + 1]; q0 += kTileChunk) {
+                    const int nq = min(kTileChunk, bnd[ph + 1] - q0);
+                    const int Tj = nq == kTileChunk ? Tj_full : group_len(nq, G);
                     const int npad = G * Tj;
                     Stage<F32>& Lb = L[0];
-                    for (int q = tid; q < npad; q += kThreads) {
-                        double yx = 2.0, yy = 2.0, yz = 2.0, w = 0.0;  // padding: far, weightless
-                        if (q < nq) {
-                            const int gq = q0 + q;
-                            int lo = 0, hi = ne - 1;
-                            while (lo < hi) {
-                                const int mid = (lo + hi + 1) >> 1;
-                                if (e_pref[mid] <= gq)
-                                    lo = mid;
-                                else
-                                    hi = mid - 1;
-                            }
-                            const int o = gq - e_pref[lo];
-                            const int code = e_code[lo];
-                            if (code >= 0) {
-                                const int j = code + o;
-                                yx = a.sx[j];
-                                yy = a.sy[j];
-                                yz = a.sz[j];
-                                w = a.sw[j];
-                            } else {
-                                const int64_t sc = -(code + 1);
-                                const double* ps = a.sprox + sc * 3 * KS;
-                                yx = ps[o];
-                                yy = ps[KS + o];
-                                yz = ps[2 * KS + o];
-                                w = a.swbar[sc * KS + o];
-                            }
-                            yx = (yx - cx) * scale;
-                            yy = (yy - cy) * scale;
-                            yz = (yz - cz) * scale;
+                    // padding after the chunk: far away and weightless
+                    for (int q = nq + tid; q < npad; q += kThreads) Lb.put(q, 2.0, 2.0, 2.0, 0.0);
+                    // each wave stages whole entries (a leaf's contiguous particles or
+                    // a cell's proxies) that overlap [q0, q0 + nq), its lanes one point
+                    // each: no per-point search for the owning entry
+                    const int qe = q0 + nq;
+                    int e = 0;
+                    {
+                        int hi = ne - 1;
+                        while (e < hi) {
+                            const int mid = (e + hi + 1) >> 1;
+                            if (e_pref[mid] <= q0)
+                                e = mid;
+                            else
+                                hi = mid - 1;
                         }
-                        if constexpr (F32) {
-                            const float fx = float(yx), fy = float(yy), fz = float(yz);
-                            const float f2 =
-                                float(double(fx) * fx + double(fy) * fy + double(fz) * fz);
-                            Lb.p[q] = make_float4(fx, fy, fz, f2);
-                            Lb.w[q] = float(w);
-                        } else {
-                            Lb.p[q] = make_double4(yx, yy, yz, w);
-                        }
+                    }
+                    e = __builtin_amdgcn_readfirstlane(e) + wave;
+                    for (; e < ne; e += kThreads / 64) {
+                        const int pb = __builtin_amdgcn_readfirstlane(e_pref[e]);
+                        if (pb >= qe) break;
+                        const int pe = min(__builtin_amdgcn_readfirstlane(e_pref[e + 1]), qe);
+                        const int code = __builtin_amdgcn_readfirstlane(e_code[e]);
+                        for (int q = max(pb, q0) + lane; q < pe; q += 64)
+                            stage_source(a, code, q - pb, cx, cy, cz, scale, Lb, q - q0);
                     }
                     __syncthreads();
                     if (active) {
@@ -502,11 +591,137 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
     }
 }
 
+// Orders a wave's LDS stores before its later loads (and the reverse) across
+// lanes; the stage of the one-wave-per-leaf path belongs to one wave.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Near field of one target leaf of at most 64 particles on one wave: lane t
+// holds target t and sums over every source, so no cross-wave reduction and no
+// block barrier.  The entries are taken in list order, split into the same
+// three forms as tile_body (overlapping PP entries, the other PP entries, PC
+// entries), and staged up to kWaveChunk sources at a time.
+template <int KERN, bool F32>
+__device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int leaf,
+                                               WaveStage<F32>& L) {
+    using R = Real<F32>;
+    constexpr int VD = vdim<KERN>();
+    constexpr double scale = coord_scale<KERN>();
+    const TileArgs a = tile_args<false>(V, mode);
+    const int lane = threadIdx.x & 63;
+    // global loads of wave-uniform indices: uniform values (scalar registers)
+    const int T = gload(a.tcells, leaf);
+    const int nT = gload(a.tcount, T), tb = gload(a.tbegin, T);
+    const double cx = gload(a.tcenter, 3 * T), cy = gload(a.tcenter, 3 * T + 1),
+                 cz = gload(a.tcenter, 3 * T + 2);
+    const bool active = lane < nT;
+    const double gx = active ? gload_near(a.tx + tb, lane) : cx;
+    const double gy = active ? gload_near(a.ty + tb, lane) : cy;
+    const double gz = active ? gload_near(a.tz + tb, lane) : cz;
+    const TargetRegs TR = target_regs(gx - cx, gy - cy, gz - cz, scale);
+    double acc[VD];
+#pragma unroll
+    for (int v = 0; v < VD; ++v) acc[v] = 0.0;
+    const int ea0 = a.use_a ? gload(a.off_a, T) : 0;
+    const int nea = a.use_a ? gload(a.off_a, T + 1) - ea0 : 0;
+    const int eb0 = a.use_b ? gload(a.off_b, T) : 0;
+    const int neb = a.use_b ? gload(a.off_b, T + 1) - eb0 : 0;
+    const int nov = (a.use_a && a.novl) ? gload(a.novl, T) : 0;
+    for (int ph = 0; ph < 3; ++ph) {
+        const int e_beg = ph == 1 ? nov : 0;
+        const int e_end = ph == 0 ? nov : ph == 1 ? nea : neb;
+        // entry cache: lane l holds the code and size of entry cb + l
+        int cb = e_beg - 64, c_code = 0, c_size = 0;
+        int e = e_beg, off = 0;  // next entry and its sources already staged
+        while (e < e_end) {
+            // Up to four items of at most 64 sources (the rest of an entry or its
+            // next 64) per step: every lane issues the loads of its point of all
+            // items before the first store, one memory latency per step.
+            int it_code[4], it_off[4], it_cnt[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                it_code[k] = 0;
+                it_off[k] = 0;
+                it_cnt[k] = 0;
+                if (e < e_end) {
+                    if (e >= cb + 64) {
+                        cb = e;
+                        const int ee = cb + lane;
+                        c_code = 0;
+                        c_size = 0;
+                        if (ee < e_end) {
+                            if (ph < 2) {
+                                const int sc = gload(a.src_a, ea0 + ee);
+                                c_code = gload(a.sbegin, sc);
+                                c_size = gload(a.scount, sc);
+                            } else {
+                                c_code = -(gload(a.src_b, eb0 + ee) + 1);
+                                c_size = a.K;
+                            }
+                        }
+                    }
+                    const int size = __builtin_amdgcn_readlane(c_size, e - cb);
+                    it_code[k] = __builtin_amdgcn_readlane(c_code, e - cb);
+                    it_off[k] = off;
+                    it_cnt[k] = min(size - off, 64);
+                    off += it_cnt[k];
+                    if (off == size) {
+                        ++e;
+                        off = 0;
+                    }
+                }
+            }
+            // every lane loads (lanes past an item's end repeat its last point), so
+            // the loads need no per-lane branches
+            double yx[4], yy[4], yz[4], yw[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (it_cnt[k] > 0)
+                    load_source(a, it_code[k], it_off[k] + min(lane, it_cnt[k] - 1), yx[k],
+                                yy[k], yz[k], yw[k]);
+            int n = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (lane < it_cnt[k])
+                    L.put(n + lane, (yx[k] - cx) * scale, (yy[k] - cy) * scale,
+                          (yz[k] - cz) * scale, yw[k]);
+                n += it_cnt[k];
+            }
+            const int npad = (n + kUnroll - 1) / kUnroll * kUnroll;
+            if (lane < npad - n) L.put(n + lane, 2.0, 2.0, 2.0, 0.0);  // far, weightless
+            wave_sync();
+            R p[VD];
+#pragma unroll
+            for (int v = 0; v < VD; ++v) p[v] = R(0);
+            if (ph == 0)
+                run_group<KERN, F32, FORM_CHECK>(L, 0, npad, TR, p);
+            else if (ph == 1)
+                run_group<KERN, F32, FORM_NEAR>(L, 0, npad, TR, p);
+            else
+                run_group<KERN, F32, FORM_FAR>(L, 0, npad, TR, p);
+#pragma unroll
+            for (int v = 0; v < VD; ++v) acc[v] += double(p[v]);
+            wave_sync();
+        }
+    }
+    if (active) {
+        double o[VD];
+        epilogue<KERN, F32>(acc, gx, gy, gz, o);
+#pragma unroll
+        for (int v = 0; v < VD; ++v) a.out[v * a.comp_stride + tb + lane] = o[v];
+    }
+}
+
 // Far-field and near-field blocks in one grid: prefix2 locates far-field work
 // (none in a kTileNearPP launch), prefix near-field work.  Every XCD runs its
 // share of far-field blocks first and then its share of near-field blocks; in
 // a kTilePCFar launch the far-field blocks are the long ones and the short PC
-// blocks fill the tail.  The occupancy hint keeps the FP32
+// blocks fill the tail.  Near-field blocks of a request marked in leaf_wave
+// take four target leaves, one per wave (tile_leaf_wave); the others take one
+// leaf over the whole block (tile_body).  The occupancy hint keeps the FP32
 // instances at 80 VGPRs (6 waves per SIMD; measured faster than 5); the FP64
 // instances, whose transcendentals are longer, get 4 waves per SIMD.
 template <int KERN, bool F32>
@@ -520,8 +735,32 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 
         tile_body<KERN, F32, true>(*b.v[req], b.mode, local, sm);
     } else {
         batch_locate(b, blk, req, local);
-        tile_body<KERN, F32, false>(*b.v[req], b.mode, local, sm);
+        const ReqView V = load_view(b.v[req]);
+        if (b.leaf_wave[req]) {
+            // four leaves per block, one per wave, each wave with its own stage
+            static_assert(4 * sizeof(WaveStage<F32>) <= sizeof(sm), "wave stages");
+            const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+            const int leaf = 4 * local + wave;
+            auto* st = reinterpret_cast<WaveStage<F32>*>(&sm) + wave;
+            if (leaf < V.nleaves_t) tile_leaf_wave<KERN, F32>(V, b.mode, leaf, *st);
+        } else {
+            tile_body<KERN, F32, false>(V, b.mode, local, sm);
+        }
     }
+}
+
+// Near-field launch whose requests all take the one-wave-per-leaf path: four
+// target leaves per block, one a wave, the waves independent of each other
+// (measured faster than blocks of one wave).
+template <int KERN, bool F32>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 4))) void k_tile_wave(Batch b) {
+    __shared__ WaveStage<F32> st[kThreads / 64];
+    int req, local;
+    batch_locate(b, xcd_logical_block(blockIdx.x, gridDim.x), req, local);
+    const ReqView V = load_view(b.v[req]);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int leaf = 4 * local + wave;
+    if (leaf < V.nleaves_t) tile_leaf_wave<KERN, F32>(V, b.mode, leaf, st[wave]);
 }
 
 // ----------------------------------------------------------------- direct
@@ -791,7 +1030,10 @@ template <int KERN, bool F32>
 int launch_tile_t(const Batch& b, hipStream_t s) {
     const int nblocks = b.prefix[b.n] + b.prefix2[b.n];
     if (nblocks <= 0) return CSFMM_OK;
-    k_tile<KERN, F32><<<nblocks, kThreads, 0, s>>>(b);
+    if (b.wave_kernel)
+        k_tile_wave<KERN, F32><<<nblocks, kThreads, 0, s>>>(b);
+    else
+        k_tile<KERN, F32><<<nblocks, kThreads, 0, s>>>(b);
     CSFMM_LAUNCH_CHECK();
     return CSFMM_OK;
 }

@@ -136,6 +136,9 @@ CASES = {
     "tiny_p1_leaf1": lambda: (cubed_sphere_grid(2)[0], None, 1, 1, 0.5, 1),
     "biharmonic_E32": lambda: (cubed_sphere_grid(32)[0], None, 4, 8, 0.7, 64),
     "sal_distinct": lambda: (random_sphere_points(2000, 43), cubed_sphere_grid(16)[0], 5, 6, 0.6, 40),
+    # leaves of more than 64 points: the near field's block path (the other
+    # cases take the one-wave-per-leaf path)
+    "random_leaf100": lambda: (random_sphere_points(6000, 47), None, 1, 6, 0.7, 100),
 }
 
 
@@ -183,6 +186,20 @@ def test_lists(case):
         want[kind] = ev
     assert (st["evals_pp"], st["evals_pc"], st["evals_cp"], st["evals_cc"]) == \
         (want["PP"], want["PC"], want["CP"], want["CC"])
+    assert st["max_leaf_t"] == max(C.count for C in ofmm.ttree.cells if C.is_leaf)
+
+
+def test_cases_cover_both_near_field_paths():
+    """Leaves of at most 64 points take the one-wave-per-leaf near field, larger
+    ones the block path: the parity cases hold both."""
+    leaf_max = {}
+    for name in ("config1", "random_leaf100"):
+        T, S, k, p, th, leaf = CASES[name]()
+        pl = cs.Plan(tdev(T), None if S is None else tdev(S), kernel=k, p=p, theta=th,
+                     leaf_size=leaf)
+        leaf_max[name] = pl.stats()["max_leaf_t"]
+        pl.close()
+    assert leaf_max["config1"] <= 64 < leaf_max["random_leaf100"]
 
 
 def test_stages_and_result(case):
