@@ -86,6 +86,11 @@ typedef struct csfmm_stats {
     int64_t max_leaf_t;                    /* most points in a target leaf; leaves of at
                                               most 64 take the one-wave-per-leaf
                                               near-field path */
+    int64_t pp_sym_pairs, pp_one_way;      /* same-set plans: PP entries of distinct
+                                              leaves that hold both ways, counted once
+                                              per pair, and those that hold one way
+                                              (the FP32 form evaluates a pair once for
+                                              both directions); 0 otherwise */
 } csfmm_stats;
 
 /*

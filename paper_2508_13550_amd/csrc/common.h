@@ -104,6 +104,20 @@ struct Tree {
 // Interaction lists in CSR form by target cell.
 enum ListKind { kPP = 0, kPC = 1, kCP = 2, kCC = 3 };
 
+// Same-set plans: the PP entries of distinct leaves split by kernel symmetry.
+// A pair of leaves {T, S} whose PP entry holds both ways ((T, S) and (S, T))
+// is evaluated once, by its owner (pair_owner), for both directions: the
+// owner's own targets take the row sums, the partner's targets the column
+// sums, which go to a slot of the workspace and are added afterwards in list
+// order.  Entries that hold one way only stay one-directional.
+struct SymPP {
+    bool on = false;
+    int64_t n_own = 0, n_one = 0;  // owned pairs (as many are received), one-way entries
+    int32_t *own_off = nullptr, *own_src = nullptr;    // [ncells+1], [n_own]; slot = index
+    int32_t *recv_off = nullptr, *recv_slot = nullptr; // [ncells+1], [n_own]
+    int32_t *one_off = nullptr, *one_src = nullptr;    // [ncells+1], [n_one]
+};
+
 struct Lists {
     int64_t cnt[4] = {0, 0, 0, 0};
     int32_t* off[4] = {nullptr, nullptr, nullptr, nullptr};  // [ncells_t + 1]
@@ -112,6 +126,7 @@ struct Lists {
     int32_t* far_targets = nullptr;  // target cells with CP or CC entries
     int32_t n_far_targets = 0;
     int64_t evals[4] = {0, 0, 0, 0};
+    SymPP sym;
 };
 
 // Device-resident description of one (plan, workspace) pair: every pointer and
@@ -134,6 +149,9 @@ struct ReqView {
     int64_t nt, ns, psi_stride;
     int32_t p, K, KS, nb1;
     int32_t nleaves_t, pad_;
+    // symmetric PP split (SymPP) and its column-sum slots [n_own][kWaveLeaf]
+    const int32_t *own_off, *own_src, *recv_off, *recv_slot, *one_off, *one_src;
+    float* sym_col;
 };
 
 // Target leaves of at most this many points take the one-wave-per-leaf path of
@@ -156,6 +174,7 @@ struct Batch {
     int32_t mode;                    // tile launches: kTileNearPP or kTilePCFar
     int32_t leaf_wave[kMaxBatch];    // tile launches: request r's near field takes one wave per leaf
     int32_t wave_kernel;  // tile launches: near field only, all one wave per leaf: k_tile_wave
+    int32_t sym[kMaxBatch];  // PP launches: request r takes the symmetric PP path (sym_path)
 };
 
 // Tile launch modes.  The PP near field needs no proxy weights, so it runs on
@@ -233,6 +252,7 @@ struct csfmm_workspace_s {
     double* psi = nullptr;      // [3][ncells_t][KS]
     double* phinear = nullptr;  // [3][nt] PP near field
     double* phipc = nullptr;    // [3][nt] PC near field
+    float* sym_col = nullptr;   // [n_own][kWaveLeaf] column sums of symmetric PP pairs
     csfmm::ReqView* dview = nullptr;  // device copy of dview_host
     csfmm::ReqView dview_host{};
     // side stream of the PP near field, with its fork and join events
@@ -251,6 +271,19 @@ inline csfmm_plan_s::~csfmm_plan_s() {
     delete ws0;
     arena.release();
 }
+
+namespace csfmm {
+// The symmetric PP path: same-set plan in the FP32 form whose target leaves
+// take the one-wave-per-leaf path; an eval uses it for the scalar kernels
+// (K(x, y) = K(y, x)), not for Biot-Savart.
+inline bool sym_path_possible(const csfmm_plan_s* P) {
+    return P->lists.sym.on && (P->flags & CSFMM_FP32_FORM) && P->tt.max_leaf <= kWaveLeaf &&
+           P->lists.sym.n_own > 0;
+}
+inline bool sym_path(const csfmm_plan_s* P, int kernel) {
+    return sym_path_possible(P) && kernel != CSFMM_K_BIOT_SAVART;
+}
+}  // namespace csfmm
 
 namespace csfmm {
 
@@ -286,6 +319,7 @@ int run_treecode(csfmm_plan_s* P, int kernel, const double* weights, double* out
 
 // ---- tile engine (tile.hip): b holds requests of one kernel and form
 int launch_tile_batch(const Batch& b, int kernel, bool fp32, hipStream_t s);
+int launch_sym_merge(const Batch& b, int kernel, hipStream_t s);
 
 // Cubed sphere treecode (paper §7, Algorithm 1): one traversal of the source
 // tree per target particle, FP64.

@@ -525,6 +525,8 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
             // one-wave-per-leaf path, else one
             const Tree& tt = reqs[r].plan->tt;
             g.leaf_wave[q] = tt.max_leaf <= kWaveLeaf ? 1 : 0;
+            // the symmetric PP path needs k_tile_wave (one wave per leaf, PP only)
+            g.sym[q] = (g.wave_kernel && sym_path(reqs[r].plan, reqs[r].kernel)) ? 1 : 0;
             tn += g.leaf_wave[q] ? (int64_t(tt.nleaves) + 3) / 4 : tt.nleaves;
             tf += mode == kTilePCFar ? reqs[r].plan->lists.n_far_targets : 0;
         }
@@ -544,6 +546,10 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
             Batch g;
             RCX(tile_group(kv.second, kTileNearPP, g));
             RCX(launch_tile_batch(g, kv.first.first, kv.first.second != 0, side));
+            // column sums of the symmetric pairs, once every pair is done
+            bool any_sym = false;
+            for (int q = 0; q < g.n; ++q) any_sym = any_sym || g.sym[q];
+            if (any_sym) RCX(launch_sym_merge(g, kv.first.first, side));
         }
         RCX(mark(Timing::kMain + 1));
         CSFMM_HIP_TRY(hipEventRecord(W0->join, side));
@@ -660,6 +666,8 @@ int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** ou
     if (rc == CSFMM_OK) rc = W->arena.alloc(&W->psi, int64_t(3) * T.ncells * P->KS);
     if (rc == CSFMM_OK) rc = W->arena.alloc(&W->phinear, int64_t(3) * P->nt);
     if (rc == CSFMM_OK) rc = W->arena.alloc(&W->phipc, int64_t(3) * P->nt);
+    if (rc == CSFMM_OK && sym_path_possible(P))
+        rc = W->arena.alloc(&W->sym_col, P->lists.sym.n_own * kWaveLeaf);
     if (rc == CSFMM_OK) rc = W->arena.alloc(&W->dview, 1);
     if (rc != CSFMM_OK) {
         delete W;
@@ -696,6 +704,10 @@ int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** ou
     v.psi_stride = int64_t(T.ncells) * P->KS;
     v.p = P->p; v.K = P->K; v.KS = P->KS; v.nb1 = P->nb1;
     v.nleaves_t = T.nleaves;
+    const SymPP& Y = P->lists.sym;
+    v.own_off = Y.own_off; v.own_src = Y.own_src; v.recv_off = Y.recv_off;
+    v.recv_slot = Y.recv_slot; v.one_off = Y.one_off; v.one_src = Y.one_src;
+    v.sym_col = W->sym_col;
     k_set_view<<<1, 64, 0, stream>>>(W->dview, v);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(stream);

@@ -222,6 +222,79 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
     if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
 }
 
+// *a = *b = *c = 0 (the element past the entries of three kind arrays)
+__global__ void k_zero_i32x3(int32_t* __restrict__ a, int32_t* __restrict__ b,
+                             int32_t* __restrict__ c) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a = *b = *c = 0;
+}
+
+// Owner of the unordered pair of cells {t, s}, t != s: the smaller id when
+// t + s is odd, else the larger, so that every cell owns about half of its
+// symmetric pairs.
+__device__ __forceinline__ int pair_owner(int t, int s) {
+    return ((t + s) & 1) ? (t < s ? t : s) : (t < s ? s : t);
+}
+
+// Index of the entry of cell c whose source is x in the CSR lists, or -1.
+__device__ __forceinline__ int pp_find(const int32_t* off, const int32_t* src, int c, int x) {
+    for (int e = off[c]; e < off[c + 1]; ++e)
+        if (src[e] == x) return e;
+    return -1;
+}
+
+// Symmetric split of the PP entries of a same-set plan (see SymPP), per
+// target cell: each entry past the overlapping head (the cell itself) is
+// one-way (kind_one), a symmetric pair the cell owns (kind_own) or one its
+// partner owns (kind_recv, rev = the partner's entry of the pair).  One
+// element past the entries stays 0, so exclusive scans of the kinds give the
+// positions and, at off[t], the offsets of every cell.  One wave per target
+// cell, a lane per entry.
+__global__ void k_sym_kinds(int ncells, const int32_t* __restrict__ off,
+                            const int32_t* __restrict__ src, const int32_t* __restrict__ novl,
+                            int32_t* __restrict__ kind_own, int32_t* __restrict__ kind_recv,
+                            int32_t* __restrict__ kind_one, int32_t* __restrict__ rev) {
+    const int t = int(blockIdx.x) * (blockDim.x / 64) + int(threadIdx.x / 64);
+    if (t >= ncells) return;
+    for (int e = off[t] + int(threadIdx.x % 64); e < off[t + 1]; e += 64) {
+        int k = 0, r = -1;
+        if (e >= off[t] + novl[t]) {
+            const int c = src[e];
+            r = c != t ? pp_find(off, src, c, t) : -1;
+            k = r < 0 ? 1 : (pair_owner(t, c) == t ? 2 : 3);
+        }
+        kind_own[e] = k == 2;
+        kind_recv[e] = k == 3;
+        kind_one[e] = k == 1;
+        rev[e] = r;
+    }
+}
+
+// Fills the SymPP arrays from the exclusive scans of the kinds (over the
+// entries plus one): owned and one-way entries keep their list order; the
+// slot of a received pair is the owned position of the partner's entry.
+// Thread e writes entry e and, for e <= ncells, the offsets of cell e.
+__global__ void k_sym_fill(int ncells, int64_t nent, const int32_t* __restrict__ off,
+                           const int32_t* __restrict__ src, const int32_t* __restrict__ kind_own,
+                           const int32_t* __restrict__ kind_recv,
+                           const int32_t* __restrict__ kind_one, const int32_t* __restrict__ rev,
+                           const int32_t* __restrict__ own_ex, const int32_t* __restrict__ recv_ex,
+                           const int32_t* __restrict__ one_ex, int32_t* __restrict__ own_off,
+                           int32_t* __restrict__ own_src, int32_t* __restrict__ recv_off,
+                           int32_t* __restrict__ recv_slot, int32_t* __restrict__ one_off,
+                           int32_t* __restrict__ one_src) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e <= ncells) {
+        const int b = off[e];  // off[ncells] = nent
+        own_off[e] = own_ex[b];
+        recv_off[e] = recv_ex[b];
+        one_off[e] = one_ex[b];
+    }
+    if (e >= nent) return;
+    if (kind_own[e]) own_src[own_ex[e]] = src[e];
+    if (kind_one[e]) one_src[one_ex[e]] = src[e];
+    if (kind_recv[e]) recv_slot[recv_ex[e]] = own_ex[rev[e]];
+}
+
 // Largest point count over the leaves of a tree.
 __global__ void k_max_leaf(const int32_t* __restrict__ leaves, int nleaves,
                            const int32_t* __restrict__ count, unsigned long long* __restrict__ mx) {
@@ -856,6 +929,50 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
     CSFMM_HIP_TRY(hipStreamSynchronize(s));
     for (int k = 0; k < 4; ++k) P->lists.evals[k] = int64_t(hev[k]);
     T.max_leaf = int32_t(hev[4]);
+
+    // symmetric split of the PP entries (same-set plans)
+    if (P->same) {
+        SymPP& Y = P->lists.sym;
+        const int nc = T.ncells;
+        const int64_t ne = P->lists.cnt[kPP];
+        int32_t *ko, *kr, *k1, *rev, *eo, *er, *e1;
+        RC(S.get(&ko, ne + 1));
+        RC(S.get(&kr, ne + 1));
+        RC(S.get(&k1, ne + 1));
+        RC(S.get(&rev, ne + 1));
+        RC(S.get(&eo, ne + 1));
+        RC(S.get(&er, ne + 1));
+        RC(S.get(&e1, ne + 1));
+        const int32_t *off = P->lists.off[kPP], *src = P->lists.src[kPP];
+        k_zero_i32x3<<<1, 1, 0, s>>>(ko + ne, kr + ne, k1 + ne);
+        k_sym_kinds<<<nblk(int64_t(nc) * 64), kT, 0, s>>>(nc, off, src, P->lists.novl, ko, kr, k1,
+                                                          rev);
+        CSFMM_LAUNCH_CHECK();
+        int32_t tot[3];
+        RC(scan_exclusive_i32(ko, eo, ne + 1, dtot, s));
+        RC(read_i32(dtot, &tot[0], s));
+        RC(scan_exclusive_i32(kr, er, ne + 1, dtot, s));
+        RC(read_i32(dtot, &tot[1], s));
+        RC(scan_exclusive_i32(k1, e1, ne + 1, dtot, s));
+        RC(read_i32(dtot, &tot[2], s));
+        if (tot[0] != tot[1]) {
+            set_error("symmetric PP pairs: %d owned but %d received", tot[0], tot[1]);
+            return CSFMM_E_HIP;
+        }
+        Y.n_own = tot[0];
+        Y.n_one = tot[2];
+        RC(A.alloc(&Y.own_off, int64_t(nc) + 1));
+        RC(A.alloc(&Y.recv_off, int64_t(nc) + 1));
+        RC(A.alloc(&Y.one_off, int64_t(nc) + 1));
+        RC(A.alloc(&Y.own_src, std::max<int64_t>(Y.n_own, 1)));
+        RC(A.alloc(&Y.recv_slot, std::max<int64_t>(Y.n_own, 1)));
+        RC(A.alloc(&Y.one_src, std::max<int64_t>(Y.n_one, 1)));
+        k_sym_fill<<<nblk(std::max<int64_t>(ne, int64_t(nc) + 1)), kT, 0, s>>>(
+            nc, ne, off, src, ko, kr, k1, rev, eo, er, e1, Y.own_off, Y.own_src, Y.recv_off,
+            Y.recv_slot, Y.one_off, Y.one_src);
+        CSFMM_LAUNCH_CHECK();
+        Y.on = true;
+    }
     return CSFMM_OK;
 }
 

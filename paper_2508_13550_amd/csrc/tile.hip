@@ -155,6 +155,26 @@ __device__ __forceinline__ TargetRegs target_regs(double dx, double dy, double d
     return TR;
 }
 
+// FP32 expanded squared distance |t|^2 + |s|^2 - 2 t.s (FORM_NEAR, FORM_FAR).
+__device__ __forceinline__ float expanded_d2(const TargetRegs& T, float sx, float sy, float sz,
+                                             float s2) {
+    return fmaf(T.mx, sx, fmaf(T.my, sy, fmaf(T.mz, sz, s2 + T.f2)));
+}
+
+// Unscaled value of a scalar kernel at scaled squared distance d (FP32 form):
+// log2 d (Poisson), dilog(1 - d) (biharmonic), the SAL bracket, 1/sqrt(d).
+template <int KERN>
+__device__ __forceinline__ float kernel_value_f32(float d) {
+    if constexpr (KERN == CSFMM_K_POISSON_LOG)
+        return dev_log2(d);
+    else if constexpr (KERN == CSFMM_K_BIHARMONIC)
+        return dilog_1m(d);
+    else if constexpr (KERN == CSFMM_K_SAL)
+        return sal_bracket(d);
+    else
+        return dev_rsq(d);
+}
+
 template <int KERN, bool F32, int FORM>
 __device__ __forceinline__ void eval_pair(const TargetRegs& T, Real<F32> sx, Real<F32> sy,
                                           Real<F32> sz, Real<F32> s2, Real<F32> w,
@@ -168,15 +188,7 @@ __device__ __forceinline__ void eval_pair(const TargetRegs& T, Real<F32> sx, Rea
     }
     constexpr bool expanded = F32 && FORM != FORM_CHECK && KERN != CSFMM_K_BIOT_SAVART;
     if constexpr (expanded) {
-        const float d = fmaf(T.mx, sx, fmaf(T.my, sy, fmaf(T.mz, sz, s2 + T.f2)));
-        if constexpr (KERN == CSFMM_K_POISSON_LOG)
-            p[0] = fmaf(w, dev_log2(d), p[0]);
-        else if constexpr (KERN == CSFMM_K_BIHARMONIC)
-            p[0] = fmaf(w, dilog_1m(d), p[0]);
-        else if constexpr (KERN == CSFMM_K_SAL)
-            p[0] = fmaf(w, sal_bracket(d), p[0]);
-        else
-            p[0] = fmaf(w, dev_rsq(d), p[0]);
+        p[0] = fmaf(w, kernel_value_f32<KERN>(expanded_d2(T, sx, sy, sz, s2)), p[0]);
     } else {
         (void)s2;
         const R dx = sx - tx, dy = sy - ty, dz = sz - tz;
@@ -591,6 +603,77 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
     }
 }
 
+// One wave's LDS on the symmetric PP path: one partner leaf staged (up to 64
+// sources) and a 64 x 16 tile of column terms.  It overlays the wave's
+// stage of the other phases (SymLds is the larger of the two).
+constexpr int kSymCols = 16;           // columns reduced per tile
+constexpr int kSymCol = kWaveLeaf + 4;  // tile column stride in floats (no bank conflicts)
+struct SymLds {
+    StageT<true, kWaveLeaf> st;
+    float m[kSymCols * kSymCol];  // column c, row i (target lane): m[kSymCol c + i]
+};
+template <bool F32>
+constexpr int wave_lds_bytes() {
+    return F32 && sizeof(SymLds) > sizeof(WaveStage<F32>) ? int(sizeof(SymLds))
+                                                           : int(sizeof(WaveStage<F32>));
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_quad(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
+                                                                 CTRL, 0xf, 0xf, true));
+}
+
+__device__ __forceinline__ void wave_sync();
+
+// One symmetric PP pair on the wave of its owner A: for every staged source j
+// of the partner B (nj, a multiple of 16, padded with weightless sources) the
+// kernel value g_ij at every lane's target i of A serves both directions: the
+// row sum p_i += w_j g_ij and the column sum col_j = sum_i wA_i g_ij.  The
+// column terms of 16 sources go through the LDS tile (column-major): lane i
+// writes its term of each column, then lane l sums rows 16 (l % 4) .. + 15 of
+// column l / 4 and a quad reduction joins the four partial sums; col_j goes
+// to colout[j] for j < nB.
+template <int KERN>
+__device__ __forceinline__ void run_sym(SymLds& S, int base, int nj, int nB,
+                                        const TargetRegs& T, float wA, float* p,
+                                        float* __restrict__ colout) {
+    const int lane = threadIdx.x & 63;
+    nj = __builtin_amdgcn_readfirstlane(nj);
+    for (int j0 = 0; j0 < nj; j0 += kSymCols) {
+        float c[kSymCols];
+#pragma unroll
+        for (int q = 0; q < kSymCols / 4; ++q) {
+            const auto& Q = S.st.b[((base + j0) >> 2) + q];
+            const float4 w4 = Q.w;
+            const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float4 sp = Q.p[u];
+                const float g = kernel_value_f32<KERN>(expanded_d2(T, sp.x, sp.y, sp.z, sp.w));
+                p[0] = fmaf(ws[u], g, p[0]);
+                c[4 * q + u] = wA * g;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSymCols; ++u) S.m[kSymCol * u + lane] = c[u];
+        wave_sync();
+        const int col = lane >> 2, r0 = lane & 3;
+        const float4* cp = reinterpret_cast<const float4*>(&S.m[kSymCol * col + 16 * r0]);
+        float4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = cp[k];
+        float part[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) part[k] = (v[k].x + v[k].y) + (v[k].z + v[k].w);
+        float sum = (part[0] + part[1]) + (part[2] + part[3]);
+        sum += dpp_quad<0xB1>(sum);  // quad_perm [1,0,3,2]
+        sum += dpp_quad<0x4E>(sum);  // quad_perm [2,3,0,1]
+        if (r0 == 0 && j0 + col < nB) colout[j0 + col] = sum;
+        wave_sync();
+    }
+}
+
 // Orders a wave's LDS stores before its later loads (and the reverse) across
 // lanes; the stage of the one-wave-per-leaf path belongs to one wave.
 __device__ __forceinline__ void wave_sync() {
@@ -599,14 +682,52 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The symmetric pairs owned by target leaf T (one wave, lane = target of T),
+// one partner leaf (at most 64 points) at a time, padded to a multiple of 16;
+// the loads of the next partner are in flight while the current one is
+// evaluated.  Row sums into acc, column sums to the pair's slot of sym_col.
+template <int KERN>
+__device__ __forceinline__ void sym_pairs(const TileArgs& a, const ReqView& V, int T, int tb,
+                                          int nT, double cx, double cy, double cz,
+                                          const TargetRegs& TR, double* acc, SymLds& S) {
+    constexpr double scale = coord_scale<KERN>();
+    const int lane = threadIdx.x & 63;
+    // T's points as sources of the column direction (same set: same order)
+    const float wA = lane < nT ? float(gload_near(a.sw + tb, lane)) : 0.f;
+    const int o0 = gload(V.own_off, T), o1 = gload(V.own_off, T + 1);
+    int cnt = 0;
+    double yx = 0.0, yy = 0.0, yz = 0.0, yw = 0.0;
+    auto fetch = [&](int k) {
+        const int c = gload(V.own_src, k);
+        const int code = gload(a.sbegin, c);
+        cnt = gload(a.scount, c);
+        if (cnt > 0) load_source(a, code, min(lane, cnt - 1), yx, yy, yz, yw);
+    };
+    if (o0 < o1) fetch(o0);
+    float p = 0.f;
+    for (int k = o0; k < o1; ++k) {
+        const int n = cnt, npad = (n + kSymCols - 1) / kSymCols * kSymCols;
+        if (lane < n)
+            S.st.put(lane, (yx - cx) * scale, (yy - cy) * scale, (yz - cz) * scale, yw);
+        else if (lane < npad)
+            S.st.put(lane, 2.0, 2.0, 2.0, 0.0);  // far, weightless
+        wave_sync();
+        if (k + 1 < o1) fetch(k + 1);
+        if (n > 0) run_sym<KERN>(S, 0, npad, n, TR, wA, &p, V.sym_col + int64_t(k) * kWaveLeaf);
+        wave_sync();
+    }
+    acc[0] += double(p);
+}
+
 // Near field of one target leaf of at most 64 particles on one wave: lane t
 // holds target t and sums over every source, so no cross-wave reduction and no
 // block barrier.  The entries are taken in list order, split into the same
 // three forms as tile_body (overlapping PP entries, the other PP entries, PC
 // entries), and staged up to kWaveChunk sources at a time.
 template <int KERN, bool F32>
-__device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int leaf,
-                                               WaveStage<F32>& L) {
+__device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int leaf, bool sym,
+                                               char* lds) {
+    WaveStage<F32>& L = *reinterpret_cast<WaveStage<F32>*>(lds);
     using R = Real<F32>;
     constexpr int VD = vdim<KERN>();
     constexpr double scale = coord_scale<KERN>();
@@ -630,9 +751,16 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
     const int eb0 = a.use_b ? gload(a.off_b, T) : 0;
     const int neb = a.use_b ? gload(a.off_b, T + 1) - eb0 : 0;
     const int nov = (a.use_a && a.novl) ? gload(a.novl, T) : 0;
+    // symmetric PP path (FP32 scalar kernels, PP launch): the distinct leaves'
+    // entries split into one-way entries (here, phase 1) and owned pairs
+    // (sym_pairs below); pairs owned by the partner come in through k_sym_merge
+    constexpr bool kSymKernel = F32 && KERN != CSFMM_K_BIOT_SAVART;
+    sym = kSymKernel && sym && a.use_a;
+    const int32_t* list1 = sym ? V.one_src : a.src_a + ea0;
+    const int one0 = sym ? gload(V.one_off, T) : 0;
     for (int ph = 0; ph < 3; ++ph) {
-        const int e_beg = ph == 1 ? nov : 0;
-        const int e_end = ph == 0 ? nov : ph == 1 ? nea : neb;
+        const int e_beg = ph == 1 ? (sym ? one0 : nov) : 0;
+        const int e_end = ph == 0 ? nov : ph == 1 ? (sym ? gload(V.one_off, T + 1) : nea) : neb;
         // entry cache: lane l holds the code and size of entry cb + l
         int cb = e_beg - 64, c_code = 0, c_size = 0;
         int e = e_beg, off = 0;  // next entry and its sources already staged
@@ -654,7 +782,8 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
                         c_size = 0;
                         if (ee < e_end) {
                             if (ph < 2) {
-                                const int sc = gload(a.src_a, ea0 + ee);
+                                const int sc = ph == 0 ? gload(a.src_a, ea0 + ee)
+                                                       : gload(list1, ee);
                                 c_code = gload(a.sbegin, sc);
                                 c_size = gload(a.scount, sc);
                             } else {
@@ -707,6 +836,11 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
             wave_sync();
         }
     }
+    if constexpr (kSymKernel) {
+        if (sym)
+            sym_pairs<KERN>(a, V, T, tb, nT, cx, cy, cz, TR, acc,
+                            *reinterpret_cast<SymLds*>(lds));
+    }
     if (active) {
         double o[VD];
         epilogue<KERN, F32>(acc, gx, gy, gz, o);
@@ -738,11 +872,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 
         const ReqView V = load_view(b.v[req]);
         if (b.leaf_wave[req]) {
             // four leaves per block, one per wave, each wave with its own stage
+            // (the symmetric PP path runs in k_tile_wave only)
             static_assert(4 * sizeof(WaveStage<F32>) <= sizeof(sm), "wave stages");
             const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
             const int leaf = 4 * local + wave;
-            auto* st = reinterpret_cast<WaveStage<F32>*>(&sm) + wave;
-            if (leaf < V.nleaves_t) tile_leaf_wave<KERN, F32>(V, b.mode, leaf, *st);
+            char* st = reinterpret_cast<char*>(&sm) + wave * sizeof(WaveStage<F32>);
+            if (leaf < V.nleaves_t) tile_leaf_wave<KERN, F32>(V, b.mode, leaf, false, st);
         } else {
             tile_body<KERN, F32, false>(V, b.mode, local, sm);
         }
@@ -754,13 +889,44 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 
 // (measured faster than blocks of one wave).
 template <int KERN, bool F32>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 4))) void k_tile_wave(Batch b) {
-    __shared__ WaveStage<F32> st[kThreads / 64];
+    constexpr int kWaveBytes = wave_lds_bytes<F32>();
+    __shared__ __attribute__((aligned(16))) char lds[(kThreads / 64) * kWaveBytes];
     int req, local;
     batch_locate(b, xcd_logical_block(blockIdx.x, gridDim.x), req, local);
     const ReqView V = load_view(b.v[req]);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int leaf = 4 * local + wave;
-    if (leaf < V.nleaves_t) tile_leaf_wave<KERN, F32>(V, b.mode, leaf, st[wave]);
+    if (leaf < V.nleaves_t)
+        tile_leaf_wave<KERN, F32>(V, b.mode, leaf, b.sym[req] != 0, lds + wave * kWaveBytes);
+}
+
+// Adds the column sums of the symmetric PP pairs owned by other leaves to the
+// near field of each target leaf (one wave per leaf, four per block, the
+// block layout of the PP launch), in the order of the leaf's receive list, so
+// the result does not depend on scheduling.
+template <int KERN, bool F32>
+__global__ __launch_bounds__(kThreads) void k_sym_merge(Batch b) {
+    int req, local;
+    batch_locate(b, xcd_logical_block(blockIdx.x, gridDim.x), req, local);
+    if (!b.sym[req]) return;
+    const ReqView V = load_view(b.v[req]);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int leaf = 4 * local + wave;
+    if (leaf >= V.nleaves_t) return;
+    const int T = gload(V.t_leaves, leaf);
+    const int nT = gload(V.t_count, T), tb = gload(V.t_begin, T);
+    const int r0 = gload(V.recv_off, T), r1 = gload(V.recv_off, T + 1);
+    double acc = 0.0;
+    for (int k = r0; k < r1; ++k) {
+        const int64_t slot = gload(V.recv_slot, k);
+        if (lane < nT) acc += double(V.sym_col[slot * kWaveLeaf + lane]);
+    }
+    if (lane < nT && r1 > r0) {
+        double o;
+        epilogue<KERN, F32>(&acc, 0.0, 0.0, 0.0, &o);
+        V.phinear[tb + lane] += o;
+    }
 }
 
 // ----------------------------------------------------------------- direct
@@ -1065,6 +1231,27 @@ int launch_direct_t(const double* tgt, int64_t nt, const double* src, int64_t ns
 }
 
 }  // namespace
+
+template <int KERN>
+int launch_sym_merge_t(const Batch& b, hipStream_t s) {
+    const int nblocks = b.prefix[b.n];
+    if (nblocks <= 0) return CSFMM_OK;
+    k_sym_merge<KERN, true><<<nblocks, kThreads, 0, s>>>(b);
+    CSFMM_LAUNCH_CHECK();
+    return CSFMM_OK;
+}
+
+int launch_sym_merge(const Batch& b, int kernel, hipStream_t s) {
+    switch (kernel) {
+        case CSFMM_K_POISSON_LOG: return launch_sym_merge_t<1>(b, s);
+        case CSFMM_K_INV_DIST: return launch_sym_merge_t<3>(b, s);
+        case CSFMM_K_BIHARMONIC: return launch_sym_merge_t<4>(b, s);
+        case CSFMM_K_SAL: return launch_sym_merge_t<5>(b, s);
+        default:
+            set_error("no symmetric PP path for kernel id %d", kernel);
+            return CSFMM_E_INVALID;
+    }
+}
 
 int launch_tile_batch(const Batch& b, int kernel, bool fp32, hipStream_t s) {
     switch (kernel) {

@@ -187,6 +187,16 @@ def test_lists(case):
     assert (st["evals_pp"], st["evals_pc"], st["evals_cp"], st["evals_cc"]) == \
         (want["PP"], want["PC"], want["CP"], want["CC"])
     assert st["max_leaf_t"] == max(C.count for C in ofmm.ttree.cells if C.is_leaf)
+    # same-set plans: PP entries of distinct leaves split into pairs that hold
+    # both ways (once per pair) and one-way entries
+    pp = set((Tc.id, Sc.id) for Tc, Sc in ofmm.lists["PP"])
+    if S is None:
+        both = sum(1 for a, b in pp if a != b and (b, a) in pp)
+        one = sum(1 for a, b in pp if a != b and (b, a) not in pp)
+        assert both % 2 == 0
+        assert (st["pp_sym_pairs"], st["pp_one_way"]) == (both // 2, one)
+    else:
+        assert (st["pp_sym_pairs"], st["pp_one_way"]) == (0, 0)
 
 
 def test_cases_cover_both_near_field_paths():
@@ -244,6 +254,26 @@ def test_fp32_form_close_to_fp64(case):
     plan32.close()
     print("fp32 vs fp64 rel_l2 %.3e" % rel_l2(b, a), flush=True)
     assert rel_l2(b, a) < 5e-6 * CANCEL[k]
+
+
+def test_fp32_near_field_matches_oracle(case):
+    """FP32 form near field (PP + PC) against the oracle's near field: same-set
+    plans with leaves of at most 64 points evaluate each symmetric PP pair once
+    for both directions; the others one direction at a time."""
+    name, T, S, k, p, th, leaf, ofmm, plan = case
+    src = T if S is None else S
+    w = np.random.default_rng(5).standard_normal(src.shape[0])
+    ref, stg = ofmm.evaluate(w, stages=True)
+    plan32 = cs.Plan(tdev(T), None if S is None else tdev(S), kernel=k, p=p, theta=th,
+                     leaf_size=leaf, fp32=True)
+    out, wbar, psi, near = plan32.eval_stages(tdev(w))
+    near = host(near)
+    again = host(plan32.eval(tdev(w)))
+    assert np.array_equal(again, host(plan32.eval(tdev(w))))  # deterministic
+    plan32.close()
+    err = rel_l2(near, stg["near"])
+    print("fp32 near field rel_l2 %.3e" % err, flush=True)
+    assert err < 2e-6 * CANCEL[k]
 
 
 def test_deterministic(case):
