@@ -80,7 +80,7 @@ def recorded_traffic():
         h = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
-    return rec["traffic_bytes_per_launch"] if rec.get("tile_hip_sha256") == h else None
+    return rec if rec.get("tile_hip_sha256") == h else None
 
 
 def copy_calibration():
@@ -720,12 +720,22 @@ def main():
     pp_ms = head["stage"]["near_pp_timed_region"]
     achieved = st["evals_pp"] * FLOP_PER_EVAL / (pp_ms / 1e3) / 1e12
     peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
+    rec = recorded_traffic() if (fp32 and head["p"] == 6) else None
     roofline = {"bound": "alu",
-                "kernel": "k_tile<Poisson,%s> PP near-field launch" % args.form.upper(),
+                "kernel": ("k_tile_wave<Poisson,FP32> + k_sym_merge: PP near-field stage"
+                           if fp32 else "k_tile<Poisson,FP64> PP near-field launch"),
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": recorded_traffic() if (fp32 and head["p"] == 6) else None,
+                "traffic": rec["traffic_bytes_per_launch"] if rec else None,
                 "flop_per_eval": FLOP_PER_EVAL, "evals_per_launch": st["evals_pp"],
                 "avg_launch_ms": pp_ms}
+    if rec:
+        # executed work from the counter record: kernel values computed (the
+        # symmetric pairs serve both directions) and VALU issue slots, per
+        # algorithmic evaluation
+        sq = rec["sq"]
+        roofline["kernel_values_per_eval"] = sq["SQ_INSTS_VALU_TRANS_F32"] * 64 / st["evals_pp"]
+        roofline["valu_issue_slots_per_eval"] = ((sq["SQ_INSTS_VALU"] + sq["SQ_INSTS_VALU_TRANS_F32"])
+                                                 * 64 / st["evals_pp"])
     far_ms = head["stage"]["pc_far"]
     evals_far = st["evals_pc"] + st["evals_cp"] + st["evals_cc"]
     roofline_far = {"kernel": "k_tile<Poisson,%s> PC near field + CP/CC far field launch"
