@@ -91,6 +91,11 @@ typedef struct csfmm_stats {
                                               per pair, and those that hold one way
                                               (the FP32 form evaluates a pair once for
                                               both directions); 0 otherwise */
+    int64_t near_exact;                    /* FP32 form: 1 when points come within 1/8 of a
+                                              half leaf width of each other across leaf
+                                              edges, so the PP entries of non-overlapping
+                                              leaves take exact differences (and no
+                                              symmetric pairs) */
 } csfmm_stats;
 
 /*

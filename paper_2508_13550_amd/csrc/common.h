@@ -81,6 +81,7 @@ struct Tree {
     int64_t n = 0;
     int32_t ncells = 0, nleaves = 0, depth = 0;
     int32_t max_leaf = 0;  // largest number of points in a leaf
+    float min_gap = 1.f;   // least 1 - max(|u|, |v|) over the points (local leaf coordinates)
     std::vector<int32_t> level_begin;   // host: first cell of each level, + end
     std::vector<int32_t> parents_begin; // host: first entry of each level in `parents`
     // sorted points (SoA) and their caller indices
@@ -148,7 +149,8 @@ struct ReqView {
     double *ws, *wbar, *psi, *phinear, *phipc;
     int64_t nt, ns, psi_stride;
     int32_t p, K, KS, nb1;
-    int32_t nleaves_t, pad_;
+    int32_t nleaves_t;
+    int32_t near_exact;  // near field of non-overlapping cells in exact differences (FP32 form)
     // symmetric PP split (SymPP) and its column-sum slots [n_own][kWaveLeaf]
     const int32_t *own_off, *own_src, *recv_off, *recv_slot, *one_off, *one_src;
     float* sym_col;
@@ -211,6 +213,10 @@ struct csfmm_workspace_s;
 struct csfmm_plan_s {
     int64_t nt = 0, ns = 0;
     bool same = false;
+    // FP32 form: points come closer to their leaf's edge than the expanded
+    // squared distance resolves, so PP entries of non-overlapping cells take
+    // exact differences (set by the plan from the trees' min_gap)
+    bool near_exact = false;
     int kernel = 1, p = 8, leaf = 64;
     double theta = 0.7;
     unsigned flags = 0;
@@ -278,7 +284,7 @@ namespace csfmm {
 // (K(x, y) = K(y, x)), not for Biot-Savart.
 inline bool sym_path_possible(const csfmm_plan_s* P) {
     return P->lists.sym.on && (P->flags & CSFMM_FP32_FORM) && P->tt.max_leaf <= kWaveLeaf &&
-           P->lists.sym.n_own > 0;
+           P->lists.sym.n_own > 0 && !P->near_exact;
 }
 inline bool sym_path(const csfmm_plan_s* P, int kernel) {
     return sym_path_possible(P) && kernel != CSFMM_K_BIOT_SAVART;

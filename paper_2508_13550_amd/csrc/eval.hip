@@ -704,6 +704,7 @@ int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** ou
     v.psi_stride = int64_t(T.ncells) * P->KS;
     v.p = P->p; v.K = P->K; v.KS = P->KS; v.nb1 = P->nb1;
     v.nleaves_t = T.nleaves;
+    v.near_exact = P->near_exact ? 1 : 0;
     const SymPP& Y = P->lists.sym;
     v.own_off = Y.own_off; v.own_src = Y.own_src; v.recv_off = Y.recv_off;
     v.recv_slot = Y.recv_slot; v.one_off = Y.one_off; v.one_src = Y.one_src;

@@ -222,6 +222,11 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
     if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
 }
 
+// *a = v
+__global__ void k_set_u32(unsigned* __restrict__ a, unsigned v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a = v;
+}
+
 // *a = *b = *c = 0 (the element past the entries of three kind arrays)
 __global__ void k_zero_i32x3(int32_t* __restrict__ a, int32_t* __restrict__ b,
                              int32_t* __restrict__ c) {
@@ -424,6 +429,16 @@ __global__ void k_leaf_local(const int32_t* __restrict__ leaves, int nleaves,
         u[b + k] = (xi[b + k] - xm) / half;
         v[b + k] = (eta[b + k] - ym) / half;
     }
+}
+
+// Least distance of a point to its leaf's edge in local coordinates,
+// 1 - max(|u|, |v|) >= 0, as float bits (monotone for non-negative floats).
+__global__ void k_min_gap(const double* __restrict__ u, const double* __restrict__ v, int64_t n,
+                          unsigned* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = fmaxf(0.f, float(1.0 - fmax(fabs(u[i]), fabs(v[i]))));
+    atomicMin(out, __float_as_uint(g));
 }
 
 // §4 barycentric Lagrange L_k(x) at the Chebyshev points, exact hit -> delta.
@@ -796,7 +811,17 @@ int build_tree(csfmm_plan_s* P, Tree& T, const double* pts, int64_t n, hipStream
     k_leaf_local<<<nleaves, 128, 0, s>>>(T.leaves, nleaves, T.level, T.ci, T.cj, T.begin, T.count,
                                          xi, eta, T.u, T.v);
     CSFMM_LAUNCH_CHECK();
+    unsigned* gap;
+    RC(S.get(&gap, 1));
+    k_set_u32<<<1, 1, 0, s>>>(gap, 0x3f800000u);  // 1.0f
+    k_min_gap<<<nblk(n), kT, 0, s>>>(T.u, T.v, n, gap);
+    CSFMM_LAUNCH_CHECK();
+    unsigned hgap = 0;
+    CSFMM_HIP_TRY(hipMemcpyAsync(&hgap, gap, sizeof(hgap), hipMemcpyDeviceToHost, s));
     CSFMM_HIP_TRY(hipStreamSynchronize(s));
+    float g = 1.f;
+    std::memcpy(&g, &hgap, sizeof(g));
+    T.min_gap = g;
     return CSFMM_OK;
 }
 
@@ -1012,6 +1037,12 @@ int build_plan(csfmm_plan_s* P, const double* targets, const double* sources, hi
     RC(A.alloc(&P->bm2m, int64_t(4) * P->KS * P->nb1));
     k_build_ops<<<1, 256, 0, s>>>(P->p, P->KS, P->nb1, P->lag1d, P->bm2m);
     CSFMM_LAUNCH_CHECK();
+    // Points in different cells are at least (gap_t + gap_s) half cell widths
+    // apart.  The expanded squared distance |t|^2 + |s|^2 - 2 t.s of the FP32
+    // form errs by a few FP32 ulps of |t|^2 + |s|^2 (up to about six squared half
+    // widths for neighbouring cells); below a separation of 1/8 half width the
+    // closest pairs would lose more than about 1e-4 of their squared distance.
+    P->near_exact = (P->flags & CSFMM_FP32_FORM) && (P->tt.min_gap + P->st->min_gap) < 0.125f;
     RC(build_lists(P, s));
     // the plan's own eval workspace
     RC(workspace_create(P, s, &P->ws0));

@@ -125,13 +125,16 @@ __device__ __forceinline__ float sal_bracket(float v) {
 //              contributes nothing; for entries whose cells overlap the target
 //  FORM_NEAR   cells that do not overlap the target (no check)
 //  FORM_FAR    MAC-separated entries
+//  FORM_EXACT  cells that do not overlap the target, exact differences and the
+//              zero check (the FP32 form of plans whose points come close to
+//              their leaf edges: close pairs in neighbouring leaves)
 // In the FP32 form the scalar kernels take |t-s|^2 = |t|^2 + |s|^2 - 2 t.s for
 // FORM_NEAR and FORM_FAR (4 operations instead of 6; coordinates are recentred
 // at the target cell, so |t|^2 + |s|^2 stays within a small multiple of the
 // squared distance of two points in different cells and the relative error of
 // the result stays near FP32 rounding); FORM_CHECK keeps exact differences so
 // that a coincident point gives exactly 0.
-enum { FORM_CHECK = 0, FORM_NEAR = 1, FORM_FAR = 2 };
+enum { FORM_CHECK = 0, FORM_NEAR = 1, FORM_FAR = 2, FORM_EXACT = 3 };
 
 struct TargetRegs {
     double tx, ty, tz;          // FP64 form
@@ -186,7 +189,8 @@ __device__ __forceinline__ void eval_pair(const TargetRegs& T, Real<F32> sx, Rea
     } else {
         tx = T.tx; ty = T.ty; tz = T.tz;
     }
-    constexpr bool expanded = F32 && FORM != FORM_CHECK && KERN != CSFMM_K_BIOT_SAVART;
+    constexpr bool expanded =
+        F32 && (FORM == FORM_NEAR || FORM == FORM_FAR) && KERN != CSFMM_K_BIOT_SAVART;
     if constexpr (expanded) {
         p[0] = fmaf(w, kernel_value_f32<KERN>(expanded_d2(T, sx, sy, sz, s2)), p[0]);
     } else {
@@ -199,7 +203,7 @@ __device__ __forceinline__ void eval_pair(const TargetRegs& T, Real<F32> sx, Rea
                 lg = dev_log2(r2);
             else
                 lg = log(r2);
-            if constexpr (FORM == FORM_CHECK) lg = r2 > R(0) ? lg : R(0);
+            if constexpr (FORM == FORM_CHECK || FORM == FORM_EXACT) lg = r2 > R(0) ? lg : R(0);
             p[0] = fma(w, lg, p[0]);
         } else if constexpr (KERN == CSFMM_K_BIOT_SAVART) {
             R inv;
@@ -208,17 +212,17 @@ __device__ __forceinline__ void eval_pair(const TargetRegs& T, Real<F32> sx, Rea
             else
                 inv = R(1) / r2;
             R f = w * inv;
-            if constexpr (FORM == FORM_CHECK) f = r2 > R(0) ? f : R(0);
+            if constexpr (FORM == FORM_CHECK || FORM == FORM_EXACT) f = r2 > R(0) ? f : R(0);
             p[0] = fma(dx, f, p[0]);
             p[1] = fma(dy, f, p[1]);
             p[2] = fma(dz, f, p[2]);
         } else if constexpr (KERN == CSFMM_K_BIHARMONIC) {
             R g = dilog_1m(r2);
-            if constexpr (FORM == FORM_CHECK) g = r2 > R(0) ? g : R(0);
+            if constexpr (FORM == FORM_CHECK || FORM == FORM_EXACT) g = r2 > R(0) ? g : R(0);
             p[0] = fma(w, g, p[0]);
         } else if constexpr (KERN == CSFMM_K_SAL) {
             R g = sal_bracket(r2);
-            if constexpr (FORM == FORM_CHECK) g = r2 > R(0) ? g : R(0);
+            if constexpr (FORM == FORM_CHECK || FORM == FORM_EXACT) g = r2 > R(0) ? g : R(0);
             p[0] = fma(w, g, p[0]);
         } else {
             R inv;
@@ -226,7 +230,7 @@ __device__ __forceinline__ void eval_pair(const TargetRegs& T, Real<F32> sx, Rea
                 inv = dev_rsq(r2);
             else
                 inv = rsqrt(r2);
-            if constexpr (FORM == FORM_CHECK) inv = r2 > R(0) ? inv : R(0);
+            if constexpr (FORM == FORM_CHECK || FORM == FORM_EXACT) inv = r2 > R(0) ? inv : R(0);
             p[0] = fma(w, inv, p[0]);
         }
     }
@@ -573,6 +577,8 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
                         for (int v = 0; v < VD; ++v) p[v] = R(0);
                         if (ph == 0)
                             run_group<KERN, F32, FORM_CHECK>(Lb, g * Tj, Tj, TR, p);
+                        else if (ph == 1 && V.near_exact)
+                            run_group<KERN, F32, FORM_EXACT>(Lb, g * Tj, Tj, TR, p);
                         else if (ph == 1)
                             run_group<KERN, F32, FORM_NEAR>(Lb, g * Tj, Tj, TR, p);
                         else
@@ -827,6 +833,8 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
             for (int v = 0; v < VD; ++v) p[v] = R(0);
             if (ph == 0)
                 run_group<KERN, F32, FORM_CHECK>(L, 0, npad, TR, p);
+            else if (ph == 1 && V.near_exact)
+                run_group<KERN, F32, FORM_EXACT>(L, 0, npad, TR, p);
             else if (ph == 1)
                 run_group<KERN, F32, FORM_NEAR>(L, 0, npad, TR, p);
             else

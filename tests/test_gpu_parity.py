@@ -276,6 +276,69 @@ def test_fp32_near_field_matches_oracle(case):
     assert err < 2e-6 * CANCEL[k]
 
 
+def _straddling_points(delta):
+    """Four points at +-delta across the central line of the face around +x
+    (xi = 0 or eta = 0, whichever axis carries it), which is a cell edge at
+    every level: two pairs of points in neighbouring leaves, 2 delta apart."""
+    Q = np.array([[1.0, delta, 0.3], [1.0, -delta, 0.3], [1.0, 0.3, delta], [1.0, 0.3, -delta]])
+    return Q / np.linalg.norm(Q, axis=1, keepdims=True)
+
+
+def test_fp32_close_pairs_across_leaf_edges():
+    """Points 2e-5 apart in neighbouring leaves: the expanded squared distance
+    |t|^2 + |s|^2 - 2 t.s of the FP32 form cannot resolve them (its rounding is
+    ~1e-9 against a squared distance of 4e-10), so the plan detects the small
+    edge gap and those entries take exact differences; the pair's targets then
+    match the oracle to FP32 coordinate resolution."""
+    _announce("grid E=32 + 4 points straddling a leaf edge, 1/r, FP32 near field")
+    G = cubed_sphere_grid(32)[0]
+    P = np.concatenate([G, _straddling_points(1e-5)])
+    w = np.random.default_rng(6).standard_normal(P.shape[0])
+    o = F.FMM(P, None, 3, 6, 0.7, 64)
+    ref, stg = o.evaluate(w, stages=True)
+    pl = cs.Plan(tdev(P), None, kernel=3, p=6, theta=0.7, leaf_size=64, fp32=True)
+    st = pl.stats()
+    out, wbar, psi, near = pl.eval_stages(tdev(w))
+    near, out = host(near)[:, 0], host(out)
+    pl.close()
+    assert st["near_exact"] == 1
+    assert np.all(np.isfinite(out))
+    on = stg["near"][:, 0]
+    q = np.arange(G.shape[0], P.shape[0])
+    err = np.abs(near[q] - on[q]) / np.abs(on[q])
+    print("straddling targets rel err", err, flush=True)
+    assert np.all(err < 1e-2)
+    n = G.shape[0]
+    assert rel_l2(near[:n], on[:n]) < 2e-6
+    # the grid alone keeps its points 1/8 of a half leaf width from the edges
+    pg = cs.Plan(tdev(G), None, kernel=3, p=6, theta=0.7, leaf_size=64, fp32=True)
+    assert pg.stats()["near_exact"] == 0
+    pg.close()
+
+
+@pytest.mark.parametrize("kernel", [1, 3])
+def test_fp32_random_points(kernel):
+    """Uniform random points: close pairs in the same or neighbouring leaves
+    limit the FP32 form to its coordinate resolution (a pair at distance d
+    carries a relative error of about ulp(leaf size) / d in its kernel value),
+    here ~1e-5 of the 1/r near field; the result stays finite."""
+    _announce("random points n=20000 leaf 40 kernel %d, FP32 near field" % kernel)
+    P = random_sphere_points(20000, 4)
+    w = np.random.default_rng(4).standard_normal(P.shape[0])
+    o = F.FMM(P, None, kernel, 6, 0.7, 40)
+    ref, stg = o.evaluate(w, stages=True)
+    pl = cs.Plan(tdev(P), None, kernel=kernel, p=6, theta=0.7, leaf_size=40, fp32=True)
+    st = pl.stats()
+    out, wbar, psi, near = pl.eval_stages(tdev(w))
+    near, out = host(near), host(out)
+    pl.close()
+    assert st["near_exact"] == 1
+    on = stg["near"]
+    print("rel_l2 %.3e max %.3e" % (rel_l2(near, on), rel_max(near, on)), flush=True)
+    assert np.all(np.isfinite(out))
+    assert rel_l2(near, on) < 3e-5 and rel_max(near, on) < 1e-4
+
+
 def test_deterministic(case):
     name, T, S, k, p, th, leaf, ofmm, plan = case
     src = T if S is None else S
