@@ -83,9 +83,7 @@ typedef struct csfmm_stats {
     int64_t n_pp, n_pc, n_cp, n_cc;        /* (target cell, source cell) pairs */
     int64_t evals_pp, evals_pc, evals_cp, evals_cc; /* kernel evaluations per eval */
     int64_t device_bytes;                  /* device memory the plan holds */
-    int64_t max_leaf_t;                    /* most points in a target leaf; leaves of at
-                                              most 64 take the one-wave-per-leaf
-                                              near-field path */
+    int64_t max_leaf_t;                    /* most points in a target leaf */
     int64_t pp_sym_pairs, pp_one_way;      /* same-set plans: PP entries of distinct
                                               leaves that hold both ways, counted once
                                               per pair, and those that hold one way
@@ -96,6 +94,10 @@ typedef struct csfmm_stats {
                                               edges, so the PP entries of non-overlapping
                                               leaves take exact differences (and no
                                               symmetric pairs) */
+    int64_t near_wave;                     /* 1: the near field takes one wave per target
+                                              leaf (leaves of at most 64 points, at least
+                                              8 leaves per compute unit); 0: one block of
+                                              four waves per leaf */
 } csfmm_stats;
 
 /*

@@ -55,7 +55,7 @@ class Stats(ctypes.Structure):
         ("evals_cp", ctypes.c_int64), ("evals_cc", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64), ("max_leaf_t", ctypes.c_int64),
         ("pp_sym_pairs", ctypes.c_int64), ("pp_one_way", ctypes.c_int64),
-        ("near_exact", ctypes.c_int64),
+        ("near_exact", ctypes.c_int64), ("near_wave", ctypes.c_int64),
     ]
 
     def as_dict(self):

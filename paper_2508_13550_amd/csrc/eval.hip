@@ -507,12 +507,12 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         g.n = int(idx.size());
         g.mode = mode;
         int64_t tn = 0, tf = 0;
-        // a PP launch whose requests all have leaves of <= kWaveLeaf points runs
+        // a PP launch whose requests all take the one-wave-per-leaf path runs
         // k_tile_wave; k_tile takes the rest (far-field blocks on its block path,
         // near-field blocks of such requests on the one-wave-per-leaf path)
         g.wave_kernel = mode == kTileNearPP ? 1 : 0;
         for (int q = 0; q < g.n; ++q)
-            if (reqs[idx[q]].plan->tt.max_leaf > kWaveLeaf) g.wave_kernel = 0;
+            if (!leaf_wave_path(reqs[idx[q]].plan->tt)) g.wave_kernel = 0;
         for (int q = 0; q < g.n; ++q) {
             const int r = idx[q];
             g.v[q] = b.v[r];
@@ -524,7 +524,7 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
             // near-field blocks: four target leaves each (one a wave) on the
             // one-wave-per-leaf path, else one
             const Tree& tt = reqs[r].plan->tt;
-            g.leaf_wave[q] = tt.max_leaf <= kWaveLeaf ? 1 : 0;
+            g.leaf_wave[q] = leaf_wave_path(tt) ? 1 : 0;
             // the symmetric PP path needs k_tile_wave (one wave per leaf, PP only)
             g.sym[q] = (g.wave_kernel && sym_path(reqs[r].plan, reqs[r].kernel)) ? 1 : 0;
             tn += g.leaf_wave[q] ? (int64_t(tt.nleaves) + 3) / 4 : tt.nleaves;

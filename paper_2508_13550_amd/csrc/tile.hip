@@ -29,6 +29,7 @@
 //             with the 1/2 scaling g/2 = sqrt(v), so the bracket is
 //             ((1-b0)/2) (1/sqrt(v) + q ln(sqrt(v) + v)), q = -2(a1-b1)/(1-b0).
 // The self term (squared distance exactly 0) contributes nothing.
+#include <atomic>
 #include <type_traits>
 
 #include "common.h"
@@ -1199,6 +1200,25 @@ __global__ __launch_bounds__(256) void k_treecode(TcArgs a) {
         for (int v = 0; v < VD; ++v) a.out[dst * VD + v] = o[v];
     }
 }
+
+}  // namespace
+
+// Compute units of the current device (queried once per device).
+int device_cus() {
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int n = cus[dev].load(std::memory_order_relaxed);
+    if (n <= 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n <= 0)
+            n = 256;
+        cus[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
+}
+
+namespace {
 
 template <int KERN, bool F32>
 int launch_tile_t(const Batch& b, hipStream_t s) {

@@ -136,9 +136,11 @@ CASES = {
     "tiny_p1_leaf1": lambda: (cubed_sphere_grid(2)[0], None, 1, 1, 0.5, 1),
     "biharmonic_E32": lambda: (cubed_sphere_grid(32)[0], None, 4, 8, 0.7, 64),
     "sal_distinct": lambda: (random_sphere_points(2000, 43), cubed_sphere_grid(16)[0], 5, 6, 0.6, 40),
-    # leaves of more than 64 points: the near field's block path (the other
-    # cases take the one-wave-per-leaf path)
+    # leaves of more than 64 points: the near field's block path
     "random_leaf100": lambda: (random_sphere_points(6000, 47), None, 1, 6, 0.7, 100),
+    # 6,144 leaves of 9 points: the one-wave-per-leaf path (and, in the FP32
+    # form, the symmetric PP pairs); the smaller cases keep the block path
+    "grid_E96_leaf16": lambda: (cubed_sphere_grid(96)[0], None, 1, 4, 0.7, 16),
 }
 
 
@@ -200,16 +202,20 @@ def test_lists(case):
 
 
 def test_cases_cover_both_near_field_paths():
-    """Leaves of at most 64 points take the one-wave-per-leaf near field, larger
-    ones the block path: the parity cases hold both."""
-    leaf_max = {}
-    for name in ("config1", "random_leaf100"):
+    """Many leaves of at most 64 points take the one-wave-per-leaf near field
+    (and the symmetric PP pairs in the FP32 form), the others the block path:
+    the parity cases hold both."""
+    got = {}
+    for name in ("config1", "random_leaf100", "grid_E96_leaf16"):
         T, S, k, p, th, leaf = CASES[name]()
         pl = cs.Plan(tdev(T), None if S is None else tdev(S), kernel=k, p=p, theta=th,
-                     leaf_size=leaf)
-        leaf_max[name] = pl.stats()["max_leaf_t"]
+                     leaf_size=leaf, fp32=True)
+        got[name] = pl.stats()
         pl.close()
-    assert leaf_max["config1"] <= 64 < leaf_max["random_leaf100"]
+    assert got["config1"]["near_wave"] == 0 and got["random_leaf100"]["near_wave"] == 0
+    assert got["random_leaf100"]["max_leaf_t"] > 64
+    assert got["grid_E96_leaf16"]["near_wave"] == 1 and got["grid_E96_leaf16"]["near_exact"] == 0
+    assert got["grid_E96_leaf16"]["pp_sym_pairs"] > 0
 
 
 def test_stages_and_result(case):
