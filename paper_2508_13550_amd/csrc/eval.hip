@@ -525,8 +525,8 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
             // one-wave-per-leaf path, else one
             const Tree& tt = reqs[r].plan->tt;
             g.leaf_wave[q] = leaf_wave_path(tt) ? 1 : 0;
-            // the symmetric PP path needs k_tile_wave (one wave per leaf, PP only)
-            g.sym[q] = (g.wave_kernel && sym_path(reqs[r].plan, reqs[r].kernel)) ? 1 : 0;
+            // the symmetric PP path (a property of the request alone)
+            g.sym[q] = (mode == kTileNearPP && sym_path(reqs[r].plan, reqs[r].kernel)) ? 1 : 0;
             tn += g.leaf_wave[q] ? (int64_t(tt.nleaves) + 3) / 4 : tt.nleaves;
             tf += mode == kTilePCFar ? reqs[r].plan->lists.n_far_targets : 0;
         }

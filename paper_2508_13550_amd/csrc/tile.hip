@@ -881,12 +881,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 
         const ReqView V = load_view(b.v[req]);
         if (b.leaf_wave[req]) {
             // four leaves per block, one per wave, each wave with its own stage
-            // (the symmetric PP path runs in k_tile_wave only)
-            static_assert(4 * sizeof(WaveStage<F32>) <= sizeof(sm), "wave stages");
+            // (the same per-wave work as in k_tile_wave, so a request's result does
+            // not depend on the other requests of its batch)
+            constexpr int kWaveBytes = wave_lds_bytes<F32>();
+            static_assert(4 * kWaveBytes <= int(sizeof(sm)), "wave stages");
             const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
             const int leaf = 4 * local + wave;
-            char* st = reinterpret_cast<char*>(&sm) + wave * sizeof(WaveStage<F32>);
-            if (leaf < V.nleaves_t) tile_leaf_wave<KERN, F32>(V, b.mode, leaf, false, st);
+            char* st = reinterpret_cast<char*>(&sm) + wave * kWaveBytes;
+            if (leaf < V.nleaves_t)
+                tile_leaf_wave<KERN, F32>(V, b.mode, leaf, b.sym[req] != 0, st);
         } else {
             tile_body<KERN, F32, false>(V, b.mode, local, sm);
         }

@@ -36,6 +36,33 @@ def weights(E, coef):
     return torch.tensor((Y @ coef) * A, dtype=torch.float64, device="cuda")
 
 
+def test_packed_mixed_near_field_paths_equal_alone_bitwise():
+    """A request on the one-wave-per-leaf near field with symmetric PP pairs
+    (6,144 leaves of 9 points) packed with requests on the block path (few
+    leaves) and with Biot-Savart (no symmetric pairs): each result is bitwise
+    the request evaluated alone, whatever else shares its launches."""
+    say("eval_many: wave/symmetric path packed with block-path requests")
+    big = cs.Plan(grid(96)[3], None, kernel=1, p=4, theta=0.7, leaf_size=16, fp32=True)
+    small = cs.Plan(grid(16)[3], None, kernel=1, p=4, theta=0.7, leaf_size=16, fp32=True)
+    assert big.stats()["near_wave"] == 1 and small.stats()["near_wave"] == 0
+    rng = np.random.default_rng(21)
+    reqs = [(big, 1), (small, 1), (big, 3), (small, 2), (big, 2)]
+    batch, alone = [], []
+    for pl, k in reqs:
+        E = 96 if pl is big else 16
+        w = weights(E, rng.standard_normal(81))
+        alone.append(pl.eval(w, kernel=k).cpu().numpy())
+        batch.append((pl, cs.Workspace(pl), k, w))
+    outs = cs.eval_many(batch)
+    torch.cuda.synchronize()
+    for a, o in zip(alone, outs):
+        assert np.array_equal(a, o.cpu().numpy())
+    for _, ws, _, _ in batch:
+        ws.close()
+    big.close()
+    small.close()
+
+
 def test_packed_equals_alone_bitwise():
     say("eval_many vs alone")
     mix = request_mix(10, seed_mix=11, e_choices=(8, 16, 32))
