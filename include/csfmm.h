@@ -84,7 +84,7 @@ typedef struct csfmm_stats {
     int64_t evals_pp, evals_pc, evals_cp, evals_cc; /* kernel evaluations per eval */
     int64_t device_bytes;                  /* device memory the plan holds */
     int64_t max_leaf_t;                    /* most points in a target leaf */
-    int64_t pp_sym_pairs, pp_one_way;      /* same-set plans: PP entries of distinct
+    int64_t pp_sym_pairs, pp_one_way;      /* same-set FP32-form plans: PP entries of distinct
                                               leaves that hold both ways, counted once
                                               per pair, and those that hold one way
                                               (the FP32 form evaluates a pair once for

@@ -955,8 +955,9 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
     for (int k = 0; k < 4; ++k) P->lists.evals[k] = int64_t(hev[k]);
     T.max_leaf = int32_t(hev[4]);
 
-    // symmetric split of the PP entries (same-set plans)
-    if (P->same) {
+    // symmetric split of the PP entries (same-set plans in the FP32 form, the
+    // form whose evals use it)
+    if (P->same && (P->flags & CSFMM_FP32_FORM)) {
         SymPP& Y = P->lists.sym;
         const int nc = T.ncells;
         const int64_t ne = P->lists.cnt[kPP];

@@ -189,16 +189,21 @@ def test_lists(case):
     assert (st["evals_pp"], st["evals_pc"], st["evals_cp"], st["evals_cc"]) == \
         (want["PP"], want["PC"], want["CP"], want["CC"])
     assert st["max_leaf_t"] == max(C.count for C in ofmm.ttree.cells if C.is_leaf)
-    # same-set plans: PP entries of distinct leaves split into pairs that hold
-    # both ways (once per pair) and one-way entries
+    # same-set plans in the FP32 form: PP entries of distinct leaves split into
+    # pairs that hold both ways (once per pair) and one-way entries
+    assert (st["pp_sym_pairs"], st["pp_one_way"]) == (0, 0)  # FP64 form: not built
     pp = set((Tc.id, Sc.id) for Tc, Sc in ofmm.lists["PP"])
+    p32 = cs.Plan(tdev(T), None if S is None else tdev(S), kernel=k, p=p, theta=th,
+                  leaf_size=leaf, fp32=True)
+    s32 = p32.stats()
+    p32.close()
     if S is None:
         both = sum(1 for a, b in pp if a != b and (b, a) in pp)
         one = sum(1 for a, b in pp if a != b and (b, a) not in pp)
         assert both % 2 == 0
-        assert (st["pp_sym_pairs"], st["pp_one_way"]) == (both // 2, one)
+        assert (s32["pp_sym_pairs"], s32["pp_one_way"]) == (both // 2, one)
     else:
-        assert (st["pp_sym_pairs"], st["pp_one_way"]) == (0, 0)
+        assert (s32["pp_sym_pairs"], s32["pp_one_way"]) == (0, 0)
 
 
 def test_cases_cover_both_near_field_paths():
