@@ -14,9 +14,14 @@
 //                (eq. CP_CC_accumulated).
 // The source list is flattened and staged through LDS in chunks, recentred
 // at the target cell's centre in FP64 (and, in the FP32 form, converted to
-// FP32 after recentring).  Thread (t, g) of the 256 owns target t and the
-// sources g, g+G, ... of each chunk; the G partial sums of a target are
-// combined in FP64 in a fixed order, so results are deterministic.
+// FP32 after recentring).  Block path (tile_body): thread (t, g) of the 256
+// owns target t and the sources g, g+G, ... of each chunk; the G partial sums
+// of a target are combined in FP64 in a fixed order.  One-wave-per-leaf path
+// (tile_leaf_wave, many target leaves of at most 64 points): lane t owns
+// target t and every source, the wave stages its own sources.  Same-set FP32
+// plans evaluate each pair of leaves whose PP entry holds both ways once
+// (sym_pairs, k_sym_merge).  Every order is fixed, so results are
+// deterministic.
 //
 // Kernels (x, y unit vectors, 1 - x.y = |x-y|^2/2):
 //   Poisson   -(1/4pi) ln(1 - x.y): coordinates scaled by 1/sqrt2 so that the
@@ -391,10 +396,6 @@ __device__ __forceinline__ void run_group(const StageT<F32, CAP>& L, int base, i
     }
 }
 
-// Point o of a list entry (stage_source: recentred and scaled, into stage slot
-// q).  code >= 0: the entry is the particles of a leaf starting at sorted
-// position code; code < 0: the KS-strided proxies of cell -(code + 1) with
-// their weights.
 // Element i of a global array read through the global address space (a load
 // with a wave-uniform address then gives a wave-uniform value).
 template <class T>
@@ -421,9 +422,12 @@ __device__ __forceinline__ T gload_near(const T* base, unsigned i) {
         (const __attribute__((address_space(1))) char*)base + byte);
 }
 
+// Point o of a list entry (stage_source: recentred and scaled, into stage slot
+// q).  code >= 0: the entry is the particles of a leaf starting at sorted
+// position code; code < 0: the KS-strided proxies of cell -(code + 1) with
+// their weights.  o is below the entry's size (a leaf's points or K proxies).
 __device__ __forceinline__ void load_source(const TileArgs& a, int code, int o, double& yx,
                                             double& yy, double& yz, double& w) {
-    // o is below the entry's size (a leaf's points or KS proxies)
     if (code >= 0) {
         yx = gload_near(a.sx + code, o);
         yy = gload_near(a.sy + code, o);
@@ -625,6 +629,7 @@ constexpr int wave_lds_bytes() {
                                                            : int(sizeof(WaveStage<F32>));
 }
 
+// x of another lane of the same quad of four lanes (DPP quad_perm CTRL)
 template <int CTRL>
 __device__ __forceinline__ float dpp_quad(float x) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
