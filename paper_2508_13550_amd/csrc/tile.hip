@@ -643,9 +643,9 @@ __device__ __forceinline__ void wave_sync();
 // kernel value g_ij at every lane's target i of A serves both directions: the
 // row sum p_i += w_j g_ij and the column sum col_j = sum_i wA_i g_ij.  The
 // column terms of 16 sources go through the LDS tile (column-major): lane i
-// writes its term of each column, then lane l sums rows 16 (l % 4) .. + 15 of
-// column l / 4 and a quad reduction joins the four partial sums; col_j goes
-// to colout[j] for j < nB.
+// writes its term of each column as it is computed, then lane l sums rows
+// 16 (l % 4) .. + 15 of column l / 4 and a quad reduction joins the four
+// partial sums; col_j goes to colout[j] for j < nB.
 template <int KERN>
 __device__ __forceinline__ void run_sym(SymLds& S, int base, int nj, int nB,
                                         const TargetRegs& T, float wA, float* p,
@@ -653,22 +653,32 @@ __device__ __forceinline__ void run_sym(SymLds& S, int base, int nj, int nB,
     const int lane = threadIdx.x & 63;
     nj = __builtin_amdgcn_readfirstlane(nj);
     for (int j0 = 0; j0 < nj; j0 += kSymCols) {
-        float c[kSymCols];
+        // the next group of four sources is read while the current one is
+        // evaluated
+        const auto* Qp = &S.st.b[(base + j0) >> 2];
+        float4 cur[5], nxt[5];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cur[k] = Qp[0].p[k];
+        cur[4] = Qp[0].w;
 #pragma unroll
         for (int q = 0; q < kSymCols / 4; ++q) {
-            const auto& Q = S.st.b[((base + j0) >> 2) + q];
-            const float4 w4 = Q.w;
-            const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
+            if (q + 1 < kSymCols / 4) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) nxt[k] = Qp[q + 1].p[k];
+                nxt[4] = Qp[q + 1].w;
+            }
+            const float ws[4] = {cur[4].x, cur[4].y, cur[4].z, cur[4].w};
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const float4 sp = Q.p[u];
+                const float4 sp = cur[u];
                 const float g = kernel_value_f32<KERN>(expanded_d2(T, sp.x, sp.y, sp.z, sp.w));
                 p[0] = fmaf(ws[u], g, p[0]);
-                c[4 * q + u] = wA * g;
+                // column term, stored at once (no registers held for the tile)
+                S.m[kSymCol * (4 * q + u) + lane] = wA * g;
             }
-        }
 #pragma unroll
-        for (int u = 0; u < kSymCols; ++u) S.m[kSymCol * u + lane] = c[u];
+            for (int k = 0; k < 5; ++k) cur[k] = nxt[k];
+        }
         wave_sync();
         const int col = lane >> 2, r0 = lane & 3;
         const float4* cp = reinterpret_cast<const float4*>(&S.m[kSymCol * col + 16 * r0]);
