@@ -149,7 +149,7 @@ struct ReqView {
     double *ws, *wbar, *psi, *phinear, *phipc;
     int64_t nt, ns, psi_stride;
     int32_t p, K, KS, nb1;
-    int32_t nleaves_t;
+    int32_t nleaves_t, nleaves_s;
     int32_t near_exact;  // near field of non-overlapping cells in exact differences (FP32 form)
     // symmetric PP split (SymPP) and its column-sum slots [n_own][kWaveLeaf]
     const int32_t *own_off, *own_src, *recv_off, *recv_slot, *one_off, *one_src;

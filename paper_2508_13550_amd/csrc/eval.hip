@@ -31,6 +31,14 @@ __device__ __forceinline__ void locate(const Batch& b, int& r, int& local) {
     batch_locate(b, xcd_logical_block(blockIdx.x, gridDim.x), r, local);
 }
 
+// Orders a wave's LDS stores before its later loads (and the reverse) across
+// its lanes; for LDS that one wave owns.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // e1: ws[k] = w[perm[k]]   (256 sorted sources per block)
 __global__ __launch_bounds__(256) void k_gather_w(Batch b) {
     int r, local;
@@ -87,31 +95,43 @@ __device__ __forceinline__ void bary_regs(const double* s, const double* beta, d
 }
 
 // e2 P2M: wbar_k(leaf) = sum_j L_k1(u_j) L_k2(v_j) w_j (eq. PC, §6), one wave
-// per source leaf.  Each lane builds the rows of one point in registers and
-// stores L1 and w L2 in LDS; then, as a matrix product over the points,
+// per source leaf (p2m_waves per block: blocks of one wave made the launch
+// wait on the rate at which workgroups are dispatched).  Each lane builds the
+// rows of one point in registers and stores L1 and w L2 in its wave's LDS;
+// then, as a matrix product over the points,
 //   Wbar[k1][k2] = sum_j L1[j][k1] (w_j L2[j][k2]),
 // runs on FP64 MFMA 16x16x4 (16-wide proxy-index tiles, 4 points per step).
 template <int P1>
-__global__ __launch_bounds__(64) void k_p2m(Batch b) {
+constexpr int p2m_waves() {
+    return P1 <= 12 ? 4 : 2;  // the waves' LDS within 64 KB
+}
+template <int P1>
+__global__ __launch_bounds__(64 * p2m_waves<P1>()) void k_p2m(Batch b) {
     constexpr int NT = (P1 + 15) / 16;
+    constexpr int PW = p2m_waves<P1>();
     __shared__ double s[P1], beta[P1];
-    __shared__ double Lu[64][P1];
-    __shared__ double Lw[64][P1];
-    const int lane = threadIdx.x;
+    __shared__ double Luw[PW][64][P1];
+    __shared__ double Lww[PW][64][P1];
+    const int lane = threadIdx.x & 63;
     int r, local;
     locate(b, r, local);
     const ReqView& V = *b.v[r];
-    const int c = V.s_leaves[local];
+    cheb_setup(P1 - 1, s, beta);
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+    const int leaf = PW * local + wave;
+    if (leaf >= V.nleaves_s) return;  // the whole wave leaves
+    double(&Lu)[64][P1] = Luw[wave];
+    double(&Lw)[64][P1] = Lww[wave];
+    const int c = V.s_leaves[leaf];
     const int bgn = V.s_begin[c], m = V.s_count[c];
     const int KS = V.KS;
-    cheb_setup(P1 - 1, s, beta);
     double4_t acc[NT][NT];
 #pragma unroll
     for (int i = 0; i < NT; ++i)
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
     const int kq = lane >> 4, l16 = lane & 15;
-    __syncthreads();
     for (int j0 = 0; j0 < m; j0 += 64) {
         const int j = j0 + lane;
         double L1[P1], L2[P1];
@@ -129,7 +149,7 @@ __global__ __launch_bounds__(64) void k_p2m(Batch b) {
             Lu[lane][k] = L1[k];
             Lw[lane][k] = wj * L2[k];
         }
-        __syncthreads();
+        wave_lds_sync();
         const int steps = min(64, m - j0);
 #pragma unroll
         for (int ti = 0; ti < NT; ++ti)
@@ -142,7 +162,7 @@ __global__ __launch_bounds__(64) void k_p2m(Batch b) {
                     acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ti][tj], 0, 0, 0);
                 }
             }
-        __syncthreads();
+        wave_lds_sync();
     }
     double* wb = V.wbar + int64_t(c) * KS;
 #pragma unroll
@@ -219,39 +239,51 @@ __global__ __launch_bounds__(256) void k_m2m(Batch b) {
 
 // e6-e8: L2L (eq. downward_2) down the leaf's ancestors, L2P (eq.
 // downward_1) at the leaf, near field (PP, PC) and scatter to the caller's
-// order; one target leaf per block, one point per thread.
+// order; one target leaf per wave (four per block: blocks of one wave made the
+// launch wait on the rate at which workgroups are dispatched), one point per
+// lane.
 // The parent-to-child operator of eq. downward_2 is the Kronecker product of
 // two 1-D factors A_bi (n1, m1) and A_bj (n2, m2), child q = 2 bi + bj, so
 // each level is two 1-D passes over the (p+1) x (p+1) proxy array:
 //   t[n1][m2] = sum_m1 A_bi[n1][m1] psi[m1][m2],
 //   psi'[n1][n2] = own[n1][n2] + sum_m2 A_bj[n2][m2] t[n1][m2],
-// starting from the root's own proxy potential.  The block walks its leaf's
+// starting from the root's own proxy potential.  The wave walks its leaf's
 // path from the root (a table built with the plan; the upper levels are
 // recomputed per leaf instead of one launch per level) and loads each level's
 // own proxy potential one level ahead.  The accumulated proxy potential of the
-// leaf is stored back into psi (other blocks never read a leaf's psi).
+// leaf is stored back into psi (no other wave reads a leaf's psi).
+// The occupancy hint holds the scalar kernels of degree p <= 6 at 80 VGPRs
+// (6 waves per SIMD, no spills): 6,144 leaves then fit the device at once.
 template <int VD, int P1>
-__global__ __launch_bounds__(64) void k_l2p(Batch b) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VD == 1 && P1 <= 7 ? 6 : 1))) void k_l2p(Batch b) {
     constexpr int K = P1 * P1;
-    constexpr int kRegs = (VD * K + 63) / 64;  // elements per thread in the 1-D passes
+    constexpr int kRegs = (VD * K + 63) / 64;  // elements per lane in the 1-D passes
     __shared__ double s[P1], beta[P1];
     __shared__ double A1[2][P1][P1];
-    __shared__ double ps[VD][K], tb[VD][K];
-    __shared__ int anc[kAncStride];
+    __shared__ double psw[4][VD][K], tbw[4][VD][K];
+    __shared__ int ancw[4][kAncStride];
     int r, local;
     locate(b, r, local);
     const ReqView& V = *b.v[r];
     double* out = b.out[r];
-    const int c = V.t_leaves[local];
-    const int bgn = V.t_begin[c], m = V.t_count[c];
-    if (m == 0) return;  // the whole block leaves
-    const int KS = V.KS;
-    const int tid = threadIdx.x;
+    // nodes, weights and 1-D factors, shared by the block's waves (one request)
     cheb_setup(P1 - 1, s, beta);
-    for (int k = tid; k < 2 * K; k += blockDim.x) (&A1[0][0][0])[k] = V.lag1d[k];
-    const int32_t* path = V.t_leaf_anc + int64_t(local) * kAncStride;
-    for (int k = tid; k < kAncStride; k += blockDim.x) anc[k] = path[k];
+    for (int k = threadIdx.x; k < 2 * K; k += blockDim.x) (&A1[0][0][0])[k] = V.lag1d[k];
     __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+    const int leaf = 4 * local + wave;
+    if (leaf >= V.nleaves_t) return;  // the whole wave leaves
+    const int c = V.t_leaves[leaf];
+    const int bgn = V.t_begin[c], m = V.t_count[c];
+    if (m == 0) return;
+    double(&ps)[VD][K] = psw[wave];
+    double(&tb)[VD][K] = tbw[wave];
+    int* anc = ancw[wave];
+    const int KS = V.KS;
+    const int tid = threadIdx.x & 63;
+    const int32_t* path = V.t_leaf_anc + int64_t(leaf) * kAncStride;
+    for (int k = tid; k < kAncStride; k += 64) anc[k] = path[k];
+    wave_lds_sync();
     const int na = anc[0];  // anc[1] is the root, anc[na] the leaf
     // own proxy potential of a cell, this thread's elements (k = tid + 64 i)
     auto load_own = [&](int cell, double (&dst)[kRegs]) {
@@ -269,7 +301,7 @@ __global__ __launch_bounds__(64) void k_l2p(Batch b) {
         if (k < VD * K) ps[k / K][k % K] = cur[i];
     }
     if (na >= 2) load_own(anc[2], nxt);
-    __syncthreads();
+    wave_lds_sync();
     for (int l = 2; l <= na; ++l) {
         const int ch = anc[l], par = anc[l - 1];
         const int q = ch - V.t_child0[par];
@@ -288,7 +320,7 @@ __global__ __launch_bounds__(64) void k_l2p(Batch b) {
                 tb[d][e] = t;
             }
         }
-        __syncthreads();
+        wave_lds_sync();
 #pragma unroll
         for (int i = 0; i < kRegs; ++i) {
             const int k = tid + 64 * i;
@@ -300,12 +332,12 @@ __global__ __launch_bounds__(64) void k_l2p(Batch b) {
                 ps[d][e] = t;
             }
         }
-        __syncthreads();
+        wave_lds_sync();
     }
-    for (int k = tid; k < K; k += blockDim.x)
+    for (int k = tid; k < K; k += 64)
 #pragma unroll
         for (int d = 0; d < VD; ++d) V.psi[d * V.psi_stride + int64_t(c) * KS + k] = ps[d][k];
-    for (int j0 = 0; j0 < m; j0 += blockDim.x) {
+    for (int j0 = 0; j0 < m; j0 += 64) {
         const int jj = j0 + tid;
         if (jj >= m) continue;
         const int j = bgn + jj;
@@ -425,9 +457,11 @@ int launch_p2m(Batch& b, const EvalReq* reqs, int n, hipStream_t s) {
         if (!any) continue;
         switch (P1) {
 #define X(Q)                                                                                   \
-    case Q:                                                                                    \
-        RCX(launch_batched(b, blk, [&](unsigned g) { k_p2m<Q><<<g, 64, 0, s>>>(b); }));    \
-        break;
+    case Q: {                                                                                  \
+        constexpr int PW = p2m_waves<Q>();                                                     \
+        for (int r = 0; r < n; ++r) blk[r] = (blk[r] + PW - 1) / PW;                           \
+        RCX(launch_batched(b, blk, [&](unsigned g) { k_p2m<Q><<<g, 64 * PW, 0, s>>>(b); }));   \
+    } break;
             CSFMM_P1_CASES(X)
 #undef X
             default: break;
@@ -599,7 +633,9 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         for (int P1 = 2; P1 <= kMaxP1; ++P1) {
             bool any = false;
             for (int r = 0; r < n; ++r) {
-                blk[r] = (b.vd[r] == vdl && reqs[r].plan->p + 1 == P1) ? reqs[r].plan->tt.nleaves : 0;
+                blk[r] = (b.vd[r] == vdl && reqs[r].plan->p + 1 == P1)
+                             ? (int64_t(reqs[r].plan->tt.nleaves) + 3) / 4
+                             : 0;
                 any = any || blk[r] > 0;
             }
             if (!any) continue;
@@ -607,9 +643,9 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
 #define X(Q)                                                                                       \
     case Q:                                                                                        \
         if (vdl == 1)                                                                              \
-            RCX(launch_batched(b, blk, [&](unsigned g) { k_l2p<1, Q><<<g, 64, 0, s>>>(b); }));  \
+            RCX(launch_batched(b, blk, [&](unsigned g) { k_l2p<1, Q><<<g, 256, 0, s>>>(b); })); \
         else                                                                                       \
-            RCX(launch_batched(b, blk, [&](unsigned g) { k_l2p<3, Q><<<g, 64, 0, s>>>(b); }));  \
+            RCX(launch_batched(b, blk, [&](unsigned g) { k_l2p<3, Q><<<g, 256, 0, s>>>(b); })); \
         break;
                 CSFMM_P1_CASES(X)
 #undef X
@@ -704,6 +740,7 @@ int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** ou
     v.psi_stride = int64_t(T.ncells) * P->KS;
     v.p = P->p; v.K = P->K; v.KS = P->KS; v.nb1 = P->nb1;
     v.nleaves_t = T.nleaves;
+    v.nleaves_s = S.nleaves;
     v.near_exact = P->near_exact ? 1 : 0;
     const SymPP& Y = P->lists.sym;
     v.own_off = Y.own_off; v.own_src = Y.own_src; v.recv_off = Y.recv_off;
