@@ -141,6 +141,10 @@ CASES = {
     # 6,144 leaves of 9 points: the one-wave-per-leaf path (and, in the FP32
     # form, the symmetric PP pairs); the smaller cases keep the block path
     "grid_E96_leaf16": lambda: (cubed_sphere_grid(96)[0], None, 1, 4, 0.7, 16),
+    # high degrees: P2M with two leaves per block (p >= 12), L2P of three
+    # components at p = 12 (LDS near its limit); PC (p = 14) and CC (p = 12) present
+    "high_p14": lambda: (cubed_sphere_grid(32)[0], None, 1, 14, 0.5, 64),
+    "bs_p12": lambda: (cubed_sphere_grid(32)[0], None, 2, 12, 0.6, 64),
 }
 
 
