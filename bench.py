@@ -643,7 +643,7 @@ def serve_bench(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only (--gpus 1); this build has no multi-GPU path",
+        print("bench.py measures one GPU only (--gpus 1): the library runs on one GPU and has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
