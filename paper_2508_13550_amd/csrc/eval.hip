@@ -595,7 +595,7 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
     // is heavy, P2M and the deepest (largest) M2M level first run without PP
     // waves beside them and PP starts after them (measured on the Poisson
     // workload N = 393,216 in the FP32 form: p = 6 (ratio 0.28) early fork
-    // 0.269 vs 0.274 ms; p = 8 (0.61) and p = 10 (1.19) the late fork).
+    // 0.257 vs 0.262 ms; p = 8 (0.61) and p = 10 (1.19) the late fork).
     constexpr double kLateFork = 0.45;
     int64_t ev_pp = 0, ev_far = 0;
     for (int r = 0; r < n; ++r) {
