@@ -354,6 +354,31 @@ def test_fp32_random_points(kernel):
     assert rel_l2(near, on) < 3e-5 and rel_max(near, on) < 1e-4
 
 
+@pytest.mark.parametrize("kernel", [1, 3])
+def test_fp32_random_points_wave_path(kernel):
+    """Many small leaves of uniform random points: the one-wave-per-leaf near
+    field in exact differences (close pairs across leaf edges; the symmetric
+    pairs are then not used) against the oracle's near field, at the bound of
+    the block-path case above; repeatable bitwise."""
+    _announce("random points n=50000 leaf 32 kernel %d, FP32 wave path" % kernel)
+    P = random_sphere_points(50000, 4)
+    w = np.random.default_rng(4).standard_normal(P.shape[0])
+    o = F.FMM(P, None, kernel, 6, 0.7, 32)
+    ref, stg = o.evaluate(w, stages=True)
+    pl = cs.Plan(tdev(P), None, kernel=kernel, p=6, theta=0.7, leaf_size=32, fp32=True)
+    st = pl.stats()
+    out, wbar, psi, near = pl.eval_stages(tdev(w))
+    near2 = host(pl.eval_stages(tdev(w))[3])
+    near, out = host(near), host(out)
+    pl.close()
+    assert st["near_exact"] == 1 and st["near_wave"] == 1
+    on = stg["near"]
+    print("rel_l2 %.3e max %.3e" % (rel_l2(near, on), rel_max(near, on)), flush=True)
+    assert np.all(np.isfinite(out))
+    assert rel_l2(near, on) < 3e-5 and rel_max(near, on) < 1e-4
+    assert np.array_equal(near, near2)
+
+
 def test_deterministic(case):
     name, T, S, k, p, th, leaf, ofmm, plan = case
     src = T if S is None else S
