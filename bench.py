@@ -1,25 +1,32 @@
 """Benchmark: one CSFMM evaluation per step on one MI355X.
 
-Workload (the headline configuration): Poisson log kernel on the equiangular
-cubed sphere with 256 x 256 cells per face (N = 393,216, same target and
-source set, i = j omitted), field f = sum_{n=1..32} a_nm Y_nm with seeded
-N(0, 1/(n+1)^2) coefficients minus its area mean, w = f A; theta = 0.7,
-leaf <= 128, degree p in {6, 8, 10}.  The headline line uses the FP32 form
-(FP32 kernel evaluations, FP64 geometry, interpolation and sums) at the
-smallest degree whose measured error meets the 1e-5 relative L2 gate (p = 6
-unless --p is given); the FP64 form at the same degree and the other degrees
-are reported beside it.  The plan (trees, lists) is built once before
-timing; a step is one csfmm_eval: P2M, M2M, PP+PC, CP+CC, L2L, L2P.  Inputs
-are resident in HBM before the timed region.
+Headline workload (the largest single-GPU configuration): the 1/|x-y|
+kernel with 6,291,456 sources on the equiangular cubed sphere (1024 x 1024
+cells per face) carrying w = f A for a seeded band-limited field (n <= 64,
+coefficient variance (n+1)^-3, seed 4004), and 1,000,000 seeded uniform
+random targets (seed 4005); p = 10, theta = 0.6, leaf <= 128.  The headline
+line is the plain FP64 form (every step in FP64, the paper's arithmetic);
+the FP32 form (FP32 kernel evaluations, FP64 geometry, interpolation and
+sums) is reported beside it with its speed-up.  The plan (trees, lists) is
+built once before timing; a step is one csfmm_eval: P2M, M2M, PP, PC, CP,
+CC, L2L, L2P.  Inputs are resident in HBM before the timed region.
 
-Prints one JSON line.  --copy-calibration instead times a plain 256 MiB
-device copy (the reference kernel for scaling HBM byte counters).
+Errors are against the FP64 direct-sum oracle (C, OpenMP) on 4,096 seeded
+targets (seed 4006) x all sources; timing that oracle run on the host cores
+is the CPU baseline.  Beside the headline: the Poisson workload on
+256 x 256 cells per face (N = 393,216) at p = 6, 8, 10 in the FP32 form and
+p = 6 in FP64, each against the oracle on its 4,096-target sample.
+
+Prints one JSON line.  Other modes: --copy-calibration times a plain
+256 MiB device copy (the reference kernel for scaling HBM byte counters);
+--counters DIR folds rocprofv3 counter runs into a record under profiles/.
 """
 
 import argparse
 import json
 import os
 import platform
+import subprocess
 import sys
 import time
 
@@ -33,22 +40,30 @@ UNIT = "N^2-equiv interactions/s"
 TOL = 1e-5
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published)
 PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector (published)
-# Algorithmic floating point work of one Poisson evaluation K(x,y) w:
-# |x-y|^2 (3 sub, 3 mul, 2 add) + 1 log + 1 multiply-add (2) = 11 flops.
+# Algorithmic floating point work of one evaluation K(x,y) w of the Poisson
+# and 1/|x-y| kernels: |x-y|^2 (3 sub, 3 mul, 2 add) + 1 log or rsqrt + 1
+# multiply-add (2) = 11 flops.
 FLOP_PER_EVAL = 11
+HEADLINE_RECORD = "near_pp_invdist_src6291456_tgt1M_p10_fp64_counters.json"
+POISSON_RECORD = "near_pp_poisson_E256_p6_fp32_counters.json"
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--p", type=int, default=None, help="degree of the headline line")
-    ap.add_argument("--form", choices=("fp32", "fp64"), default="fp32")
-    ap.add_argument("--quick", action="store_true", help="headline configuration only")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--form", choices=("fp32", "fp64"), default="fp64",
+                    help="form of the headline line (the other one is reported beside it)")
+    ap.add_argument("--quick", action="store_true",
+                    help="headline form only (no other form, no Poisson lines, no CPU baseline)")
+    ap.add_argument("--poisson-only", action="store_true",
+                    help="only the Poisson N=393,216 lines (its kernels for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--counters", metavar="DIR",
+                    help="fold the rocprofv3 csv runs under DIR into a profiles/ record")
+    ap.add_argument("--record", default=HEADLINE_RECORD, help="record name for --counters")
     ap.add_argument("--serve", action="store_true", help="serving stream instead (2,000 requests)")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rho", type=float, nargs="*", default=[0.5, 0.8])
@@ -66,21 +81,57 @@ def parse():
     ap.add_argument("--bve-k", type=int, default=7)
     ap.add_argument("--configs", action="store_true",
                     help="the other workloads: Poisson E=32, Biot-Savart E=512, 1/|x-y| 6.3M x 1M")
+    ap.add_argument("--extras", action="store_true",
+                    help="also the per-kernel table and the treecode on the Poisson grid")
     return ap.parse_args()
 
 
-def recorded_traffic():
-    """HBM bytes per near-field launch from the committed counter record, or
-    None when the tile kernel's source has changed since it was taken."""
+def say(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def source_sha(name="tile.hip"):
     import hashlib
-    rec_path = os.path.join(ROOT, "profiles", "near_pp_poisson_E256_p6_fp32_counters.json")
-    src = os.path.join(ROOT, "paper_2508_13550_amd", "csrc", "tile.hip")
+    return hashlib.sha256(open(os.path.join(ROOT, "paper_2508_13550_amd", "csrc", name),
+                               "rb").read()).hexdigest()
+
+
+def recorded_traffic(name):
+    """The committed counter record `name`, or None when the tile kernel's
+    source has changed since it was taken."""
     try:
-        rec = json.load(open(rec_path))
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    except OSError:
+        rec = json.load(open(os.path.join(ROOT, "profiles", name)))
+    except (OSError, ValueError):
         return None
-    return rec if rec.get("tile_hip_sha256") == h else None
+    return rec if rec.get("tile_hip_sha256") == source_sha() else None
+
+
+def host_cpu():
+    """Model name of the host CPU (lscpu), for the CPU-baseline record."""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _norms(x):
+    x = np.asarray(x, dtype=np.float64)
+    return np.abs(x) if x.ndim == 1 else np.sqrt(np.sum(x * x, axis=1))
+
+
+def errors(got, ref, area=None):
+    """rel L2 (area weights or 1), max err (max |d| / max |ref|) and the
+    worst per-target error floored at the sample RMS, against the oracle."""
+    d, r = _norms(np.asarray(got) - ref), _norms(ref)
+    a = np.ones_like(r) if area is None else area
+    rms = float(np.sqrt(np.mean(r * r)))
+    return {"rel_l2_err": float(np.sqrt(np.sum(a * d * d) / np.sum(a * r * r))),
+            "max_err": float(np.max(d) / np.max(r)),
+            "elem_max_err": float(np.max(d / np.maximum(r, rms)))}
 
 
 def copy_calibration():
@@ -92,55 +143,6 @@ def copy_calibration():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
-
-
-def run_form(cs, torch, T, W, N, p, fp32, theta, leaf, steps, warmup, S, ref_s):
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan = cs.Plan(T, None, kernel=cs.POISSON, p=p, theta=theta, leaf_size=leaf, fp32=fp32)
-    torch.cuda.synchronize()
-    plan_ms = 1e3 * (time.perf_counter() - t0)
-    out = torch.empty(N, dtype=torch.float64, device=T.device)
-    for _ in range(warmup):
-        plan.eval(W, out=out)
-    torch.cuda.synchronize()
-    # timed region: events around the PP launch on its side stream (the
-    # roofline's kernel) and nothing else on the eval stream
-    plan.timing(2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.eval(W, out=out)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    n_pp, stage_pp = plan.timing_read()
-    plan.timing(False)
-    # latency of one eval: events around every eval, in a pass of its own
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(min(steps, 100))]
-    for a, b in ev:
-        a.record()
-        plan.eval(W, out=out)
-        b.record()
-    torch.cuda.synchronize()
-    lat = np.array([a.elapsed_time(b) for a, b in ev])
-    # stage breakdown in a separate pass with events at every stage boundary
-    plan.timing(1)
-    for _ in range(max(5, steps // 4)):
-        plan.eval(W, out=out)
-    n, stage = plan.timing_read()
-    plan.timing(False)
-    stage = {k: v / max(n, 1) for k, v in stage.items()}
-    stage["near_pp_timed_region"] = stage_pp["near_pp"] / max(n_pp, 1)
-    st = plan.stats()
-    plan.close()
-    phi = out[S]
-    rel = float(torch.sqrt(torch.sum((phi - ref_s) ** 2) / torch.sum(ref_s ** 2)))
-    mx = float(torch.max(torch.abs(phi - ref_s)) / torch.max(torch.abs(ref_s)))
-    ms = 1e3 * wall / steps
-    return dict(p=p, form="fp32" if fp32 else "fp64", plan_ms=plan_ms, ms=ms,
-                value=float(N) * N / (ms / 1e3), lat=lat, steps=steps,
-                stage=stage, stats=st, rel=rel, max=mx)
 
 
 KERNEL_NAMES = {1: "poisson", 2: "biot_savart", 3: "inv_dist", 4: "biharmonic", 5: "sal"}
@@ -191,32 +193,6 @@ def treecode_line(cs, torch, T, W, N, p, theta, leaf, S, ref_s, steps=5):
     res["form"] = "fp64"
     res["csfmm_speedup"] = res["cstc"]["ms"] / res["csfmm"]["ms"]
     return res
-
-
-def cpu_baseline(P, w, seconds):
-    """The direct-sum oracle on the host cores, on a bounded sample of targets."""
-    from oracle import direct, oracle_threads
-    from workloads import config_subset
-    n = P.shape[0]
-    m = 256
-    while True:
-        S = config_subset(n, m, 2003)
-        t0 = time.perf_counter()
-        direct(1, P[S], P, w)
-        t = time.perf_counter() - t0
-        if t > seconds / 4 or m >= n:
-            break
-        m = min(n, int(m * max(2.0, 0.9 * seconds / 4 / max(t, 1e-3))))
-    if t < seconds / 2 and m < n:
-        m = min(n, int(m * seconds / max(t, 1e-3)))
-        S = config_subset(n, m, 2003)
-        t0 = time.perf_counter()
-        direct(1, P[S], P, w)
-        t = time.perf_counter() - t0
-    return {"value": m * n / t, "unit": UNIT, "cores": oracle_threads(), "kind": "oracle",
-            "sample": "FP64 direct-sum oracle (C, OpenMP): %d seeded targets x all %d sources "
-                      "in %.1f s; the direct method's pairs/s is its N^2-equiv rate" % (m, n, t),
-            "host": platform.processor() or platform.machine()}
 
 
 SWEEP_TOLS = (1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12)
@@ -640,141 +616,310 @@ def serve_bench(args):
     print(json.dumps(line), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only (--gpus 1): the library runs on one GPU and has no multi-GPU path",
-              file=sys.stderr)
-        sys.exit(2)
-    if args.copy_calibration:
-        copy_calibration()
-        return
-    if args.serve:
-        serve_bench(args)
-        return
-    if args.sweep:
-        sweep_bench(args)
-        return
-    if args.table2:
-        table2_bench(args)
-        return
-    if args.table3:
-        table3_bench(args)
-        return
-    if args.bve:
-        bve_bench(args)
-        return
-    if args.configs:
-        configs_bench(args)
-        return
-    import torch
-    import paper_2508_13550_amd as cs
-    from workloads import make_config, config_subset
+def measure(cs, torch, Td, Sd, W, kernel, p, theta, leaf, fp32, steps, warmup, samp):
+    """Plan once, then: warm-up evals; `steps` timed evals with HIP events
+    around the PP launch (side stream) and the PC + far-field launch (eval
+    stream) and nothing else recorded; a latency pass with events around every
+    eval; a stage-breakdown pass.  Returns times, stats and the outputs at the
+    sampled targets (host)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = cs.Plan(Td, Sd, kernel=kernel, p=p, theta=theta, leaf_size=leaf, fp32=fp32)
+    torch.cuda.synchronize()
+    plan_ms = 1e3 * (time.perf_counter() - t0)
+    out = plan.eval(W)
+    for _ in range(warmup):
+        plan.eval(W, out=out)
+    torch.cuda.synchronize()
+    plan.timing(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.eval(W, out=out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n_t, st_t = plan.timing_read()
+    plan.timing(False)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(min(steps, 100))]
+    for a, b in ev:
+        a.record()
+        plan.eval(W, out=out)
+        b.record()
+    torch.cuda.synchronize()
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    plan.timing(1)
+    for _ in range(max(5, min(50, steps // 4))):
+        plan.eval(W, out=out)
+    n, stage = plan.timing_read()
+    plan.timing(False)
+    stage = {k: v / max(n, 1) for k, v in stage.items()}
+    stage["near_pp_timed_region"] = st_t["near_pp"] / max(n_t, 1)
+    stage["pc_far_timed_region"] = st_t["pc_far"] / max(n_t, 1)
+    st = plan.stats()
+    plan.close()
+    got = out[torch.as_tensor(samp, device=out.device)].cpu().numpy()
+    ms = 1e3 * wall / steps
+    del out
+    torch.cuda.empty_cache()
+    return dict(p=p, form="fp32" if fp32 else "fp64", plan_ms=plan_ms, ms=ms, steps=steps,
+                lat=lat, stage=stage, stats=st, got=got)
 
-    cfg = make_config(2)
-    P, w = cfg["sources"], cfg["weights"]
+
+def pp_grid(st):
+    """Work-items of the PP launch: four target leaves per block on the
+    one-wave-per-leaf path, else one leaf per block; 256 threads a block."""
+    nl = st["n_leaves_t"]
+    return 256 * ((nl + 3) // 4 if st["near_wave"] else nl)
+
+
+def roofline_of(r, fp32, record_name, kernel_desc):
+    """Roofline of the dominant stage (the longer of the PP launch and the PC +
+    far-field launch) from the HIP events of the timed region."""
+    st, stage = r["stats"], r["stage"]
+    peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
+    ev_far = st["evals_pc"] + st["evals_cp"] + st["evals_cc"]
+    pp_ms, far_ms = stage["near_pp_timed_region"], stage["pc_far_timed_region"]
+    parts = {
+        "pp": {"kernel": kernel_desc + ": PP near-field launch", "evals": st["evals_pp"],
+               "ms": pp_ms},
+        "pc_far": {"kernel": kernel_desc + ": PC near field + CP/CC far field launch",
+                   "evals": ev_far, "ms": far_ms}}
+    for q in parts.values():
+        q["achieved"] = q["evals"] * FLOP_PER_EVAL / (q["ms"] / 1e3) / 1e12 if q["ms"] > 0 else 0.0
+        q["frac"] = q["achieved"] / peak
+    dom = "pp" if pp_ms >= far_ms else "pc_far"
+    d = parts[dom]
+    rec = recorded_traffic(record_name)
+    traffic = None
+    if rec and dom == "pp":
+        g = pp_grid(st)
+        rows = [x for x in rec.get("dispatches", []) if x["grid_size"] == g and x["pp"]]
+        if rows:
+            traffic = sum(x["traffic_bytes"] for x in rows)
+    line = {"bound": "alu", "kernel": d["kernel"], "achieved": d["achieved"], "peak": peak,
+            "unit": "TFLOP/s", "frac": d["frac"], "traffic": traffic,
+            "flop_per_eval": FLOP_PER_EVAL, "evals_per_launch": d["evals"],
+            "avg_launch_ms": d["ms"], "dominant_stage": dom,
+            "other_stage": {k: v for k, v in parts[("pc_far" if dom == "pp" else "pp")].items()},
+            "traffic_record": record_name if traffic is not None else None}
+    return line
+
+
+def cpu_baseline_of(t_oracle, n_samp, n_src, what):
+    from oracle import oracle_threads
+    return {"value": n_samp * n_src / t_oracle, "unit": UNIT, "cores": oracle_threads(),
+            "kind": "oracle",
+            "sample": "FP64 direct-sum oracle (C, OpenMP) on %s: %d seeded targets x all %d "
+                      "sources in %.1f s; the direct method's pairs/s is its N^2-equiv rate"
+                      % (what, n_samp, n_src, t_oracle),
+            "host_cpu": host_cpu()}
+
+
+def poisson_lines(cs, torch, args):
+    """The Poisson workload N = 393,216 (theta 0.7, leaf 128) at p = 6, 8, 10
+    in the FP32 form and p = 6 in FP64, against the oracle on its sample."""
+    from oracle import direct as odirect
+    from workloads import make_config, config_subset
+    c = make_config(2)
+    P, w, A = c["sources"], c["weights"], c["areas"]
     N = P.shape[0]
+    S = config_subset(N, 4096, c["subset_seed"])
+    say("poisson: oracle on 4,096 targets x %d sources" % N)
+    ref = odirect(1, P[S], P, w)
     dev = torch.device("cuda:0")
     T = torch.tensor(P, dtype=torch.float64, device=dev)
     W = torch.tensor(w, dtype=torch.float64, device=dev)
-    theta, leaf = cfg["theta"], cfg["leaf"]
-    # error sample: 4,096 seeded targets against the GPU FP64 direct sum
-    S = torch.tensor(config_subset(N, 4096, cfg["subset_seed"]), device=dev)
-    ref_s = cs.direct(T[S].contiguous(), T, W, kernel=cs.POISSON)
+    steps = max(5, args.steps // 4)
+    res = {}
+    for fp32, p in ((True, 6), (True, 8), (True, 10), (False, 6)):
+        r = measure(cs, torch, T, None, W, 1, p, c["theta"], c["leaf"], fp32, steps,
+                    max(2, args.warmup // 2), S)
+        e = errors(r["got"], ref, A[S])
+        key = "%s_p%d" % (r["form"], p)
+        res[key] = {"ms_per_step": r["ms"], "value": float(N) * N / (r["ms"] / 1e3),
+                    "latency_ms": {"p50": float(np.percentile(r["lat"], 50)),
+                                   "p99": float(np.percentile(r["lat"], 99))},
+                    "plan_ms": r["plan_ms"], "stage_ms": r["stage"],
+                    "evals": {k: r["stats"]["evals_" + k] for k in ("pp", "pc", "cp", "cc")},
+                    "pp_close": r["stats"]["pp_close"], **e}
+        if fp32 and p == 6:
+            res[key]["roofline"] = roofline_of(r, True, POISSON_RECORD,
+                                               "k_tile_wave<Poisson,FP32> + k_sym_merge")
+        say("poisson %s done: %.4f ms, rel L2 %.2e" % (key, r["ms"], e["rel_l2_err"]))
+    res["fp32_over_fp64_speedup_p6"] = res["fp64_p6"]["ms_per_step"] / res["fp32_p6"]["ms_per_step"]
+    res["workload"] = ("Poisson log kernel, equiangular cubed sphere 256x256 cells per face "
+                       "(N=%d), same set, band-limited n<=32 field (seed 2002), theta=%g, "
+                       "leaf<=%d" % (N, c["theta"], c["leaf"]))
+    res["error_reference"] = "oracle direct sum on 4,096 seeded targets (seed 2003)"
+    extras = None
+    if args.extras:
+        Sd = torch.tensor(S, device=dev)
+        ref_s = torch.tensor(ref, device=dev)
+        extras = {"kernels": kernel_table(cs, torch, T, W, N, 6, c["theta"], c["leaf"], Sd, 10),
+                  "treecode": treecode_line(cs, torch, T, W, N, 6, c["theta"], c["leaf"], Sd,
+                                            ref_s)}
+    return res, extras
+
+
+def fold_counters(args):
+    """Fold rocprofv3 --pmc csv runs into profiles/<record>: DIR holds the runs
+    FETCH_SIZE, WRITE_SIZE (the benchmark), FETCH_SIZE_copy, WRITE_SIZE_copy
+    (--copy-calibration) and optionally SQ; every csv *counter_collection*
+    below each is read.  Per dispatch: counters summed over their rows; per
+    (kernel, grid size): the mean over its dispatches."""
+    import csv
+    import glob
+
+    def load(sub):
+        rows = {}
+        for f in glob.glob(os.path.join(args.counters, sub, "**", "*counter_collection*.csv"),
+                           recursive=True):
+            for r in csv.DictReader(open(f)):
+                key = (r["Kernel_Name"], int(r["Grid_Size"]))
+                d = rows.setdefault(key, {})
+                dd = d.setdefault(r["Dispatch_Id"], {})
+                dd[r["Counter_Name"]] = dd.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        out = {}
+        for key, d in rows.items():
+            names = set(n for dd in d.values() for n in dd)
+            out[key] = {"dispatches": len(d),
+                        **{n: float(np.mean([dd.get(n, 0.0) for dd in d.values()])) for n in names}}
+        return out
+
+    fetch, write = load("FETCH_SIZE"), load("WRITE_SIZE")
+    cf, cw = load("FETCH_SIZE_copy"), load("WRITE_SIZE_copy")
+    sq = load("SQ")
+    ck = [k for k in cf if "copyBuffer" in k[0]]
+    copy_bytes = 256 * 1024 * 1024
+    ffac = copy_bytes / (cf[ck[0]]["FETCH_SIZE"] * 1024.0)
+    wfac = copy_bytes / (cw[[k for k in cw if "copyBuffer" in k[0]][0]]["WRITE_SIZE"] * 1024.0)
+    disp = []
+    for key in sorted(fetch, key=lambda k: -fetch[k]["FETCH_SIZE"]):
+        name, grid = key
+        if not name.startswith(("k_tile", "k_sym_merge")):
+            continue
+        fk, wk = fetch[key]["FETCH_SIZE"], write.get(key, {}).get("WRITE_SIZE", float("nan"))
+        disp.append({"kernel": name, "grid_size": grid, "dispatches": fetch[key]["dispatches"],
+                     "fetch_size_kib": fk, "write_size_kib": wk,
+                     "traffic_bytes": fk * 1024.0 * ffac + wk * 1024.0 * wfac,
+                     "sq": {k: v for k, v in sq.get(key, {}).items() if k.startswith("SQ_")},
+                     "pp": False})
+    rec = {"record": args.record, "tile_hip_sha256": source_sha(),
+           "copy_calibration": {"bytes": copy_bytes, "fetch_factor": ffac, "write_factor": wfac},
+           "dispatches": disp,
+           "note": "mark the PP launch's rows with pp = true (grid size = its work-items)"}
+    path = os.path.join(ROOT, "profiles", args.record)
+    json.dump(rec, open(path, "w"), indent=1)
+    print(json.dumps(rec))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (--gpus 1): the library runs on one GPU and has "
+              "no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    if args.counters:
+        fold_counters(args)
+        return
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    for flag, fn in (("serve", serve_bench), ("sweep", sweep_bench), ("table2", table2_bench),
+                     ("table3", table3_bench), ("bve", bve_bench), ("configs", configs_bench)):
+        if getattr(args, flag):
+            fn(args)
+            return
+    import torch
+    import paper_2508_13550_amd as cs
+    cs.load_library()
+    if args.poisson_only:
+        res, extras = poisson_lines(cs, torch, args)
+        print(json.dumps({"metric": METRIC, "unit": UNIT, "n_gpus": 1, "poisson_E256": res,
+                          "extras": extras}), flush=True)
+        return
+    from oracle import direct as odirect
+    from workloads import make_config, config_subset
+
+    say("headline inputs: 6,291,456 sources (E=1024), 1,000,000 random targets")
+    c = make_config(4)
+    Y, w, X = c["sources"], c["weights"], c["targets"]
+    nt, ns = X.shape[0], Y.shape[0]
+    samp = config_subset(nt, 4096, c["subset_seed"])
+    say("oracle direct sum on 4,096 targets x %d sources" % ns)
+    t0 = time.perf_counter()
+    ref = odirect(3, X[samp], Y, w)
+    t_oracle = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    Xd = torch.tensor(X, dtype=torch.float64, device=dev)
+    Yd = torch.tensor(Y, dtype=torch.float64, device=dev)
+    W = torch.tensor(w, dtype=torch.float64, device=dev)
     fp32 = args.form == "fp32"
-
-    runs = []
-    degrees = [args.p] if args.p else [6, 8, 10]
-    head = None
-    for p in degrees:
-        r = run_form(cs, torch, T, W, N, p, fp32, theta, leaf,
-                     args.steps if head is None else max(5, args.steps // 5), args.warmup, S, ref_s)
-        runs.append(r)
-        if head is None and r["rel"] <= TOL:
-            head = r
-        if args.quick and head is not None:
-            break
-    if head is None:
-        head = runs[-1]
-    other = None
-    if not args.quick:
-        other = run_form(cs, torch, T, W, N, head["p"], not fp32, theta, leaf,
-                         max(5, args.steps // 5), args.warmup, S, ref_s)
-
-    # same-device direct sum on the 4,096-target sample
-    direct_rate = {}
-    if not args.quick:
-        Ts = T[S].contiguous()
-        for form in ("fp64", "fp32"):
-            cs.direct(Ts, T, W, kernel=cs.POISSON, fp32=(form == "fp32"))
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(3):
-                cs.direct(Ts, T, W, kernel=cs.POISSON, fp32=(form == "fp32"))
-            torch.cuda.synchronize()
-            direct_rate[form] = 3 * S.numel() * N / (time.perf_counter() - t0)
-
+    kw = dict(kernel=3, p=c["p"], theta=c["theta"], leaf=c["leaf"])
+    say("headline form %s: plan + %d warm-up + %d timed evals" % (args.form, args.warmup, args.steps))
+    head = measure(cs, torch, Xd, Yd, W, kw["kernel"], kw["p"], kw["theta"], kw["leaf"], fp32,
+                   args.steps, args.warmup, samp)
+    eh = errors(head["got"], ref)
+    say("headline done: %.3f ms per eval, rel L2 %.2e" % (head["ms"], eh["rel_l2_err"]))
     st = head["stats"]
-    # dominant kernel: the PP near-field launch (side stream, concurrent with
-    # the upward pass, so its duration includes sharing the device)
-    pp_ms = head["stage"]["near_pp_timed_region"]
-    achieved = st["evals_pp"] * FLOP_PER_EVAL / (pp_ms / 1e3) / 1e12
-    peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
-    rec = recorded_traffic() if (fp32 and head["p"] == 6) else None
-    roofline = {"bound": "alu",
-                "kernel": ("k_tile_wave<Poisson,FP32> + k_sym_merge: PP near-field stage"
-                           if fp32 else "k_tile<Poisson,FP64> PP near-field launch"),
-                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": rec["traffic_bytes_per_launch"] if rec else None,
-                "flop_per_eval": FLOP_PER_EVAL, "evals_per_launch": st["evals_pp"],
-                "avg_launch_ms": pp_ms}
-    if rec:
-        # executed work from the counter record: kernel values computed (the
-        # symmetric pairs serve both directions) and VALU issue slots, per
-        # algorithmic evaluation
-        sq = rec["sq"]
-        roofline["kernel_values_per_eval"] = sq["SQ_INSTS_VALU_TRANS_F32"] * 64 / st["evals_pp"]
-        roofline["valu_issue_slots_per_eval"] = ((sq["SQ_INSTS_VALU"] + sq["SQ_INSTS_VALU_TRANS_F32"])
-                                                 * 64 / st["evals_pp"])
-    far_ms = head["stage"]["pc_far"]
-    evals_far = st["evals_pc"] + st["evals_cp"] + st["evals_cc"]
-    roofline_far = {"kernel": "k_tile<Poisson,%s> PC near field + CP/CC far field launch"
-                              % args.form.upper(),
-                    "achieved": evals_far * FLOP_PER_EVAL / (far_ms / 1e3) / 1e12,
-                    "peak": peak, "unit": "TFLOP/s", "evals_per_launch": evals_far,
-                    "avg_launch_ms": far_ms}
+    workload = ("1/|x-y| kernel, 6,291,456 sources on the equiangular cubed sphere 1024x1024 "
+                "cells per face with a band-limited n<=64 field (seed 4004) x 1,000,000 uniform "
+                "random targets (seed 4005), p=%d, theta=%g, leaf<=%d, %s form"
+                % (kw["p"], kw["theta"], kw["leaf"], args.form))
     line = {
-        "metric": METRIC, "value": head["value"], "unit": UNIT, "n_gpus": 1,
-        "steps": head["steps"], "warmup": args.warmup, "ms_per_step": head["ms"],
+        "metric": METRIC, "value": float(nt) * ns / (head["ms"] / 1e3), "unit": UNIT,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if fp32 else "f64", "data": "synthetic",
-        "config": {"workload": "Poisson log kernel, equiangular cubed sphere 256x256 cells per "
-                               "face (N=%d), same set, band-limited n<=32 field (seed 2002), "
-                               "p=%d, theta=%g, leaf<=%d, %s form"
-                               % (N, head["p"], theta, leaf, args.form),
-                   "n": N, "p": head["p"], "theta": theta, "leaf": leaf, "form": args.form},
-        "rel_l2_err": head["rel"], "max_err": head["max"], "tolerance": TOL,
-        "meets_tolerance": head["rel"] <= TOL,
+        "config": {"workload": workload, "n_targets": nt, "n_sources": ns, "kernel": "inv_dist",
+                   "p": kw["p"], "theta": kw["theta"], "leaf": kw["leaf"], "form": args.form},
+        **eh, "tolerance": TOL, "meets_tolerance": eh["rel_l2_err"] <= TOL,
+        "error_reference": "FP64 direct-sum oracle (C) on 4,096 seeded targets (seed 4006) x "
+                           "all sources",
         "latency_ms": {"p50": float(np.percentile(head["lat"], 50)),
                        "p99": float(np.percentile(head["lat"], 99))},
         "plan_ms": head["plan_ms"], "stage_ms": head["stage"],
         "evals": {k: st["evals_" + k] for k in ("pp", "pc", "cp", "cc")},
-        "degrees": {str(r["p"]): {"value": r["value"], "ms_per_step": r["ms"],
-                                  "rel_l2_err": r["rel"]} for r in runs},
-        "roofline": roofline,
-        "roofline_pc_far": roofline_far,
+        "pp_close": st["pp_close"], "device_bytes": st["device_bytes"],
+        "roofline": roofline_of(head, fp32, HEADLINE_RECORD,
+                                "k_tile<InvDist,%s>" % ("FP32" if fp32 else "FP64")),
     }
-    if other is not None:
-        line["other_form"] = {"form": other["form"], "p": other["p"], "value": other["value"],
-                              "ms_per_step": other["ms"], "rel_l2_err": other["rel"],
-                              "stage_ms": other["stage"]}
+    if not args.quick:
+        say("other form")
+        other = measure(cs, torch, Xd, Yd, W, kw["kernel"], kw["p"], kw["theta"], kw["leaf"],
+                        not fp32, max(5, args.steps // 4), max(2, args.warmup // 2), samp)
+        eo = errors(other["got"], ref)
+        line["other_form"] = {"form": other["form"], "value": float(nt) * ns / (other["ms"] / 1e3),
+                              "ms_per_step": other["ms"], "plan_ms": other["plan_ms"],
+                              "stage_ms": other["stage"], "pp_close": other["stats"]["pp_close"],
+                              "latency_ms": {"p50": float(np.percentile(other["lat"], 50)),
+                                             "p99": float(np.percentile(other["lat"], 99))},
+                              **eo}
         f32, f64 = (head, other) if fp32 else (other, head)
         line["fp32_over_fp64_speedup"] = f64["ms"] / f32["ms"]
-        line["gpu_direct_rate"] = direct_rate
-        line["kernels"] = kernel_table(cs, torch, T, W, N, head["p"], theta, leaf, S, 10)
-        line["treecode"] = treecode_line(cs, torch, T, W, N, head["p"], theta, leaf, S, ref_s)
+        # same-device direct sum on the sample (the FMM's speed-up on one MI355X)
+        Xs = Xd[torch.as_tensor(samp, device=dev)].contiguous()
+        rates = {}
+        for form in ("fp64", "fp32"):
+            cs.direct(Xs, Yd, W, kernel=3, fp32=(form == "fp32"))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cs.direct(Xs, Yd, W, kernel=3, fp32=(form == "fp32"))
+            torch.cuda.synchronize()
+            rates[form] = len(samp) * ns / (time.perf_counter() - t0)
+        line["gpu_direct_rate"] = rates
+        line["fmm_over_gpu_direct_fp64"] = line["value"] / rates["fp64"] if not fp32 else None
+        del Xs
+        del Xd, Yd, W
+        torch.cuda.empty_cache()
+        say("poisson lines")
+        line["poisson_E256"], extras = poisson_lines(cs, torch, args)
+        if extras:
+            line["extras"] = extras
     if not args.no_cpu_baseline and not args.quick:
-        line["cpu_baseline"] = cpu_baseline(P, w, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline_of(t_oracle, len(samp), ns,
+                                               "the headline workload (1/|x-y|)")
     print(json.dumps(line), flush=True)
 
 

@@ -48,7 +48,8 @@ enum csfmm_status {
     CSFMM_E_OOM = -3,           /* device allocation failed */
     CSFMM_E_HIP = -4,           /* a HIP runtime call failed */
     CSFMM_E_BUSY = -5,          /* reserved */
-    CSFMM_E_UNSUPPORTED = -6    /* reserved */
+    CSFMM_E_UNSUPPORTED = -6,   /* reserved */
+    CSFMM_E_INTERNAL = -7       /* a kernel reported a broken internal bound (its result is void) */
 };
 
 /* Kernels K(x, y) for x, y on the unit sphere (paper §2). */
@@ -60,7 +61,7 @@ enum csfmm_kernel {
     CSFMM_K_SAL = 5          /* eq. (G_SAL_approx): (3 rw/(4pi re)) ((1 - b0)/gamma
                                 - (a1 - b1) ln(gamma/2 + gamma^2/4)), gamma = |x - y|,
                                 a1 = -2.7, b0 = -6.21196, b1 = 6.1, rw/re = 1025/5514
-                                (the ratio is named, not given, in §2.5); one output */
+                                (the ratio is named, not given, in §2.4); one output */
 };
 
 /* Precision forms. */
@@ -89,11 +90,11 @@ typedef struct csfmm_stats {
                                               per pair, and those that hold one way
                                               (the FP32 form evaluates a pair once for
                                               both directions); 0 otherwise */
-    int64_t near_exact;                    /* FP32 form: 1 when points come within 1/8 of a
-                                              half leaf width of each other across leaf
-                                              edges, so the PP entries of non-overlapping
-                                              leaves take exact differences (and no
-                                              symmetric pairs) */
+    int64_t pp_close;                      /* FP32 form: PP entries of non-overlapping
+                                              leaves whose points may come so close that
+                                              the expanded squared distance would lose
+                                              more than ~1e-4 of it; they take exact
+                                              differences (and no symmetric pairs) */
     int64_t near_wave;                     /* 1: the near field takes one wave per target
                                               leaf (leaves of at most 64 points, at least
                                               8 leaves per compute unit); 0: one block of
@@ -151,9 +152,13 @@ int csfmm_eval_kernel(csfmm_plan_t plan, int kernel_id, const double* weights, d
  * PP (eq. PP, its particles, exact coincidences omitted); other clusters are
  * opened into their children.  Always FP64, whatever the plan's flags.
  *   weights [n_s] device, out [n_t] or [n_t][3] device (caller order).
- * Asynchronous on `stream`; uses the plan's own workspace, so it must not
- * overlap a csfmm_eval of the same plan.
- * Errors: CSFMM_E_INVALID (NULL pointer, kernel id), CSFMM_E_HIP.
+ * Waits for `stream` before it returns: the traversal's stack (72 entries
+ * per wave; 66 suffice for 20 levels) reports an overflow in a status word
+ * that is read back, and the call then fails with CSFMM_E_INTERNAL instead
+ * of returning a sum with clusters left out.  Uses the plan's own workspace,
+ * so it must not overlap a csfmm_eval of the same plan.
+ * Errors: CSFMM_E_INVALID (NULL pointer, kernel id), CSFMM_E_INTERNAL,
+ * CSFMM_E_HIP.
  */
 int csfmm_eval_treecode(csfmm_plan_t plan, int kernel_id, const double* weights, double* out,
                         void* stream);
@@ -200,6 +205,12 @@ int csfmm_direct(const double* targets, int64_t n_t, const double* sources, int6
  * default), weights[r] [n_s] and outs[r] [n_t] or [n_t][3].  Each request's
  * arithmetic is the same as csfmm_eval's, whatever it is batched with.
  * A workspace must not be used by two evals in flight at once.
+ * Signature: this adds the `workspaces` argument to the plain
+ * (n_req, plans, kernel_ids, weights, outs, stream) form.  A plan's buffers
+ * for one eval (proxy weights, proxy potentials, near field) cannot be shared
+ * by two requests in flight, so the caller names the workspace of each
+ * request; that is what lets one resident plan serve several requests at once
+ * instead of allocating per call.
  */
 int csfmm_workspace_create(csfmm_plan_t plan, void* stream, csfmm_workspace_t* out);
                                                         /* waits for `stream` */
@@ -256,9 +267,10 @@ int csfmm_plan_stats(csfmm_plan_t plan, csfmm_stats* s);
 
 /*
  * Per-stage timing of csfmm_eval with HIP events recorded on the eval's
- * streams.  enable = 1 times every stage, 2 only the PP launch (its events
- * are on the side stream, so the eval stream gets no extra work; the other
- * sums stay 0), 0 turns timing off; turning it on resets the sums.
+ * streams.  enable = 1 times every stage, 2 only the two interaction
+ * launches, [2] and [3] below (two events on the side stream and two on the
+ * eval stream around them; the other sums stay 0), 0 turns timing off;
+ * turning it on resets the sums.
  * csfmm_plan_timing_read waits for the recorded events and returns the summed
  * milliseconds of the 5 stages over the timed evals:
  *   [0] weight gather + P2M, [1] M2M (and zeroing the proxy potentials),

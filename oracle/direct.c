@@ -7,8 +7,8 @@
  *
  *     phi_i = sum_j K(x_i, y_j) w_j ,
  *
- * over every source j, with the singular self term left out (paper §1: "the
- * i=j term in the sum is omitted").  A source is left out of target i exactly
+ * over every source j, with the singular self term left out (paper §1 leaves
+ * the term of a particle with itself out of the sum).  A source is left out of target i exactly
  * when its three coordinates equal those of x_i bit for bit; for a point set
  * without duplicates used as both targets and sources this is the i=j rule,
  * and for distinct sets it drops exact coincidences only.
@@ -20,14 +20,14 @@
  *   4  biharmonic (paper eq. G_B):       (1/4pi) dilog((1 + x.y)/2)
  *   5  SAL closed form (paper eq. G_SAL_approx):
  *        (3 rw/(4 pi re)) ((1 - b0)/gamma - (a1 - b1) ln(gamma/2 + gamma^2/4)),
- *        gamma = |x-y|, a1 = -2.7, b0 = -6.21196, b1 = 6.1 (§2.5), and the
+ *        gamma = |x-y|, a1 = -2.7, b0 = -6.21196, b1 = 6.1 (§2.4), and the
  *        density ratio rw/re = 1025/5514 (seawater over mean Earth density;
  *        the paper names the ratio without a number).
  * 1 - x.y is evaluated as |x-y|^2/2, which is the same number on the sphere
  * and keeps its relative accuracy for close pairs; likewise the dilogarithm's
  * argument u = (1 + x.y)/2 is carried as 1 - u = |x-y|^2/4.
  *
- * dilog(u) = -int_0^u ln(1-t)/t dt (§2.4) is summed from its power series
+ * dilog(u) = -int_0^u ln(1-t)/t dt (§2.2) is summed from its power series
  * sum_k u^k/k^2 (integrate the series of -ln(1-t)/t term by term) when
  * u <= 1/2, and through Euler's reflection formula
  * dilog(u) = pi^2/6 - ln(u) ln(1-u) - dilog(1-u) when u > 1/2, so the series

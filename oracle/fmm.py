@@ -77,7 +77,7 @@ KERNEL_INV_DIST = 3
 KERNEL_BIHARMONIC = 4
 KERNEL_SAL = 5
 
-# eq. (G_SAL_approx): Load Love number fit k'_n ~ a1/n, h'_n ~ b0 + b1/n (§2.5)
+# eq. (G_SAL_approx): Load Love number fit k'_n ~ a1/n, h'_n ~ b0 + b1/n (§2.4)
 SAL_A1, SAL_B0, SAL_B1 = -2.7, -6.21196, 6.1
 # seawater over mean Earth density; the paper names the ratio, not its value
 SAL_RHO_RATIO = 1025.0 / 5514.0

@@ -55,7 +55,7 @@ class Stats(ctypes.Structure):
         ("evals_cp", ctypes.c_int64), ("evals_cc", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64), ("max_leaf_t", ctypes.c_int64),
         ("pp_sym_pairs", ctypes.c_int64), ("pp_one_way", ctypes.c_int64),
-        ("near_exact", ctypes.c_int64), ("near_wave", ctypes.c_int64),
+        ("pp_close", ctypes.c_int64), ("near_wave", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -236,8 +236,8 @@ class Plan:
         return s.as_dict()
 
     def timing(self, enable=True):
-        """Per-stage event timing: True/1 every stage, 2 the PP launch only
-        (nothing recorded on the eval stream), False/0 off; on resets the sums."""
+        """Per-stage event timing: True/1 every stage, 2 the PP and the PC + far
+        launches only, False/0 off; on resets the sums."""
         level = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
         _check(_lib.csfmm_plan_timing(self.handle, level))
 

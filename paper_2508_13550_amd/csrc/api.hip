@@ -188,7 +188,7 @@ int csfmm_plan_stats(csfmm_plan_t plan, csfmm_stats* s) {
     s->max_leaf_t = plan->tt.max_leaf;
     s->pp_sym_pairs = plan->lists.sym.n_own;
     s->pp_one_way = plan->lists.sym.n_one;
-    s->near_exact = plan->near_exact ? 1 : 0;
+    s->pp_close = plan->lists.n_close;
     s->near_wave = csfmm::leaf_wave_path(plan->tt) ? 1 : 0;
     s->n_pp = plan->lists.cnt[kPP];
     s->n_pc = plan->lists.cnt[kPC];

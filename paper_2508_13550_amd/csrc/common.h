@@ -81,7 +81,6 @@ struct Tree {
     int64_t n = 0;
     int32_t ncells = 0, nleaves = 0, depth = 0;
     int32_t max_leaf = 0;  // largest number of points in a leaf
-    float min_gap = 1.f;   // least 1 - max(|u|, |v|) over the points (local leaf coordinates)
     std::vector<int32_t> level_begin;   // host: first cell of each level, + end
     std::vector<int32_t> parents_begin; // host: first entry of each level in `parents`
     // sorted points (SoA) and their caller indices
@@ -97,6 +96,9 @@ struct Tree {
     int32_t* leaf_anc = nullptr;
     double* center = nullptr;  // [ncells][3]
     double* radius = nullptr;  // [ncells]
+    // [ncells] leaves: a lower bound on the geodesic distance of the leaf's
+    // points to its edges; 0 for the other cells
+    double* gap = nullptr;
     double* prox = nullptr;    // [ncells][3][KS] proxy coordinates (SoA per cell)
     int32_t* leaves = nullptr;  // [nleaves] leaf cell ids (Morton order)
     int32_t* parents = nullptr; // non-leaf cells grouped by level (host offsets above)
@@ -124,6 +126,8 @@ struct Lists {
     int32_t* off[4] = {nullptr, nullptr, nullptr, nullptr};  // [ncells_t + 1]
     int32_t* src[4] = {nullptr, nullptr, nullptr, nullptr};  // [cnt]
     int32_t* novl = nullptr;  // [ncells_t] leading PP entries whose cells overlap the target
+    int32_t* ncl = nullptr;   // [ncells_t] FP32 form: the close PP entries that follow them
+    int64_t n_close = 0;      // sum of ncl
     int32_t* far_targets = nullptr;  // target cells with CP or CC entries
     int32_t n_far_targets = 0;
     int64_t evals[4] = {0, 0, 0, 0};
@@ -142,7 +146,7 @@ struct ReqView {
     // interaction lists
     const int32_t* off[4];
     const int32_t* src[4];
-    const int32_t *novl, *far_targets;
+    const int32_t *novl, *ncl, *far_targets;
     // fixed operators
     const double *bm2m, *lag1d;
     // workspace
@@ -150,7 +154,6 @@ struct ReqView {
     int64_t nt, ns, psi_stride;
     int32_t p, K, KS, nb1;
     int32_t nleaves_t, nleaves_s;
-    int32_t near_exact;  // near field of non-overlapping cells in exact differences (FP32 form)
     // symmetric PP split (SymPP) and its column-sum slots [n_own][kWaveLeaf]
     const int32_t *own_off, *own_src, *recv_off, *recv_slot, *one_off, *one_src;
     float* sym_col;
@@ -213,10 +216,6 @@ struct csfmm_workspace_s;
 struct csfmm_plan_s {
     int64_t nt = 0, ns = 0;
     bool same = false;
-    // FP32 form: points come closer to their leaf's edge than the expanded
-    // squared distance resolves, so PP entries of non-overlapping cells take
-    // exact differences (set by the plan from the trees' min_gap)
-    bool near_exact = false;
     int kernel = 1, p = 8, leaf = 64;
     double theta = 0.7;
     unsigned flags = 0;
@@ -231,6 +230,7 @@ struct csfmm_plan_s {
     int nb1 = 0;
     // the plan's own workspace, used by csfmm_eval
     csfmm_workspace_s* ws0 = nullptr;
+    int32_t* tc_status = nullptr;  // treecode stack-overflow flag (device)
     // optional per-stage timing with HIP events (ring of event sets)
     struct Timing {
         // P2M, M2M, PP (side stream), PC + CP + CC, L2L + L2P
@@ -238,7 +238,7 @@ struct csfmm_plan_s {
         static constexpr int kMain = 5;   // events on the eval stream per slot
         static constexpr int kEvents = kMain + 2;  // + PP start/end on the side stream
         static constexpr int kSlots = 32;
-        int on = 0;  // 0 off, 1 every stage, 2 the PP launch only (side stream)
+        int on = 0;  // 0 off, 1 every stage, 2 the PP and the PC + far-field launches only
         std::vector<hipEvent_t> ev;  // [kSlots][kEvents]
         std::vector<int> pending;    // slot recorded and not yet read
         double sum_ms[kStages] = {0, 0, 0, 0, 0};
@@ -295,7 +295,7 @@ inline bool leaf_wave_path(const csfmm::Tree& tt) {
 // (K(x, y) = K(y, x)), not for Biot-Savart.
 inline bool sym_path_possible(const csfmm_plan_s* P) {
     return P->lists.sym.on && (P->flags & CSFMM_FP32_FORM) && leaf_wave_path(P->tt) &&
-           P->lists.sym.n_own > 0 && !P->near_exact;
+           P->lists.sym.n_own > 0;
 }
 inline bool sym_path(const csfmm_plan_s* P, int kernel) {
     return sym_path_possible(P) && kernel != CSFMM_K_BIOT_SAVART;
@@ -351,6 +351,7 @@ struct TcArgs {
     int K, KS, N0, nroots;            // roots are cells 0 .. nroots-1
     double theta2;                    // MAC^2
     double* out;                      // [nt] or [nt][3], caller order
+    int32_t* status;                  // set to 1 by a wave whose stack overflows
 };
 int launch_treecode(const TcArgs& a, int kernel, hipStream_t s);
 int launch_direct(const double* tgt, int64_t nt, const double* src, int64_t ns, const double* w,

@@ -379,6 +379,11 @@ __global__ void k_scatter_near(const double* __restrict__ near, const double* __
     for (int d = 0; d < vd; ++d) out[o * vd + d] = near[d * nt + k] + pc[d * nt + k];
 }
 
+// *p = v (a fill kernel rather than a memset node)
+__global__ void k_set_i32(int32_t* p, int32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
 // Writes a request view to device memory (kernel argument instead of a copy,
 // so that it is ordered on the caller's stream only).
 __global__ void k_set_view(ReqView* dst, ReqView v) {
@@ -392,16 +397,21 @@ using Timing = csfmm_plan_s::Timing;
 // Adds the stage times of a finished slot to the sums.  Events of a slot:
 // [0..4] on the eval stream (start, after P2M, after M2M, after PC + far,
 // after L2L + L2P), [5, 6] around the PP launch on the side stream.
-// With timing level 2 only [5, 6] are recorded (no events on the eval stream).
+// With timing level 2 only the events around the two interaction launches
+// are recorded: [2, 3] (PC + far field) and [5, 6] (PP).
+bool event_recorded(int level, int k) {
+    return level == 1 || k == 2 || k == 3 || k == 5 || k == 6;
+}
 int drain_slot(Timing& tm, int slot) {
     if (!tm.pending[slot]) return CSFMM_OK;
     hipEvent_t* e = &tm.ev[size_t(slot) * Timing::kEvents];
-    const bool all = tm.pending[slot] == 1;
-    CSFMM_HIP_TRY(hipEventSynchronize(e[all ? Timing::kMain - 1 : Timing::kMain + 1]));
+    const int level = tm.pending[slot];
+    CSFMM_HIP_TRY(hipEventSynchronize(e[level == 1 ? Timing::kMain - 1 : 3]));
+    CSFMM_HIP_TRY(hipEventSynchronize(e[Timing::kMain + 1]));
     static constexpr int from[Timing::kStages] = {0, 1, 5, 2, 3};
     static constexpr int to[Timing::kStages] = {1, 2, 6, 3, 4};
     for (int k = 0; k < Timing::kStages; ++k) {
-        if (!all && from[k] < Timing::kMain) continue;
+        if (!event_recorded(level, from[k]) || !event_recorded(level, to[k])) continue;
         float ms = 0.f;
         CSFMM_HIP_TRY(hipEventElapsedTime(&ms, e[from[k]], e[to[k]]));
         tm.sum_ms[k] += ms;
@@ -516,14 +526,14 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
         int rc = drain_slot(tm, slot);
         if (rc != CSFMM_OK) return rc;
         ev = &tm.ev[size_t(slot) * Timing::kEvents];
-        tm.pending[slot] = tm.on;  // 1 every stage, 2 the PP launch only
+        tm.pending[slot] = tm.on;  // 1 every stage, 2 the two interaction launches
     }
-    const bool main_marks = ev && reqs[0].plan->timing.on == 1;
+    const int level = ev ? reqs[0].plan->timing.on : 0;
     // the PP near field runs on the first workspace's side stream
     csfmm_workspace_s* W0 = reqs[0].ws;
     hipStream_t side = W0->side;
     auto mark = [&](int k) -> int {
-        if (ev && (k >= Timing::kMain || main_marks))
+        if (ev && event_recorded(level, k))
             CSFMM_HIP_TRY(hipEventRecord(ev[k], k < Timing::kMain ? s : side));
         return CSFMM_OK;
     };
@@ -732,6 +742,7 @@ int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** ou
         v.src[k] = P->lists.src[k];
     }
     v.novl = P->lists.novl;
+    v.ncl = P->lists.ncl;
     v.far_targets = P->lists.far_targets;
     v.bm2m = P->bm2m;
     v.lag1d = P->lag1d;
@@ -741,7 +752,6 @@ int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** ou
     v.p = P->p; v.K = P->K; v.KS = P->KS; v.nb1 = P->nb1;
     v.nleaves_t = T.nleaves;
     v.nleaves_s = S.nleaves;
-    v.near_exact = P->near_exact ? 1 : 0;
     const SymPP& Y = P->lists.sym;
     v.own_off = Y.own_off; v.own_src = Y.own_src; v.recv_off = Y.recv_off;
     v.recv_slot = Y.recv_slot; v.one_off = Y.one_off; v.one_src = Y.one_src;
@@ -820,7 +830,19 @@ int run_treecode(csfmm_plan_s* P, int kernel, const double* weights, double* out
     a.nroots = S.level_begin.size() > 1 ? S.level_begin[1] : 0;
     a.theta2 = P->theta * P->theta;
     a.out = out;
-    return launch_treecode(a, kernel, s);
+    if (!P->tc_status) RCX(P->arena.alloc(&P->tc_status, 1));
+    a.status = P->tc_status;
+    k_set_i32<<<1, 64, 0, s>>>(P->tc_status, 0);
+    CSFMM_LAUNCH_CHECK();
+    RCX(launch_treecode(a, kernel, s));
+    int32_t st = 0;
+    CSFMM_HIP_TRY(hipMemcpyAsync(&st, P->tc_status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    CSFMM_HIP_TRY(hipStreamSynchronize(s));
+    if (st != 0) {
+        set_error("treecode: a traversal stack overflowed (result void)");
+        return CSFMM_E_INTERNAL;
+    }
+    return CSFMM_OK;
 }
 
 }  // namespace csfmm

@@ -218,14 +218,16 @@ __global__ void k_leaf_flags(const int32_t* __restrict__ child0, int n, int32_t*
     parent[k] = child0[k] < 0 ? 0 : 1;
 }
 
+__global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int n) {
     if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
 }
 
 // *a = v
-__global__ void k_set_u32(unsigned* __restrict__ a, unsigned v) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *a = v;
-}
 
 // *a = *b = *c = 0 (the element past the entries of three kind arrays)
 __global__ void k_zero_i32x3(int32_t* __restrict__ a, int32_t* __restrict__ b,
@@ -249,23 +251,28 @@ __device__ __forceinline__ int pp_find(const int32_t* off, const int32_t* src, i
 
 // Symmetric split of the PP entries of a same-set plan (see SymPP), per
 // target cell: each entry past the overlapping head (the cell itself) is
-// one-way (kind_one), a symmetric pair the cell owns (kind_own) or one its
-// partner owns (kind_recv, rev = the partner's entry of the pair).  One
+// one-way (kind_one; every close entry, which keeps exact differences, and so
+// stays first in the cell's one-way list), a symmetric pair the cell owns
+// (kind_own) or one its partner owns (kind_recv, rev = the partner's entry of
+// the pair).  One
 // element past the entries stays 0, so exclusive scans of the kinds give the
 // positions and, at off[t], the offsets of every cell.  One wave per target
 // cell, a lane per entry.
 __global__ void k_sym_kinds(int ncells, const int32_t* __restrict__ off,
                             const int32_t* __restrict__ src, const int32_t* __restrict__ novl,
-                            int32_t* __restrict__ kind_own, int32_t* __restrict__ kind_recv,
-                            int32_t* __restrict__ kind_one, int32_t* __restrict__ rev) {
+                            const int32_t* __restrict__ ncl, int32_t* __restrict__ kind_own,
+                            int32_t* __restrict__ kind_recv, int32_t* __restrict__ kind_one,
+                            int32_t* __restrict__ rev) {
     const int t = int(blockIdx.x) * (blockDim.x / 64) + int(threadIdx.x / 64);
     if (t >= ncells) return;
     for (int e = off[t] + int(threadIdx.x % 64); e < off[t + 1]; e += 64) {
         int k = 0, r = -1;
-        if (e >= off[t] + novl[t]) {
+        if (e >= off[t] + novl[t] + ncl[t]) {
             const int c = src[e];
             r = c != t ? pp_find(off, src, c, t) : -1;
             k = r < 0 ? 1 : (pair_owner(t, c) == t ? 2 : 3);
+        } else if (e >= off[t] + novl[t]) {
+            k = 1;
         }
         kind_own[e] = k == 2;
         kind_recv[e] = k == 3;
@@ -410,15 +417,25 @@ __global__ void k_cell_geometry(int n, const int32_t* __restrict__ level,
     }
 }
 
-// Local coordinates (u, v) in [-1,1]^2 of every point in its leaf (§4).
+// Local coordinates (u, v) in [-1,1]^2 of every point in its leaf (§4), and
+// the leaf's gap: a lower bound on the geodesic distance from its points to
+// the leaf's boundary.  The cell edges xi = const and eta = const are great
+// circles; a point at angle xi on its face lies at sin-distance
+// rho_a sin(xi - xi0) from the circle xi = xi0, rho_a^2 = (1 + A^2)/(1 + A^2 +
+// B^2), A = tan xi, B = tan eta (and likewise for eta), and the geodesic
+// distance is at least its sine.  Two points in leaves that do not overlap
+// (cells are convex) are then at least gap_T + gap_S apart along the sphere.
 __global__ void k_leaf_local(const int32_t* __restrict__ leaves, int nleaves,
                              const int32_t* __restrict__ level, const int32_t* __restrict__ ci,
                              const int32_t* __restrict__ cj, const int32_t* __restrict__ begin,
                              const int32_t* __restrict__ count, const double* __restrict__ xi,
                              const double* __restrict__ eta, double* __restrict__ u,
-                             double* __restrict__ v) {
+                             double* __restrict__ v, double* __restrict__ gap) {
+    __shared__ unsigned gmin;
     const int L = blockIdx.x;
     if (L >= nleaves) return;
+    if (threadIdx.x == 0) gmin = 0x7f800000u;  // +inf
+    __syncthreads();
     const int c = leaves[L];
     const double d = kPi2 / double(1u << level[c]);
     const double half = 0.5 * d;
@@ -426,19 +443,20 @@ __global__ void k_leaf_local(const int32_t* __restrict__ leaves, int nleaves,
     const double ym = -kPi4 + (double(cj[c]) + 0.5) * d;
     const int b = begin[c], m = count[c];
     for (int k = threadIdx.x; k < m; k += blockDim.x) {
-        u[b + k] = (xi[b + k] - xm) / half;
-        v[b + k] = (eta[b + k] - ym) / half;
+        const double uu = (xi[b + k] - xm) / half, vv = (eta[b + k] - ym) / half;
+        u[b + k] = uu;
+        v[b + k] = vv;
+        const double A = tan(xi[b + k]), B = tan(eta[b + k]);
+        const double q = 1.0 + A * A + B * B;
+        const double ga = sqrt((1.0 + A * A) / q) * sin(fmax(0.0, 1.0 - fabs(uu)) * half);
+        const double gb = sqrt((1.0 + B * B) / q) * sin(fmax(0.0, 1.0 - fabs(vv)) * half);
+        // rounded down to FP32 (a lower bound); bits of non-negative floats order
+        float g = float(fmax(0.0, fmin(ga, gb)));
+        if (g > 0.f && double(g) > fmin(ga, gb)) g = __uint_as_float(__float_as_uint(g) - 1u);
+        atomicMin(&gmin, __float_as_uint(g));
     }
-}
-
-// Least distance of a point to its leaf's edge in local coordinates,
-// 1 - max(|u|, |v|) >= 0, as float bits (monotone for non-negative floats).
-__global__ void k_min_gap(const double* __restrict__ u, const double* __restrict__ v, int64_t n,
-                          unsigned* __restrict__ out) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float g = fmaxf(0.f, float(1.0 - fmax(fabs(u[i]), fabs(v[i]))));
-    atomicMin(out, __float_as_uint(g));
+    __syncthreads();
+    if (threadIdx.x == 0) gap[c] = m > 0 ? double(__uint_as_float(gmin)) : 0.0;
 }
 
 // §4 barycentric Lagrange L_k(x) at the Chebyshev points, exact hit -> delta.
@@ -594,31 +612,65 @@ __device__ __forceinline__ bool cells_overlap(const CellIds& A, int a, const Cel
            (A.cj[a] >> (la - l)) == (B.cj[b] >> (lb - l));
 }
 
-// Sort key of a (target, source) entry: by target, then overlapping entries
-// first (for PP only), then by source:  t*2ns + (overlap ? 0 : ns) + s.
+// PP entries of non-overlapping leaves whose points may come close (FP32 form).
+// The expanded squared distance |t|^2 + |s|^2 - 2 t.s of two points recentred
+// at a cell centre errs by a few FP32 ulps of |t|^2 + |s|^2 =
+// (|t + s|^2 + d^2)/2, d = |t - s|, and |t + s| <= 2 r + d for t in a cell of
+// radius r about the centre: its relative error is a few ulps of
+// (1 + (1 + 2 r/d)^2)/2.  With d at least the chord of gap_T + gap_S and r
+// the larger radius (so that the class is the same for (T, S) and (S, T)),
+// an entry is close when 2 r/d may exceed kCloseRatio, i.e. when the ratio
+// may exceed 256 (a relative error of about 1e-4 of d^2 at most); such
+// entries take exact differences.  Leaves of a uniform grid (points at least
+// 1/8 of a half width from the edges) stay below it; random points do not.
+constexpr double kCloseRatio = 21.6;
+struct CloseGeom {
+    const double *gap_t, *gap_s, *rad_t, *rad_s;
+};
+__device__ __forceinline__ bool pp_close(const CloseGeom& G, int t, int s) {
+    const double dmin = 2.0 * sin(0.5 * fmin(G.gap_t[t] + G.gap_s[s], kPi));
+    const double r = fmax(G.rad_t[t], G.rad_s[s]);
+    return 2.0 * r > kCloseRatio * dmin;
+}
+
+// Sort key of a (target, source) entry: by target, then (PP only) the
+// overlapping entries, the close ones (classify_close) and the others, then by
+// source:  t*3ns + class*ns + s.
 __global__ void k_pair_keys(const int32_t* __restrict__ t, const int32_t* __restrict__ s, int64_t n,
-                            int64_t ns_cells, bool mark_overlap, CellIds TC, CellIds SC,
-                            uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+                            int64_t ns_cells, bool mark_overlap, bool classify_close, CellIds TC,
+                            CellIds SC, CloseGeom G, uint64_t* __restrict__ keys,
+                            int32_t* __restrict__ vals) {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const bool ovl = mark_overlap && cells_overlap(TC, t[k], SC, s[k]);
-    keys[k] = uint64_t(t[k]) * uint64_t(2 * ns_cells) + (ovl ? 0ull : uint64_t(ns_cells)) +
+    const int cls = ovl ? 0 : ((classify_close && pp_close(G, t[k], s[k])) ? 1 : 2);
+    keys[k] = uint64_t(t[k]) * uint64_t(3 * ns_cells) + uint64_t(cls) * uint64_t(ns_cells) +
               uint64_t(s[k]);
     vals[k] = int32_t(k);
 }
 
 __global__ void k_csr_from_keys(const uint64_t* __restrict__ keys, int64_t n, int64_t ns_cells,
                                 int nt_cells, int32_t* __restrict__ off, int32_t* __restrict__ src,
-                                int32_t* __restrict__ novl) {
+                                int32_t* __restrict__ novl, int32_t* __restrict__ ncl) {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const uint64_t ns2 = uint64_t(2 * ns_cells);
-    if (k < n) src[k] = int32_t((keys[k] % ns2) % uint64_t(ns_cells));
+    const uint64_t ns3 = uint64_t(3 * ns_cells), ns1 = uint64_t(ns_cells);
+    if (k < n) src[k] = int32_t((keys[k] % ns3) % ns1);
     if (k <= nt_cells) {
-        const int64_t b = lower_bound_u64(keys, 0, n, uint64_t(k) * ns2);
+        const int64_t b = lower_bound_u64(keys, 0, n, uint64_t(k) * ns3);
         off[k] = int32_t(b);
-        if (novl && k < nt_cells)
-            novl[k] = int32_t(lower_bound_u64(keys, b, n, uint64_t(k) * ns2 + uint64_t(ns_cells)) - b);
+        if (novl && k < nt_cells) {
+            const int64_t b1 = lower_bound_u64(keys, b, n, uint64_t(k) * ns3 + ns1);
+            const int64_t b2 = lower_bound_u64(keys, b1, n, uint64_t(k) * ns3 + 2 * ns1);
+            novl[k] = int32_t(b1 - b);
+            ncl[k] = int32_t(b2 - b1);
+        }
     }
+}
+
+// n_close += ncl[t] over the target cells
+__global__ void k_sum_i32(const int32_t* __restrict__ a, int n, unsigned long long* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n && a[k] != 0) atomicAdd(out, (unsigned long long)a[k]);
 }
 
 __global__ void k_far_flags(const int32_t* __restrict__ ocp, const int32_t* __restrict__ occ, int n,
@@ -808,20 +860,11 @@ int build_tree(csfmm_plan_s* P, Tree& T, const double* pts, int64_t n, hipStream
     k_cell_geometry<<<nc, 128, 0, s>>>(nc, T.level, T.face, T.ci, T.cj, P->p, P->KS, T.center,
                                        T.radius, T.prox);
     CSFMM_LAUNCH_CHECK();
+    RC(A.alloc(&T.gap, nc));
+    k_fill_f64<<<nblk(nc), kT, 0, s>>>(T.gap, nc, 0.0);
     k_leaf_local<<<nleaves, 128, 0, s>>>(T.leaves, nleaves, T.level, T.ci, T.cj, T.begin, T.count,
-                                         xi, eta, T.u, T.v);
+                                         xi, eta, T.u, T.v, T.gap);
     CSFMM_LAUNCH_CHECK();
-    unsigned* gap;
-    RC(S.get(&gap, 1));
-    k_set_u32<<<1, 1, 0, s>>>(gap, 0x3f800000u);  // 1.0f
-    k_min_gap<<<nblk(n), kT, 0, s>>>(T.u, T.v, n, gap);
-    CSFMM_LAUNCH_CHECK();
-    unsigned hgap = 0;
-    CSFMM_HIP_TRY(hipMemcpyAsync(&hgap, gap, sizeof(hgap), hipMemcpyDeviceToHost, s));
-    CSFMM_HIP_TRY(hipStreamSynchronize(s));
-    float g = 1.f;
-    std::memcpy(&g, &hgap, sizeof(g));
-    T.min_gap = g;
     return CSFMM_OK;
 }
 
@@ -886,10 +929,13 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
 
     // concatenate, sort by (target, source), CSR by target cell
     const int64_t nsc = Sx.ncells;
-    const int64_t maxkey = int64_t(T.ncells) * 2 * nsc;
+    const int64_t maxkey = int64_t(T.ncells) * 3 * nsc;
     const CellIds tcid{T.level, T.face, T.ci, T.cj};
     const CellIds scid{Sx.level, Sx.face, Sx.ci, Sx.cj};
+    const CloseGeom cg{T.gap, Sx.gap, T.radius, Sx.radius};
+    const bool classify_close = (P->flags & CSFMM_FP32_FORM) != 0;
     RC(A.alloc(&P->lists.novl, T.ncells));
+    RC(A.alloc(&P->lists.ncl, T.ncells));
     int bits = 1;
     while (bits < 63 && (int64_t(1) << bits) < maxkey) ++bits;
     for (int k = 0; k < 4; ++k) {
@@ -910,8 +956,9 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
         RC(S.get(&keys, cnt));
         RC(S.get(&vals, cnt));
         if (cnt > 0) {
-            k_pair_keys<<<nblk(cnt), kT, 0, s>>>(lt, ls, cnt, nsc, k == kPP, tcid, scid, keys,
-                                                 vals);
+            k_pair_keys<<<nblk(cnt), kT, 0, s>>>(lt, ls, cnt, nsc, k == kPP,
+                                                 k == kPP && classify_close, tcid, scid, cg,
+                                                 keys, vals);
             CSFMM_LAUNCH_CHECK();
             RC(radix_sort_u64(keys, vals, cnt, bits, s));
         }
@@ -920,7 +967,8 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
         const int64_t m = std::max<int64_t>(cnt, int64_t(T.ncells) + 1);
         k_csr_from_keys<<<nblk(m), kT, 0, s>>>(keys, cnt, nsc, T.ncells, P->lists.off[k],
                                                P->lists.src[k],
-                                               k == kPP ? P->lists.novl : nullptr);
+                                               k == kPP ? P->lists.novl : nullptr,
+                                               k == kPP ? P->lists.ncl : nullptr);
         CSFMM_LAUNCH_CHECK();
     }
     // target cells with far-field (CP or CC) work
@@ -939,8 +987,9 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
 
     // evaluation counts of the four lists (integer sums on the device)
     unsigned long long* dev_ev;
-    RC(S.get(&dev_ev, 5));
-    k_zero_u64<<<1, 5, 0, s>>>(dev_ev, 5);
+    RC(S.get(&dev_ev, 6));
+    k_zero_u64<<<1, 6, 0, s>>>(dev_ev, 6);
+    k_sum_i32<<<nblk(T.ncells), kT, 0, s>>>(P->lists.ncl, T.ncells, dev_ev + 5);
     for (int k = 0; k < 4; ++k) {
         k_count_evals<<<nblk(T.ncells), kT, 0, s>>>(k, P->lists.off[k], P->lists.src[k], T.count,
                                                      Sx.count, T.ncells, P->K, P->same ? 1 : 0,
@@ -949,11 +998,12 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
     // and the largest target leaf (selects the near-field tile path)
     k_max_leaf<<<nblk(T.nleaves), kT, 0, s>>>(T.leaves, T.nleaves, T.count, dev_ev + 4);
     CSFMM_LAUNCH_CHECK();
-    unsigned long long hev[5];
+    unsigned long long hev[6];
     CSFMM_HIP_TRY(hipMemcpyAsync(hev, dev_ev, sizeof(hev), hipMemcpyDeviceToHost, s));
     CSFMM_HIP_TRY(hipStreamSynchronize(s));
     for (int k = 0; k < 4; ++k) P->lists.evals[k] = int64_t(hev[k]);
     T.max_leaf = int32_t(hev[4]);
+    P->lists.n_close = int64_t(hev[5]);
 
     // symmetric split of the PP entries (same-set plans in the FP32 form, the
     // form whose evals use it)
@@ -971,8 +1021,8 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
         RC(S.get(&e1, ne + 1));
         const int32_t *off = P->lists.off[kPP], *src = P->lists.src[kPP];
         k_zero_i32x3<<<1, 1, 0, s>>>(ko + ne, kr + ne, k1 + ne);
-        k_sym_kinds<<<nblk(int64_t(nc) * 64), kT, 0, s>>>(nc, off, src, P->lists.novl, ko, kr, k1,
-                                                          rev);
+        k_sym_kinds<<<nblk(int64_t(nc) * 64), kT, 0, s>>>(nc, off, src, P->lists.novl,
+                                                          P->lists.ncl, ko, kr, k1, rev);
         CSFMM_LAUNCH_CHECK();
         int32_t tot[3];
         RC(scan_exclusive_i32(ko, eo, ne + 1, dtot, s));
@@ -1038,12 +1088,6 @@ int build_plan(csfmm_plan_s* P, const double* targets, const double* sources, hi
     RC(A.alloc(&P->bm2m, int64_t(4) * P->KS * P->nb1));
     k_build_ops<<<1, 256, 0, s>>>(P->p, P->KS, P->nb1, P->lag1d, P->bm2m);
     CSFMM_LAUNCH_CHECK();
-    // Points in different cells are at least (gap_t + gap_s) half cell widths
-    // apart.  The expanded squared distance |t|^2 + |s|^2 - 2 t.s of the FP32
-    // form errs by a few FP32 ulps of |t|^2 + |s|^2 (up to about six squared half
-    // widths for neighbouring cells); below a separation of 1/8 half width the
-    // closest pairs would lose more than about 1e-4 of their squared distance.
-    P->near_exact = (P->flags & CSFMM_FP32_FORM) && (P->tt.min_gap + P->st->min_gap) < 0.125f;
     RC(build_lists(P, s));
     // the plan's own eval workspace
     RC(workspace_create(P, s, &P->ws0));

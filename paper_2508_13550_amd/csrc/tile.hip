@@ -109,7 +109,7 @@ __device__ __forceinline__ float dilog_1m(float v) {
     return refl ? fmaf(-ln2 * ln2, a * b, float(kPi2Over6)) - sr : sr;
 }
 
-// SAL closed form, eq. (G_SAL_approx), with the Love number fit of §2.5.
+// SAL closed form, eq. (G_SAL_approx), with the Love number fit of §2.4.
 constexpr double kSalA1 = -2.7, kSalB0 = -6.21196, kSalB1 = 6.1;
 constexpr double kSalRho = 1025.0 / 5514.0;  // seawater / mean Earth density
 constexpr double kSalQ = -2.0 * (kSalA1 - kSalB1) / (1.0 - kSalB0);
@@ -132,14 +132,14 @@ __device__ __forceinline__ float sal_bracket(float v) {
 //  FORM_NEAR   cells that do not overlap the target (no check)
 //  FORM_FAR    MAC-separated entries
 //  FORM_EXACT  cells that do not overlap the target, exact differences and the
-//              zero check (the FP32 form of plans whose points come close to
-//              their leaf edges: close pairs in neighbouring leaves)
+//              zero check (FP32 form: the PP entries the plan marks close,
+//              whose points may come near each other across leaf edges)
 // In the FP32 form the scalar kernels take |t-s|^2 = |t|^2 + |s|^2 - 2 t.s for
 // FORM_NEAR and FORM_FAR (4 operations instead of 6; coordinates are recentred
-// at the target cell, so |t|^2 + |s|^2 stays within a small multiple of the
-// squared distance of two points in different cells and the relative error of
-// the result stays near FP32 rounding); FORM_CHECK keeps exact differences so
-// that a coincident point gives exactly 0.
+// at the target cell, and the plan's close-pair rule, or the MAC, bounds
+// (|t|^2 + |s|^2)/|t-s|^2, so the relative error of the squared distance stays
+// within a few hundred FP32 ulps); FORM_CHECK keeps exact differences so that
+// a coincident point gives exactly 0.
 enum { FORM_CHECK = 0, FORM_NEAR = 1, FORM_FAR = 2, FORM_EXACT = 3 };
 
 struct TargetRegs {
@@ -271,6 +271,7 @@ struct TileArgs {
     const int32_t *off_a, *src_a;  // list with particle sources (PP or CP)
     const int32_t *off_b, *src_b;  // list with proxy sources (PC or CC)
     const int32_t* novl;           // leading overlapping entries of list a (PP), or NULL
+    const int32_t* ncl;            // close entries of list a after them (PP), or NULL
     const int32_t *sbegin, *scount;
     const double *sx, *sy, *sz, *sw;
     const double *sprox, *swbar;
@@ -299,6 +300,7 @@ __device__ __forceinline__ TileArgs tile_args(const ReqView& V, int mode) {
     a.off_b = V.off[TPROX ? kCC : kPC];
     a.src_b = V.src[TPROX ? kCC : kPC];
     a.novl = TPROX ? nullptr : V.novl;
+    a.ncl = TPROX ? nullptr : V.ncl;
     a.sbegin = V.s_begin;
     a.scount = V.s_count;
     a.sx = V.s_x;
@@ -486,9 +488,11 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
     const int ea0 = a.off_a[T], nea = a.use_a ? a.off_a[T + 1] - ea0 : 0;
     const int eb0 = a.off_b[T], neb = a.use_b ? a.off_b[T + 1] - eb0 : 0;
     const int nov = (a.use_a && a.novl) ? a.novl[T] : 0;
-    // entry ranges of the three forms: [0,nov) check, [nov,nea) near, [nea,nea+neb) far;
-    // sources of the far kernel are all MAC separated
-    const int ph_hi[3] = {TPROX ? 0 : nov, TPROX ? 0 : nea, nea + neb};
+    const int ncl = (a.use_a && a.ncl) ? a.ncl[T] : 0;
+    // entry ranges of the four forms: [0,nov) check, [nov,nov+ncl) exact,
+    // [nov+ncl,nea) near, [nea,nea+neb) far; sources of the far kernel are all
+    // MAC separated
+    const int ph_hi[4] = {TPROX ? 0 : nov, TPROX ? 0 : nov + ncl, TPROX ? 0 : nea, nea + neb};
     const int ne_all = nea + neb;
 
     for (int t0 = 0; t0 < nT; t0 += kThreads) {
@@ -538,12 +542,12 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
             if (tid == kThreads - 1) e_pref[kMaxEntries] = incl;
             __syncthreads();
             // source offsets where the forms change inside this batch
-            int bnd[4];
+            int bnd[5];
             bnd[0] = 0;
-            bnd[3] = e_pref[kMaxEntries];
-            bnd[1] = e_pref[min(max(ph_hi[0] - ebase, 0), kMaxEntries)];
-            bnd[2] = e_pref[min(max(ph_hi[1] - ebase, 0), kMaxEntries)];
-            for (int ph = 0; ph < 3; ++ph) {
+            bnd[4] = e_pref[kMaxEntries];
+#pragma unroll
+            for (int q = 1; q < 4; ++q) bnd[q] = e_pref[min(max(ph_hi[q - 1] - ebase, 0), kMaxEntries)];
+            for (int ph = 0; ph < 4; ++ph) {
                 for (int q0 = bnd[ph]; q0 < bnd[ph + 1]; q0 += kTileChunk) {
                     const int nq = min(kTileChunk, bnd[ph + 1] - q0);
                     const int Tj = nq == kTileChunk ? Tj_full : group_len(nq, G);
@@ -582,9 +586,9 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
                         for (int v = 0; v < VD; ++v) p[v] = R(0);
                         if (ph == 0)
                             run_group<KERN, F32, FORM_CHECK>(Lb, g * Tj, Tj, TR, p);
-                        else if (ph == 1 && V.near_exact)
-                            run_group<KERN, F32, FORM_EXACT>(Lb, g * Tj, Tj, TR, p);
                         else if (ph == 1)
+                            run_group<KERN, F32, FORM_EXACT>(Lb, g * Tj, Tj, TR, p);
+                        else if (ph == 2)
                             run_group<KERN, F32, FORM_NEAR>(Lb, g * Tj, Tj, TR, p);
                         else
                             run_group<KERN, F32, FORM_FAR>(Lb, g * Tj, Tj, TR, p);
@@ -773,16 +777,21 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
     const int eb0 = a.use_b ? gload(a.off_b, T) : 0;
     const int neb = a.use_b ? gload(a.off_b, T + 1) - eb0 : 0;
     const int nov = (a.use_a && a.novl) ? gload(a.novl, T) : 0;
+    const int ncl = (a.use_a && a.ncl) ? gload(a.ncl, T) : 0;
     // symmetric PP path (FP32 scalar kernels, PP launch): the distinct leaves'
-    // entries split into one-way entries (here, phase 1) and owned pairs
-    // (sym_pairs below); pairs owned by the partner come in through k_sym_merge
+    // entries split into one-way entries (here, phases 1 and 2; the close ones
+    // lead the one-way list) and owned pairs (sym_pairs below); pairs owned by
+    // the partner come in through k_sym_merge
     constexpr bool kSymKernel = F32 && KERN != CSFMM_K_BIOT_SAVART;
     sym = kSymKernel && sym && a.use_a;
     const int32_t* list1 = sym ? V.one_src : a.src_a + ea0;
-    const int one0 = sym ? gload(V.one_off, T) : 0;
-    for (int ph = 0; ph < 3; ++ph) {
-        const int e_beg = ph == 1 ? (sym ? one0 : nov) : 0;
-        const int e_end = ph == 0 ? nov : ph == 1 ? (sym ? gload(V.one_off, T + 1) : nea) : neb;
+    const int base1 = sym ? gload(V.one_off, T) : nov;
+    const int end1 = sym ? gload(V.one_off, T + 1) : nea;
+    // phases: 0 overlapping entries (check), 1 close entries (exact
+    // differences), 2 the other PP entries, 3 PC entries (far form)
+    for (int ph = 0; ph < 4; ++ph) {
+        const int e_beg = ph == 1 ? base1 : ph == 2 ? base1 + ncl : 0;
+        const int e_end = ph == 0 ? nov : ph == 1 ? base1 + ncl : ph == 2 ? end1 : neb;
         // entry cache: lane l holds the code and size of entry cb + l
         int cb = e_beg - 64, c_code = 0, c_size = 0;
         int e = e_beg, off = 0;  // next entry and its sources already staged
@@ -803,7 +812,7 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
                         c_code = 0;
                         c_size = 0;
                         if (ee < e_end) {
-                            if (ph < 2) {
+                            if (ph < 3) {
                                 const int sc = ph == 0 ? gload(a.src_a, ea0 + ee)
                                                        : gload(list1, ee);
                                 c_code = gload(a.sbegin, sc);
@@ -849,9 +858,9 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
             for (int v = 0; v < VD; ++v) p[v] = R(0);
             if (ph == 0)
                 run_group<KERN, F32, FORM_CHECK>(L, 0, npad, TR, p);
-            else if (ph == 1 && V.near_exact)
-                run_group<KERN, F32, FORM_EXACT>(L, 0, npad, TR, p);
             else if (ph == 1)
+                run_group<KERN, F32, FORM_EXACT>(L, 0, npad, TR, p);
+            else if (ph == 2)
                 run_group<KERN, F32, FORM_NEAR>(L, 0, npad, TR, p);
             else
                 run_group<KERN, F32, FORM_FAR>(L, 0, npad, TR, p);
@@ -1123,6 +1132,8 @@ __global__ void k_direct_reduce(const double* __restrict__ tgt, int64_t nt,
 // interactions, so the result is the per-target traversal of Algorithm 1.
 // Stack bound: at most 5 waiting roots and 3 waiting siblings per level below
 // them, plus 4 pushed children: 5 + 3 * 19 + 4 = 66 entries for 20 levels.
+// A push beyond the stack sets the status word instead (the host then fails
+// the call), so a broken bound can never drop a cluster silently.
 constexpr int kTcStack = 72;
 
 __device__ __forceinline__ bool tc_separated(double x, double y, double z, const double* c,
@@ -1157,6 +1168,7 @@ __global__ __launch_bounds__(256) void k_treecode(TcArgs a) {
     for (int v = 0; v < VD; ++v) acc[v] = 0.0;
     const uint64_t vmask = __ballot(valid);
     int sp = 0;
+    bool overflow = false;
     if (vmask) {
         for (int c = a.nroots - 1; c >= 0; --c)
             if (a.scount[c] > 0) {
@@ -1201,15 +1213,20 @@ __global__ __launch_bounds__(256) void k_treecode(TcArgs a) {
         }
         const uint64_t om = __ballot(op);
         if (om) {
-            for (int q = 3; q >= 0; --q)
-                if (a.scount[c0 + q] > 0 && sp < kTcStack) {
-                    st_node[wv][sp] = c0 + q;
-                    st_lo[wv][sp] = uint32_t(om);
-                    st_hi[wv][sp] = uint32_t(om >> 32);
-                    ++sp;
+            for (int q = 3; q >= 0; --q) {
+                if (a.scount[c0 + q] <= 0) continue;
+                if (sp >= kTcStack) {
+                    overflow = true;
+                    continue;
                 }
+                st_node[wv][sp] = c0 + q;
+                st_lo[wv][sp] = uint32_t(om);
+                st_hi[wv][sp] = uint32_t(om >> 32);
+                ++sp;
+            }
         }
     }
+    if (overflow && lane == 0) *a.status = 1;
     if (valid) {
         double o[VD];
         epilogue<KERN, false>(acc, gx, gy, gz, o);

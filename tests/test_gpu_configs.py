@@ -4,11 +4,20 @@ The oracle computes the direct sum at 4,096 seeded targets against every
 source (and, for the Poisson workload, the oracle FMM at 256 targets); the
 library runs at full size in the launch configuration the benchmark times.
 
-Gates (relative L2 over the sampled targets, Euclidean norm for vectors):
+Gates: relative L2 over the sampled targets (Euclidean norm for vectors) and,
+beside it, the worst relative error of one target floored at the sample RMS
+(`gates.elem_max`), which an error confined to a few targets cannot pass:
   Poisson N=393,216, theta 0.7: FP64 2e-5 (p=6), 1e-6 (p=8), 1e-7 (p=10);
-      FP32 form max(FP64 gate, 2e-6)
-  Biot-Savart N=1,572,864, theta 0.6, p=8, FP32 form: 1e-5
-  1/|x-y| 6,291,456 sources x 1,000,000 random targets, theta 0.6, p=10, FP32 form: 1e-5
+      FP32 form max(FP64 gate, 2e-6); element-wise 10x the FP64 gate, and
+      max(that, 2e-5) in the FP32 form
+  Biot-Savart N=1,572,864, theta 0.6, p=8, FP32 form: 1e-5, element-wise 1e-4
+  1/|x-y| 6,291,456 sources x 1,000,000 random targets, theta 0.6, p=10:
+      FP64 and FP32 form 1e-5, element-wise 1e-4
+The element-wise FP32 allowance comes from the error analysis of the FP32
+form (expanded squared distance within ~1e-4 relative for the closest
+non-close pairs, a few ulps elsewhere): summed over a target's near field it
+stays below ~2e-6 of the field's RMS on these grids, and the rest of the
+allowance is the FMM truncation error's peak over its RMS.
 """
 
 import math
@@ -21,17 +30,13 @@ import paper_2508_13550_amd as cs
 from workloads import make_config, config_subset
 from oracle import direct as odirect
 from oracle import fmm as F
+from gates import rel_l2, elem_max
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
 
 
 def tdev(a):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
-
-
-def rel_l2(a, b):
-    a, b = np.asarray(a), np.asarray(b)
-    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
 
 
 def say(msg):
@@ -51,16 +56,20 @@ def cfg2():
 @pytest.mark.parametrize("p,gate", [(6, 2e-5), (8, 1e-6), (10, 1e-7)])
 def test_config2_poisson_both_forms(cfg2, p, gate):
     c, S, ref = cfg2
-    P, w = c["sources"], c["weights"]
+    P, w, A = c["sources"], c["weights"], c["areas"]
     T, W = tdev(P), tdev(w)
-    for fp32, g in ((False, gate), (True, max(gate, 2e-6))):
+    for fp32, g, ge in ((False, gate, 10 * gate), (True, max(gate, 2e-6), max(10 * gate, 2e-5))):
         say("config 2 p=%d fp32=%s" % (p, fp32))
         pl = cs.Plan(T, None, kernel=1, p=p, theta=c["theta"], leaf_size=c["leaf"], fp32=fp32)
         out = pl.eval(W).cpu().numpy()
+        st = pl.stats()
         pl.close()
-        err = rel_l2(out[S], ref)
-        print("p=%d fp32=%s rel L2 %.3e (gate %.0e)" % (p, fp32, err, g), flush=True)
+        err = rel_l2(out[S], ref, A[S])
+        em = elem_max(out[S], ref)
+        print("p=%d fp32=%s rel L2 %.3e (gate %.0e) elem_max %.3e (gate %.0e) pp_close %d"
+              % (p, fp32, err, g, em, ge, st["pp_close"]), flush=True)
         assert err <= g
+        assert em <= ge
 
 
 def test_config2_matches_oracle_fmm_on_sample(cfg2):
@@ -97,10 +106,12 @@ def test_config3_biot_savart_fp32():
     say("config 3 plan + eval (FP32 form, p=8, theta=0.6)")
     pl = cs.Plan(T, None, kernel=2, p=c["p"], theta=c["theta"], leaf_size=c["leaf"], fp32=True)
     out = pl.eval(tdev(w)).cpu().numpy()
-    err = rel_l2(out[S], ref)
-    print("config 3 rel L2 %.3e" % err, flush=True)
+    err = rel_l2(out[S], ref, A[S])
+    em = elem_max(out[S], ref)
+    print("config 3 rel L2 %.3e elem_max %.3e" % (err, em), flush=True)
     assert out.shape == (P.shape[0], 3)
     assert err <= 1e-5
+    assert em <= 1e-4
     # noise off: the whole-sphere result against u = grad(zeta/20) x x (paper §2.3 + eq. G_L)
     from workloads import real_y41
     w0 = real_y41(P) * A
@@ -112,19 +123,33 @@ def test_config3_biot_savart_fp32():
     assert e < 3e-5   # discretization error at N = 1.57M is ~1.4e-5 (second order)
 
 
-def test_config4_distinct_inverse_distance_fp32():
+@pytest.fixture(scope="module")
+def cfg4():
     say("config 4 inputs (6.3M sources, degree-64 field, 1M targets)")
     c = make_config(4)
     Y, w, X = c["sources"], c["weights"], c["targets"]
     S = config_subset(X.shape[0], 4096, c["subset_seed"])
     say("config 4 oracle direct on 4,096 targets x 6.3M sources")
     ref = odirect(3, X[S], Y, w)
-    say("config 4 plan + eval (FP32 form, p=10, theta=0.6)")
+    return c, S, ref
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_config4_distinct_inverse_distance(cfg4, fp32):
+    """The headline workload in both forms, in the launch configuration the
+    benchmark times (random targets carry area 1 in the metric)."""
+    c, S, ref = cfg4
+    Y, w, X = c["sources"], c["weights"], c["targets"]
+    say("config 4 plan + eval (fp32=%s, p=10, theta=0.6)" % fp32)
     pl = cs.Plan(tdev(X), tdev(Y), kernel=3, p=c["p"], theta=c["theta"], leaf_size=c["leaf"],
-                 fp32=True)
+                 fp32=fp32)
     out = pl.eval(tdev(w)).cpu().numpy()
     st = pl.stats()
     pl.close()
     err = rel_l2(out[S], ref)
-    print("config 4 rel L2 %.3e stats %s" % (err, st), flush=True)
+    em = elem_max(out[S], ref)
+    print("config 4 fp32=%s rel L2 %.3e elem_max %.3e pp_close %d of %d"
+          % (fp32, err, em, st["pp_close"], st["n_pp"]), flush=True)
     assert err <= 1e-5
+    assert em <= 1e-4
+    torch.cuda.empty_cache()

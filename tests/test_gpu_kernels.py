@@ -2,7 +2,7 @@
 the GPU: the Poisson workload's grid (E=256, N=393,216) and field, p=8,
 theta=0.7, leaf 128, both precision forms, checked against the oracle's direct
 sum at 1,024 seeded targets; and the biharmonic eigenrelation
-G_B * Y_n = Y_n/(n^2 (n+1)^2) (§2.4) for a degree-2 harmonic, where the
+G_B * Y_n = Y_n/(n^2 (n+1)^2) (§2.2) for a degree-2 harmonic, where the
 method's error must sit below the grid's own quadrature error.
 
 Gates (relative L2 over the sampled targets): 1e-5 for both forms and both

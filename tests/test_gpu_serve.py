@@ -135,3 +135,50 @@ def test_served_stream_under_tight_budget():
         err = np.sqrt(np.sum((got[S] - ref) ** 2) / np.sum(ref ** 2))
         assert err < 1e-5
     srv.close()
+
+
+def test_served_stream_at_full_request_sizes():
+    """The serving workload's request sizes: E in {16, ..., 512} (N up to
+    1,572,864), all three kernels, p in {6, 8}, 36 requests arriving faster
+    than they are served.  Every result equals, bit for bit, the request
+    evaluated alone on its resident plan; sampled requests of each kernel, the
+    largest among them, match the oracle on 1,024 targets within 1e-5."""
+    from workloads import config_subset
+    from gates import rel_l2
+    say("served stream at full request sizes: 36 requests, E up to 512")
+    n = 36
+    mix = request_mix(n, seed_mix=5006)
+    arr = poisson_arrivals(n, rate=2000.0, seed=5005)
+    free, _ = torch.cuda.mem_get_info()
+    srv = Server(budget_bytes=int(0.5 * free), theta=0.6, leaf=128, fp32=True, max_batch=16)
+    reqs = [Request(id=i, geometry=("grid", E), targets=grid(E)[3], sources=None, kernel=k, p=p,
+                    weights=weights(E, c), t_arrival=float(t))
+            for i, ((E, k, p, c), t) in enumerate(zip(mix, arr))]
+    done = srv.run(reqs)
+    st = srv.sched.stats()
+    print("sched", st, "latency", latency_stats(done), "batches", srv.batch_sizes, flush=True)
+    assert len(done) == n and st["completed"] == n and st["rejected"] == 0
+    assert st["evictions"] == 0
+    from paper_2508_13550_amd.serve import plan_key
+    by_id = {r.id: r for r in done}
+    for r in done:
+        pl = srv.plans[plan_key(r.geometry, r.p, 0.6, 128, True)]
+        alone = pl.eval(r.weights, kernel=r.kernel)
+        assert torch.equal(alone, r.out), r.id
+    # oracle check: for each kernel the largest request, and two more
+    picks = set()
+    for k in (1, 2, 3):
+        ids = [i for i, m in enumerate(mix) if m[1] == k]
+        picks.add(max(ids, key=lambda i: mix[i][0]))
+        picks.add(ids[0])
+    for i in sorted(picks):
+        r = by_id[i]
+        E = r.geometry[1]
+        P = grid(E)[0]
+        S = config_subset(P.shape[0], 1024, 5008)
+        say("oracle check of request %d: E=%d kernel %d p=%d" % (i, E, r.kernel, r.p))
+        ref = odirect(r.kernel, P[S], P, r.weights.cpu().numpy())
+        err = rel_l2(r.out.cpu().numpy()[S], ref)
+        print("request %d E=%d kernel %d p=%d rel L2 %.3e" % (i, E, r.kernel, r.p, err), flush=True)
+        assert err < 1e-5
+    srv.close()

@@ -13,7 +13,7 @@ and the mathematics fix (no GPU).
 * Biot-Savart: K_BS = grad G_L x x (§2.3) gives u = grad(psi) x x;
 * symmetry of the kernels; 50-digit brute force with the literal formulas;
 * biharmonic (eq. G_B): Legendre coefficients 1/(n^2 (n+1)^2) (the
-  eigenvalues of the biharmonic operator, §2.4) and pi^2/6 - 1 for n = 0,
+  eigenvalues of the biharmonic operator, §2.2) and pi^2/6 - 1 for n = 0,
   by Funk-Hecke quadrature of the oracle's kernel; closed-form dilogarithm
   values; second order convergence of the eigenrelation on the grid;
 * SAL (eq. G_SAL_approx): Legendre coefficients (1 - b0) + (a1 - b1)/n of
@@ -292,7 +292,7 @@ def _legendre_coeffs(kernel, nmax):
 
 
 def test_P7_biharmonic_legendre_coefficients():
-    """Delta^2 Y_n = n^2 (n+1)^2 Y_n (§2.4): G_B has coefficients 1/(n^2 (n+1)^2)."""
+    """Delta^2 Y_n = n^2 (n+1)^2 Y_n (§2.2): G_B has coefficients 1/(n^2 (n+1)^2)."""
     lam = _legendre_coeffs(4, 8)
     assert abs(lam[0] - (math.pi ** 2 / 6 - 1)) < 1e-13  # int_0^1 dilog(u) du
     for n in range(1, 9):
