@@ -193,6 +193,23 @@ int csfmm_direct(const double* targets, int64_t n_t, const double* sources, int6
                  void* stream);
 
 /*
+ * csfmm_direct for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops that forbid hipMalloc): the same
+ * arguments, kernels and result, bit for bit, with no hipMalloc, hipFree or
+ * other allocating call.  The partial sums over source splits go to a static
+ * scratch array of 4 Mi doubles (32 MiB) that each GPU the library runs on
+ * holds until the process ends; so n_t is at most 4,194,304 (1,398,101 for
+ * Biot-Savart, three outputs), and larger n_t fails with CSFMM_E_INVALID
+ * before any launch.  Every call on one GPU uses that GPU's one array:
+ * calls that overlap on a GPU (other streams, other host threads) race and
+ * must be ordered by the caller.  The array needs no clearing (every
+ * partial sum is written before it is read).  Asynchronous on `stream`.
+ */
+int csfmm_direct_noalloc(const double* targets, int64_t n_t, const double* sources,
+                         int64_t n_s, const double* weights, int kernel_id, unsigned flags,
+                         double* out, void* stream);
+
+/*
  * Serving: several requests evaluated together (continuous batching).
  * A workspace holds one request's eval buffers (sorted weights, proxy
  * weights, proxy potentials, near field) and the side stream of its PP near

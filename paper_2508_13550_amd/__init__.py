@@ -70,7 +70,7 @@ EXPORTED = (
     "csfmm_plan_proxies", "csfmm_plan_permutation", "csfmm_plan_list", "csfmm_eval_stages",
     "csfmm_plan_timing", "csfmm_plan_timing_read", "csfmm_workspace_create",
     "csfmm_workspace_destroy", "csfmm_workspace_bytes", "csfmm_eval_many",
-    "csfmm_eval_treecode", "csfmm_bve_rk4_step",
+    "csfmm_eval_treecode", "csfmm_bve_rk4_step", "csfmm_direct_noalloc",
 )
 
 STAGES = ("p2m", "m2m", "near_pp", "pc_far", "l2l_l2p")
@@ -96,6 +96,7 @@ def load_library(path=LIB_PATH):
                                      ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_uint,
                                      ctypes.c_int, vp]
     L.csfmm_direct.argtypes = [dp, i64, dp, i64, dp, ctypes.c_int, ctypes.c_uint, dp, vp]
+    L.csfmm_direct_noalloc.argtypes = L.csfmm_direct.argtypes
     L.csfmm_plan_destroy.argtypes = [vp]
     L.csfmm_plan_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.csfmm_estimate_bytes.argtypes = [i64, i64, ctypes.c_int, ctypes.c_int, ctypes.c_uint]
@@ -399,4 +400,22 @@ def direct(targets, sources, weights, kernel=POISSON, fp32=False, out=None):
         out = torch.empty(shape, dtype=torch.float64, device=t.device)
     _check(_lib.csfmm_direct(t.data_ptr(), t.shape[0], s.data_ptr(), s.shape[0], w.data_ptr(),
                              int(kernel), FP32_FORM if fp32 else FP64, out.data_ptr(), _stream()))
+    return out
+
+
+def direct_noalloc(targets, sources, weights, out, kernel=POISSON, fp32=False):
+    """csfmm_direct_noalloc: the direct sum into a caller-provided `out`, with
+    no device allocation by the library (static scratch; calls that overlap
+    on one GPU race)."""
+    _require_gpu()
+    t = _points(targets, "targets")
+    s = _points(sources, "sources")
+    w = _vec(weights, s.shape[0], "weights")
+    shape = (t.shape[0], 3) if int(kernel) == BIOT_SAVART else (t.shape[0],)
+    if (not isinstance(out, torch.Tensor) or out.dtype != torch.float64 or
+            out.device.type != "cuda" or tuple(out.shape) != shape or not out.is_contiguous()):
+        raise ValueError("out must be a contiguous float64 GPU tensor of shape %s" % (shape,))
+    _check(_lib.csfmm_direct_noalloc(t.data_ptr(), t.shape[0], s.data_ptr(), s.shape[0],
+                                     w.data_ptr(), int(kernel), FP32_FORM if fp32 else FP64,
+                                     out.data_ptr(), _stream()))
     return out

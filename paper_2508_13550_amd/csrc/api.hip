@@ -137,8 +137,10 @@ int csfmm_eval_treecode(csfmm_plan_t plan, int kernel_id, const double* weights,
     return run_treecode(plan, kernel_id, weights, out, static_cast<hipStream_t>(stream));
 }
 
-int csfmm_direct(const double* targets, int64_t n_t, const double* sources, int64_t n_s,
-                 const double* weights, int kernel_id, unsigned flags, double* out, void* stream) {
+namespace {
+int direct_entry(const double* targets, int64_t n_t, const double* sources, int64_t n_s,
+                 const double* weights, int kernel_id, unsigned flags, double* out, void* stream,
+                 bool no_alloc) {
     clear_error();
     if (!targets || !sources || !weights || !out || n_t < 1 || n_s < 1) {
         set_error("direct: non-NULL arrays and n_t, n_s >= 1 required");
@@ -153,7 +155,20 @@ int csfmm_direct(const double* targets, int64_t n_t, const double* sources, int6
         return CSFMM_E_INVALID;
     }
     return launch_direct(targets, n_t, sources, n_s, weights, kernel_id,
-                         (flags & CSFMM_FP32_FORM) != 0, out, static_cast<hipStream_t>(stream));
+                         (flags & CSFMM_FP32_FORM) != 0, out, static_cast<hipStream_t>(stream),
+                         no_alloc);
+}
+}  // namespace
+
+int csfmm_direct(const double* targets, int64_t n_t, const double* sources, int64_t n_s,
+                 const double* weights, int kernel_id, unsigned flags, double* out, void* stream) {
+    return direct_entry(targets, n_t, sources, n_s, weights, kernel_id, flags, out, stream, false);
+}
+
+int csfmm_direct_noalloc(const double* targets, int64_t n_t, const double* sources, int64_t n_s,
+                         const double* weights, int kernel_id, unsigned flags, double* out,
+                         void* stream) {
+    return direct_entry(targets, n_t, sources, n_s, weights, kernel_id, flags, out, stream, true);
 }
 
 int csfmm_plan_destroy(csfmm_plan_t plan) {

@@ -354,8 +354,11 @@ struct TcArgs {
     int32_t* status;                  // set to 1 by a wave whose stack overflows
 };
 int launch_treecode(const TcArgs& a, int kernel, hipStream_t s);
+// Partial sums of the direct sum without allocation: 4 Mi doubles (32 MiB)
+// of static device memory per device.
+constexpr int64_t kDirectScratchDoubles = int64_t(1) << 22;
 int launch_direct(const double* tgt, int64_t nt, const double* src, int64_t ns, const double* w,
-                  int kernel, bool fp32, double* out, hipStream_t s);
+                  int kernel, bool fp32, double* out, hipStream_t s, bool no_alloc = false);
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 

@@ -35,6 +35,7 @@
 //             ((1-b0)/2) (1/sqrt(v) + q ln(sqrt(v) + v)), q = -2(a1-b1)/(1-b0).
 // The self term (squared distance exactly 0) contributes nothing.
 #include <atomic>
+#include <mutex>
 #include <type_traits>
 
 #include "common.h"
@@ -1267,29 +1268,65 @@ int launch_tile_t(const Batch& b, hipStream_t s) {
     return CSFMM_OK;
 }
 
-template <int KERN, bool F32>
-int launch_direct_t(const double* tgt, int64_t nt, const double* src, int64_t ns, const double* w,
-                    double* out, hipStream_t s) {
-    constexpr int VD = vdim<KERN>();
+// Source splits of the direct sum: enough (target block, split) blocks to
+// fill the device, at most one split per source chunk.
+int64_t direct_splits(int64_t nt, int64_t ns) {
     const int64_t ntb = (nt + 63) / 64;
     const int64_t maxsplit = (ns + kChunk - 1) / kChunk;
-    int64_t nsplit = (4096 + ntb - 1) / ntb;
-    nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, std::min<int64_t>(maxsplit, 65535)));
+    const int64_t nsplit = (4096 + ntb - 1) / ntb;
+    return std::max<int64_t>(1, std::min<int64_t>(nsplit, std::min<int64_t>(maxsplit, 65535)));
+}
+
+// Partial sums [split][VD][nt] go to `part` when given (it holds at least
+// direct_splits * VD * nt doubles), else to a stream-ordered allocation.
+template <int KERN, bool F32>
+int launch_direct_t(const double* tgt, int64_t nt, const double* src, int64_t ns, const double* w,
+                    double* out, hipStream_t s, double* part) {
+    constexpr int VD = vdim<KERN>();
+    const int64_t ntb = (nt + 63) / 64;
+    const int64_t nsplit = direct_splits(nt, ns);
     const int64_t nsp = (ns + nsplit - 1) / nsplit;
-    double* part = nullptr;
-    CSFMM_HIP_TRY(hipMallocAsync((void**)&part, sizeof(double) * size_t(nsplit * VD * nt), s));
+    const bool own = part == nullptr;
+    if (own)
+        CSFMM_HIP_TRY(hipMallocAsync((void**)&part, sizeof(double) * size_t(nsplit * VD * nt), s));
     k_direct<KERN, F32><<<dim3(unsigned(ntb), unsigned(nsplit)), kThreads, 0, s>>>(tgt, nt, src, ns,
                                                                                   w, nsp, part);
     hipError_t e1 = hipGetLastError();
     k_direct_reduce<KERN, F32><<<unsigned((nt + 255) / 256), 256, 0, s>>>(tgt, nt, part,
                                                                           int(nsplit), out);
     hipError_t e2 = hipGetLastError();
-    (void)hipFreeAsync(part, s);
+    if (own) (void)hipFreeAsync(part, s);
     if (e1 != hipSuccess || e2 != hipSuccess) {
         set_error("direct launch failed: %s",
                   hipGetErrorString(e1 != hipSuccess ? e1 : e2));
         return CSFMM_E_HIP;
     }
+    return CSFMM_OK;
+}
+
+// Scratch of the direct sum for callers that cannot allocate: one array per
+// device, held until the process ends.  Host code uses only the device
+// address that hipGetSymbolAddress returns for the current device (the
+// array's name on the host is a stand-in, not a device address).
+static __device__ __align__(256) double scratch[kDirectScratchDoubles];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64] = {};
+
+int scratch_address(double** out) {
+    int dev = 0;
+    CSFMM_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) {
+        set_error("device %d out of range for the scratch table", dev);
+        return CSFMM_E_HIP;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        CSFMM_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
     return CSFMM_OK;
 }
 
@@ -1352,23 +1389,36 @@ int launch_treecode(const TcArgs& a, int kernel, hipStream_t s) {
 }
 
 int launch_direct(const double* tgt, int64_t nt, const double* src, int64_t ns, const double* w,
-                  int kernel, bool fp32, double* out, hipStream_t s) {
+                  int kernel, bool fp32, double* out, hipStream_t s, bool no_alloc) {
+    double* part = nullptr;
+    if (no_alloc) {
+        const int64_t need = direct_splits(nt, ns) * (kernel == CSFMM_K_BIOT_SAVART ? 3 : 1) * nt;
+        if (need > kDirectScratchDoubles) {
+            set_error("direct without allocation: %lld partial sums exceed the scratch of %lld "
+                      "doubles (at most %lld targets, a third for Biot-Savart)",
+                      (long long)need, (long long)kDirectScratchDoubles,
+                      (long long)kDirectScratchDoubles);
+            return CSFMM_E_INVALID;
+        }
+        int rc = scratch_address(&part);
+        if (rc != CSFMM_OK) return rc;
+    }
     switch (kernel) {
         case CSFMM_K_POISSON_LOG:
-            return fp32 ? launch_direct_t<1, true>(tgt, nt, src, ns, w, out, s)
-                        : launch_direct_t<1, false>(tgt, nt, src, ns, w, out, s);
+            return fp32 ? launch_direct_t<1, true>(tgt, nt, src, ns, w, out, s, part)
+                        : launch_direct_t<1, false>(tgt, nt, src, ns, w, out, s, part);
         case CSFMM_K_BIOT_SAVART:
-            return fp32 ? launch_direct_t<2, true>(tgt, nt, src, ns, w, out, s)
-                        : launch_direct_t<2, false>(tgt, nt, src, ns, w, out, s);
+            return fp32 ? launch_direct_t<2, true>(tgt, nt, src, ns, w, out, s, part)
+                        : launch_direct_t<2, false>(tgt, nt, src, ns, w, out, s, part);
         case CSFMM_K_INV_DIST:
-            return fp32 ? launch_direct_t<3, true>(tgt, nt, src, ns, w, out, s)
-                        : launch_direct_t<3, false>(tgt, nt, src, ns, w, out, s);
+            return fp32 ? launch_direct_t<3, true>(tgt, nt, src, ns, w, out, s, part)
+                        : launch_direct_t<3, false>(tgt, nt, src, ns, w, out, s, part);
         case CSFMM_K_BIHARMONIC:
-            return fp32 ? launch_direct_t<4, true>(tgt, nt, src, ns, w, out, s)
-                        : launch_direct_t<4, false>(tgt, nt, src, ns, w, out, s);
+            return fp32 ? launch_direct_t<4, true>(tgt, nt, src, ns, w, out, s, part)
+                        : launch_direct_t<4, false>(tgt, nt, src, ns, w, out, s, part);
         case CSFMM_K_SAL:
-            return fp32 ? launch_direct_t<5, true>(tgt, nt, src, ns, w, out, s)
-                        : launch_direct_t<5, false>(tgt, nt, src, ns, w, out, s);
+            return fp32 ? launch_direct_t<5, true>(tgt, nt, src, ns, w, out, s, part)
+                        : launch_direct_t<5, false>(tgt, nt, src, ns, w, out, s, part);
         default:
             set_error("unknown kernel id %d", kernel);
             return CSFMM_E_INVALID;
