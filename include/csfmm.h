@@ -104,7 +104,7 @@ typedef struct csfmm_stats {
 /*
  * Build a plan: trees, cell geometry and proxy points, the fixed parent-child
  * interpolation matrices and the PP/PC/CP/CC interaction lists (paper §3, §4,
- * §8 Algorithm 2 lines 4 and 6-18; the lists depend only on the points, p,
+ * §8 Algorithm 2, tree and traversal; the lists depend only on the points, p,
  * theta and N0, not on the weights).
  *
  *   targets   [n_t][3] device, unit vectors; copied into the plan
@@ -124,7 +124,7 @@ int csfmm_plan(const double* targets, int64_t n_t, const double* sources, int64_
                void* stream, csfmm_plan_t* out);
 
 /*
- * Apply a plan to source weights (Algorithm 2 lines 3, 5-21): upward pass
+ * Apply a plan to source weights (§8 Algorithm 2 after the traversal): upward pass
  * (P2M, M2M), interactions (PP, PC, CP, CC), downward pass (L2L, L2P).
  *   weights [n_s] device (for a same-set plan n_s = n_t)
  *   out     [n_t] device, or [n_t][3] for Biot-Savart

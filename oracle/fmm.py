@@ -395,10 +395,10 @@ class FMM:
             if np.any(want[C.idx]):
                 live.add(C.id)
 
-        # Line 5: upward pass on the source tree
+        # Algorithm 2, upward pass on the source tree
         wbar = upward_pass(st, w)
 
-        # Lines 6-19: interactions by list type, grouped by target cluster
+        # Algorithm 2, interactions by list type, grouped by target cluster
         phi = np.zeros((nt, vd))
         psi = {}
         by_t = {}
@@ -431,7 +431,7 @@ class FMM:
 
         near = phi.copy()
 
-        # Line 20: downward pass, eq. (downward_2) through all levels, then
+        # Algorithm 2, downward pass: eq. (downward_2) through all levels, then
         # eq. (downward_1) at the leaves
         for lev in tt.levels:
             for C in lev:
@@ -476,9 +476,9 @@ def point_separated(x, S, theta):
 
 
 def treecode(targets, sources, weights, kernel, n, theta, N0, sample=None):
-    """Cubed sphere treecode (Algorithm 1): the source tree and its upward pass
-    (lines 4-5), then for every target particle a traversal from the six
-    source roots (lines 6-14): PC for separated clusters with more than N0
+    """Cubed sphere treecode (Algorithm 1): the source tree and its upward
+    pass, then for every target particle a traversal from the six source
+    roots: PC for separated clusters with more than N0
     points, PP for separated small clusters and for leaves that are not
     separated, children otherwise.  `kernel` is a kernel id or a function
     (X, Y) -> matrix of kernel values (for tests).  Returns phi at every

@@ -1,4 +1,4 @@
-// Evaluation of plans (paper §8, Algorithm 2 lines 3, 5 and 7-21):
+// Evaluation of plans (paper §8, Algorithm 2 after the traversal):
 //   gather weights -> [PP near field on a side stream] -> P2M (eq. PC proxy
 //   weights of the leaves) -> M2M by levels (eq. upwardpass2, FP64 MFMA) ->
 //   PC near field and CP+CC far field (tile engine) -> join -> per leaf: L2L

@@ -66,6 +66,23 @@ constexpr double coord_scale() {
 }
 
 __device__ __forceinline__ float dev_log2(float x) { return __builtin_amdgcn_logf(x); }
+
+// FP64 1/sqrt(x) for finite x > 0: the hardware estimate (relative error about
+// 5e-8, measured) and one third-order correction y (1 + e/2 + 3e^2/8),
+// e = 1 - x y^2, which leaves about 1 ulp (measured 1.1e-16).  No special
+// values: x = 0 gives a NaN, which the callers' zero test masks.
+__device__ __forceinline__ double rsq64(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+// FP64 1/x for finite x != 0: the hardware estimate and one third-order
+// correction y (1 + e + e^2), e = 1 - x y.
+__device__ __forceinline__ double rcp64(double x) {
+    const double y = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, y, 1.0);
+    return fma(y, fma(e, e, e), y);
+}
 __device__ __forceinline__ float dev_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float dev_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
@@ -118,7 +135,7 @@ constexpr double kSalScale = 3.0 * kSalRho / (4.0 * kPi) * 0.5 * (1.0 - kSalB0);
 
 // 1/sqrt(v) + q ln(sqrt(v) + v) for v = |x-y|^2/4 > 0
 __device__ __forceinline__ double sal_bracket(double v) {
-    const double rs = rsqrt(v);
+    const double rs = rsq64(v);
     return fma(kSalQ, log(fma(v, rs, v)), rs);
 }
 __device__ __forceinline__ float sal_bracket(float v) {
@@ -145,6 +162,7 @@ enum { FORM_CHECK = 0, FORM_NEAR = 1, FORM_FAR = 2, FORM_EXACT = 3 };
 
 struct TargetRegs {
     double tx, ty, tz;          // FP64 form
+    double d2, dmx, dmy, dmz;   // FP64 form: |t|^2 and -2 t (FORM_FAR)
     float fx, fy, fz, f2;       // FP32 form: recentred target and |t|^2
     float mx, my, mz;           // -2 t
 };
@@ -155,6 +173,10 @@ __device__ __forceinline__ TargetRegs target_regs(double dx, double dy, double d
     TR.tx = dx * scale;
     TR.ty = dy * scale;
     TR.tz = dz * scale;
+    TR.d2 = TR.tx * TR.tx + TR.ty * TR.ty + TR.tz * TR.tz;
+    TR.dmx = -2.0 * TR.tx;
+    TR.dmy = -2.0 * TR.ty;
+    TR.dmz = -2.0 * TR.tz;
     TR.fx = float(TR.tx);
     TR.fy = float(TR.ty);
     TR.fz = float(TR.tz);
@@ -169,6 +191,13 @@ __device__ __forceinline__ TargetRegs target_regs(double dx, double dy, double d
 __device__ __forceinline__ float expanded_d2(const TargetRegs& T, float sx, float sy, float sz,
                                              float s2) {
     return fmaf(T.mx, sx, fmaf(T.my, sy, fmaf(T.mz, sz, s2 + T.f2)));
+}
+// FP64 expanded squared distance, MAC-separated pairs only (FORM_FAR): the MAC
+// bounds (|t|^2 + |s|^2)/|t-s|^2 by (1 + (1 + 2 theta/(1 - theta))^2)/2 (8.5 at
+// theta 0.6, 16.6 at 0.7), so it keeps FP64 accuracy within a few ulps.
+__device__ __forceinline__ double expanded_d2(const TargetRegs& T, double sx, double sy,
+                                              double sz, double s2) {
+    return fma(T.dmx, sx, fma(T.dmy, sy, fma(T.dmz, sz, s2 + T.d2)));
 }
 
 // Unscaled value of a scalar kernel at scaled squared distance d (FP32 form):
@@ -198,8 +227,21 @@ __device__ __forceinline__ void eval_pair(const TargetRegs& T, Real<F32> sx, Rea
     }
     constexpr bool expanded =
         F32 && (FORM == FORM_NEAR || FORM == FORM_FAR) && KERN != CSFMM_K_BIOT_SAVART;
+    constexpr bool expanded64 = !F32 && FORM == FORM_FAR && KERN != CSFMM_K_BIOT_SAVART;
     if constexpr (expanded) {
         p[0] = fmaf(w, kernel_value_f32<KERN>(expanded_d2(T, sx, sy, sz, s2)), p[0]);
+    } else if constexpr (expanded64) {
+        const double d = expanded_d2(T, double(sx), double(sy), double(sz), double(s2));
+        double g;
+        if constexpr (KERN == CSFMM_K_POISSON_LOG)
+            g = log(d);
+        else if constexpr (KERN == CSFMM_K_BIHARMONIC)
+            g = dilog_1m(d);
+        else if constexpr (KERN == CSFMM_K_SAL)
+            g = sal_bracket(d);
+        else
+            g = rsq64(d);
+        p[0] = fma(double(w), g, p[0]);
     } else {
         (void)s2;
         const R dx = sx - tx, dy = sy - ty, dz = sz - tz;
@@ -217,7 +259,7 @@ __device__ __forceinline__ void eval_pair(const TargetRegs& T, Real<F32> sx, Rea
             if constexpr (F32)
                 inv = dev_rcp(r2);
             else
-                inv = R(1) / r2;
+                inv = rcp64(r2);
             R f = w * inv;
             if constexpr (FORM == FORM_CHECK || FORM == FORM_EXACT) f = r2 > R(0) ? f : R(0);
             p[0] = fma(dx, f, p[0]);
@@ -236,7 +278,7 @@ __device__ __forceinline__ void eval_pair(const TargetRegs& T, Real<F32> sx, Rea
             if constexpr (F32)
                 inv = dev_rsq(r2);
             else
-                inv = rsqrt(r2);
+                inv = rsq64(r2);
             if constexpr (FORM == FORM_CHECK || FORM == FORM_EXACT) inv = r2 > R(0) ? inv : R(0);
             p[0] = fma(w, inv, p[0]);
         }
@@ -323,14 +365,21 @@ constexpr int kMaxG = 32;   // source groups per target
 constexpr int kUnroll = 4;  // one staged group of four sources per unrolled step
 static_assert(kUnroll == 4, "Stage<true> packs sources in groups of four");
 // Sources staged per step of the tile kernel.  The staging buffer (20 bytes a
-// source in the FP32 form) and the block's other LDS arrays fit six blocks of
-// four waves in a CU's 160 KB, the occupancy the FP32 instances run at.
-constexpr int kTileChunk = 1024;
-constexpr int kLds = kTileChunk + kUnroll * kMaxG;
+// source in the FP32 form, 40 in FP64) and the block's other LDS arrays fit
+// six blocks of four waves in a CU's 160 KB in the FP32 form and four in FP64,
+// the occupancies the instances run at.
+template <bool F32>
+constexpr int tile_chunk() {
+    return F32 ? 1024 : 768;
+}
+template <bool F32>
+constexpr int lds_sources() {
+    return tile_chunk<F32>() + kUnroll * kMaxG;
+}
 
-// Staged sources, recentred at the target cell, for CAP sources.  FP32 form:
-// groups of four sources, (x, y, z, |s|^2) each and then the four weights, so
-// that one LDS address serves a whole unrolled step; FP64 form: (x, y, z, w).
+// Staged sources, recentred at the target cell, for CAP sources: groups of
+// four sources, (x, y, z, |s|^2) each and then the four weights, so that one
+// LDS address serves a whole unrolled step (FP32 or FP64 values).
 template <bool F32, int CAP>
 struct StageT;
 template <int CAP>
@@ -350,20 +399,29 @@ struct StageT<true, CAP> {
 };
 template <int CAP>
 struct StageT<false, CAP> {
-    struct Quad;
-    double4 p[CAP];
+    static_assert(CAP % 4 == 0, "groups of four");
+    struct Quad {
+        double4 p[4];
+        double4 w;
+    };
+    Quad b[CAP / 4];
     __device__ __forceinline__ void put(int q, double x, double y, double z, double w) {
-        p[q] = make_double4(x, y, z, w);
+        b[q >> 2].p[q & 3] = make_double4(x, y, z, x * x + y * y + z * z);
+        reinterpret_cast<double*>(&b[q >> 2].w)[q & 3] = w;
     }
 };
 template <bool F32>
-using Stage = StageT<F32, kLds>;
+using Stage = StageT<F32, lds_sources<F32>()>;
 
-// One-wave-per-leaf path: each wave stages up to kWaveChunk sources of its
-// own leaf at a time (padded to a multiple of four).
-constexpr int kWaveChunk = 256;
+// One-wave-per-leaf path: each wave stages up to wave_items items of at most
+// 64 sources at a time (padded to a multiple of four): four in the FP32
+// form, three in FP64 (whose stage holds twice the bytes per source).
 template <bool F32>
-using WaveStage = StageT<F32, kWaveChunk + kUnroll>;
+constexpr int wave_items() {
+    return F32 ? 4 : 3;
+}
+template <bool F32>
+using WaveStage = StageT<F32, 64 * wave_items<F32>() + kUnroll>;
 
 // Sources per group when nq staged sources are split over G groups, a multiple
 // of the unroll (the tail is padded with weightless sources).
@@ -377,24 +435,15 @@ __device__ __forceinline__ void run_group(const StageT<F32, CAP>& L, int base, i
     // nj is the same for every thread of the block: a scalar trip count keeps
     // the loop control off the vector unit
     nj = __builtin_amdgcn_readfirstlane(nj);
-    [[maybe_unused]] const typename StageT<F32, CAP>::Quad* Qp = nullptr;
-    if constexpr (F32) Qp = &L.b[base >> 2];  // base is a multiple of four
+    const typename StageT<F32, CAP>::Quad* Qp = &L.b[base >> 2];  // base: a multiple of four
     for (int j = 0; j < nj; j += kUnroll) {
-        if constexpr (F32) {
-            const auto& Q = *Qp++;
-            const float4 w4 = Q.w;
-            const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
+        const auto& Q = *Qp++;
+        const auto w4 = Q.w;
+        const Real<F32> ws[4] = {w4.x, w4.y, w4.z, w4.w};
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const float4 s = Q.p[u];
-                eval_pair<KERN, true, FORM>(T, s.x, s.y, s.z, s.w, ws[u], p);
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const double4 s = L.p[base + j + u];
-                eval_pair<KERN, false, FORM>(T, s.x, s.y, s.z, 0.0, s.w, p);
-            }
+        for (int u = 0; u < kUnroll; ++u) {
+            const auto s = Q.p[u];
+            eval_pair<KERN, F32, FORM>(T, s.x, s.y, s.z, s.w, ws[u], p);
         }
     }
 }
@@ -501,6 +550,7 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
         const int G = min(kThreads / TC, kMaxG);
         const int t = tid % TC, g = tid / TC;
         const bool active = g < G;
+        constexpr int kTileChunk = tile_chunk<F32>();
         const int Tj_full = group_len(kTileChunk, G);
         double gx = cx, gy = cy, gz = cz;
         if (active) {
@@ -750,7 +800,7 @@ __device__ __forceinline__ void sym_pairs(const TileArgs& a, const ReqView& V, i
 // holds target t and sums over every source, so no cross-wave reduction and no
 // block barrier.  The entries are taken in list order, split into the same
 // three forms as tile_body (overlapping PP entries, the other PP entries, PC
-// entries), and staged up to kWaveChunk sources at a time.
+// entries), and staged up to wave_items x 64 sources at a time.
 template <int KERN, bool F32>
 __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int leaf, bool sym,
                                                char* lds) {
@@ -797,12 +847,13 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
         int cb = e_beg - 64, c_code = 0, c_size = 0;
         int e = e_beg, off = 0;  // next entry and its sources already staged
         while (e < e_end) {
-            // Up to four items of at most 64 sources (the rest of an entry or its
-            // next 64) per step: every lane issues the loads of its point of all
-            // items before the first store, one memory latency per step.
-            int it_code[4], it_off[4], it_cnt[4];
+            // Up to kItems items of at most 64 sources (the rest of an entry or
+            // its next 64) per step: every lane issues the loads of its point of
+            // all items before the first store, one memory latency per step.
+            constexpr int kItems = wave_items<F32>();
+            int it_code[kItems], it_off[kItems], it_cnt[kItems];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < kItems; ++k) {
                 it_code[k] = 0;
                 it_off[k] = 0;
                 it_cnt[k] = 0;
@@ -837,15 +888,15 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
             }
             // every lane loads (lanes past an item's end repeat its last point), so
             // the loads need no per-lane branches
-            double yx[4], yy[4], yz[4], yw[4];
+            double yx[kItems], yy[kItems], yz[kItems], yw[kItems];
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
+            for (int k = 0; k < kItems; ++k)
                 if (it_cnt[k] > 0)
                     load_source(a, it_code[k], it_off[k] + min(lane, it_cnt[k] - 1), yx[k],
                                 yy[k], yz[k], yw[k]);
             int n = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < kItems; ++k) {
                 if (lane < it_cnt[k])
                     L.put(n + lane, (yx[k] - cx) * scale, (yy[k] - cy) * scale,
                           (yz[k] - cz) * scale, yw[k]);
@@ -1200,8 +1251,8 @@ __global__ __launch_bounds__(256) void k_treecode(TcArgs a) {
             const double* pw = a.swbar + int64_t(c) * a.KS;
             for (int k = 0; k < a.K; ++k) {
                 if (pc)
-                    eval_pair<KERN, false, FORM_FAR>(T, px[k] * scale, px[a.KS + k] * scale,
-                                                     px[2 * a.KS + k] * scale, 0.0, pw[k], acc);
+                    eval_pair<KERN, false, FORM_NEAR>(T, px[k] * scale, px[a.KS + k] * scale,
+                                                      px[2 * a.KS + k] * scale, 0.0, pw[k], acc);
             }
         }
         if (__ballot(pp)) {
