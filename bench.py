@@ -26,6 +26,7 @@ import argparse
 import json
 import os
 import platform
+import re
 import subprocess
 import sys
 import time
@@ -790,6 +791,8 @@ def fold_counters(args):
     fetch, write = load("FETCH_SIZE"), load("WRITE_SIZE")
     cf, cw = load("FETCH_SIZE_copy"), load("WRITE_SIZE_copy")
     sq = load("SQ")
+    for k, v in load("SQ2").items():
+        sq.setdefault(k, {}).update({n: x for n, x in v.items() if n != "dispatches"})
     ck = [k for k in cf if "copyBuffer" in k[0]]
     copy_bytes = 256 * 1024 * 1024
     ffac = copy_bytes / (cf[ck[0]]["FETCH_SIZE"] * 1024.0)
@@ -797,7 +800,7 @@ def fold_counters(args):
     disp = []
     for key in sorted(fetch, key=lambda k: -fetch[k]["FETCH_SIZE"]):
         name, grid = key
-        if not name.startswith(("k_tile", "k_sym_merge")):
+        if not re.search(r"::(k_tile|k_sym_merge)", name):
             continue
         fk, wk = fetch[key]["FETCH_SIZE"], write.get(key, {}).get("WRITE_SIZE", float("nan"))
         disp.append({"kernel": name, "grid_size": grid, "dispatches": fetch[key]["dispatches"],
@@ -805,10 +808,16 @@ def fold_counters(args):
                      "traffic_bytes": fk * 1024.0 * ffac + wk * 1024.0 * wfac,
                      "sq": {k: v for k, v in sq.get(key, {}).items() if k.startswith("SQ_")},
                      "pp": False})
+    # the PP launch: k_tile_wave and k_sym_merge always; of a k_tile kernel
+    # seen at two grid sizes, the smaller (target leaves only; the PC + far
+    # launch adds the far-field target cells)
+    for x in disp:
+        sizes = [y["grid_size"] for y in disp if y["kernel"] == x["kernel"]]
+        x["pp"] = (not re.search(r"::k_tile<", x["kernel"]) or
+                   (len(sizes) > 1 and x["grid_size"] == min(sizes)))
     rec = {"record": args.record, "tile_hip_sha256": source_sha(),
            "copy_calibration": {"bytes": copy_bytes, "fetch_factor": ffac, "write_factor": wfac},
-           "dispatches": disp,
-           "note": "mark the PP launch's rows with pp = true (grid size = its work-items)"}
+           "dispatches": disp}
     path = os.path.join(ROOT, "profiles", args.record)
     json.dump(rec, open(path, "w"), indent=1)
     print(json.dumps(rec))
