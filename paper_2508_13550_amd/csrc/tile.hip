@@ -429,9 +429,12 @@ __device__ __forceinline__ int group_len(int nq, int G) {
     return (((nq + G - 1) / G) + kUnroll - 1) / kUnroll * kUnroll;
 }
 
-template <int KERN, bool F32, int FORM, int CAP>
+// Sources base .. base + nj of a stage against TPT targets of one thread
+// (each staged source read once serves all of them).
+template <int KERN, bool F32, int FORM, int CAP, int TPT>
 __device__ __forceinline__ void run_group(const StageT<F32, CAP>& L, int base, int nj,
-                                          const TargetRegs& T, Real<F32>* p) {
+                                          const TargetRegs (&T)[TPT],
+                                          Real<F32> (&p)[TPT][vdim<KERN>()]) {
     // nj is the same for every thread of the block: a scalar trip count keeps
     // the loop control off the vector unit
     nj = __builtin_amdgcn_readfirstlane(nj);
@@ -443,9 +446,22 @@ __device__ __forceinline__ void run_group(const StageT<F32, CAP>& L, int base, i
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const auto s = Q.p[u];
-            eval_pair<KERN, F32, FORM>(T, s.x, s.y, s.z, s.w, ws[u], p);
+#pragma unroll
+            for (int q = 0; q < TPT; ++q)
+                eval_pair<KERN, F32, FORM>(T[q], s.x, s.y, s.z, s.w, ws[u], p[q]);
         }
     }
+}
+template <int KERN, bool F32, int FORM, int CAP>
+__device__ __forceinline__ void run_group(const StageT<F32, CAP>& L, int base, int nj,
+                                          const TargetRegs& T, Real<F32>* p) {
+    const TargetRegs T1[1] = {T};
+    Real<F32> p1[1][vdim<KERN>()];
+#pragma unroll
+    for (int v = 0; v < vdim<KERN>(); ++v) p1[0][v] = p[v];
+    run_group<KERN, F32, FORM, CAP, 1>(L, base, nj, T1, p1);
+#pragma unroll
+    for (int v = 0; v < vdim<KERN>(); ++v) p[v] = p1[0][v];
 }
 
 // Element i of a global array read through the global address space (a load
@@ -509,7 +525,7 @@ struct TileSmem {
     int e_pref[kMaxEntries + 1];
     int lw[4];
     // the per-target reduction over source groups reuses the staging buffer
-    static_assert(sizeof(Stage<F32>) >= sizeof(double) * vdim<KERN>() * kThreads, "red");
+    static_assert(sizeof(Stage<F32>) >= sizeof(double) * 2 * vdim<KERN>() * kThreads, "red");
     __device__ __forceinline__ double (*red())[kThreads] {
         return reinterpret_cast<double (*)[kThreads]>(&L[0]);
     }
@@ -545,30 +561,44 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
     const int ph_hi[4] = {TPROX ? 0 : nov, TPROX ? 0 : nov + ncl, TPROX ? 0 : nea, nea + neb};
     const int ne_all = nea + neb;
 
-    for (int t0 = 0; t0 < nT; t0 += kThreads) {
-        const int TC = min(nT - t0, kThreads);
+    // FP64 instances give each thread two targets (t and t + TC), so that a
+    // block's threads split a leaf of any size evenly over source groups and
+    // each staged source read serves two evaluations
+    constexpr int TPT = F32 ? 1 : 2;
+    for (int t0 = 0; t0 < nT; t0 += TPT * kThreads) {
+        const int TC = min((nT - t0 + TPT - 1) / TPT, kThreads);
         const int G = min(kThreads / TC, kMaxG);
         const int t = tid % TC, g = tid / TC;
         const bool active = g < G;
         constexpr int kTileChunk = tile_chunk<F32>();
         const int Tj_full = group_len(kTileChunk, G);
-        double gx = cx, gy = cy, gz = cz;
-        if (active) {
-            if constexpr (TPROX) {
-                const double* pc = a.tprox + int64_t(T) * 3 * KS;
-                gx = pc[t0 + t];
-                gy = pc[KS + t0 + t];
-                gz = pc[2 * KS + t0 + t];
-            } else {
-                gx = a.tx[tb + t0 + t];
-                gy = a.ty[tb + t0 + t];
-                gz = a.tz[tb + t0 + t];
-            }
-        }
-        const TargetRegs TR = target_regs(gx - cx, gy - cy, gz - cz, scale);
-        double acc[VD];
+        double gx[TPT], gy[TPT], gz[TPT];
+        TargetRegs TR[TPT];
 #pragma unroll
-        for (int v = 0; v < VD; ++v) acc[v] = 0.0;
+        for (int q = 0; q < TPT; ++q) {
+            const int it = t0 + t + q * TC;  // this thread's q-th target
+            gx[q] = cx;
+            gy[q] = cy;
+            gz[q] = cz;
+            if (active && it < nT) {
+                if constexpr (TPROX) {
+                    const double* pc = a.tprox + int64_t(T) * 3 * KS;
+                    gx[q] = pc[it];
+                    gy[q] = pc[KS + it];
+                    gz[q] = pc[2 * KS + it];
+                } else {
+                    gx[q] = a.tx[tb + it];
+                    gy[q] = a.ty[tb + it];
+                    gz[q] = a.tz[tb + it];
+                }
+            }
+            TR[q] = target_regs(gx[q] - cx, gy[q] - cy, gz[q] - cz, scale);
+        }
+        double acc[TPT][VD];
+#pragma unroll
+        for (int q = 0; q < TPT; ++q)
+#pragma unroll
+            for (int v = 0; v < VD; ++v) acc[q][v] = 0.0;
 
         // Entries are processed in batches of up to kMaxEntries; inside a batch
         // the flattened sources split into the three forms (check, near, far)
@@ -632,38 +662,50 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
                     }
                     __syncthreads();
                     if (active) {
-                        R p[VD];
+                        R p[TPT][VD];
 #pragma unroll
-                        for (int v = 0; v < VD; ++v) p[v] = R(0);
+                        for (int q = 0; q < TPT; ++q)
+#pragma unroll
+                            for (int v = 0; v < VD; ++v) p[q][v] = R(0);
+                        constexpr int CAP = lds_sources<F32>();
                         if (ph == 0)
-                            run_group<KERN, F32, FORM_CHECK>(Lb, g * Tj, Tj, TR, p);
+                            run_group<KERN, F32, FORM_CHECK, CAP, TPT>(Lb, g * Tj, Tj, TR, p);
                         else if (ph == 1)
-                            run_group<KERN, F32, FORM_EXACT>(Lb, g * Tj, Tj, TR, p);
+                            run_group<KERN, F32, FORM_EXACT, CAP, TPT>(Lb, g * Tj, Tj, TR, p);
                         else if (ph == 2)
-                            run_group<KERN, F32, FORM_NEAR>(Lb, g * Tj, Tj, TR, p);
+                            run_group<KERN, F32, FORM_NEAR, CAP, TPT>(Lb, g * Tj, Tj, TR, p);
                         else
-                            run_group<KERN, F32, FORM_FAR>(Lb, g * Tj, Tj, TR, p);
+                            run_group<KERN, F32, FORM_FAR, CAP, TPT>(Lb, g * Tj, Tj, TR, p);
 #pragma unroll
-                        for (int v = 0; v < VD; ++v) acc[v] += double(p[v]);
+                        for (int q = 0; q < TPT; ++q)
+#pragma unroll
+                            for (int v = 0; v < VD; ++v) acc[q][v] += double(p[q][v]);
                     }
                     __syncthreads();
                 }
             }
         }
 #pragma unroll
-        for (int v = 0; v < VD; ++v) red[v][tid] = active ? acc[v] : 0.0;
+        for (int q = 0; q < TPT; ++q)
+#pragma unroll
+            for (int v = 0; v < VD; ++v) red[q * VD + v][tid] = active ? acc[q][v] : 0.0;
         __syncthreads();
         if (tid < TC) {
-            double r[VD], o[VD];
 #pragma unroll
-            for (int v = 0; v < VD; ++v) {
-                r[v] = 0.0;
-                for (int gg = 0; gg < G; ++gg) r[v] += red[v][gg * TC + tid];
+            for (int q = 0; q < TPT; ++q) {
+                const int it = t0 + tid + q * TC;
+                if (it >= nT) continue;
+                double r[VD], o[VD];
+#pragma unroll
+                for (int v = 0; v < VD; ++v) {
+                    r[v] = 0.0;
+                    for (int gg = 0; gg < G; ++gg) r[v] += red[q * VD + v][gg * TC + tid];
+                }
+                epilogue<KERN, F32>(r, gx[q], gy[q], gz[q], o);
+                const int64_t base = TPROX ? int64_t(T) * KS + it : int64_t(tb) + it;
+#pragma unroll
+                for (int v = 0; v < VD; ++v) a.out[v * a.comp_stride + base] = o[v];
             }
-            epilogue<KERN, F32>(r, gx, gy, gz, o);
-            const int64_t base = TPROX ? int64_t(T) * KS + t0 + tid : int64_t(tb) + t0 + tid;
-#pragma unroll
-            for (int v = 0; v < VD; ++v) a.out[v * a.comp_stride + base] = o[v];
         }
         __syncthreads();
     }
@@ -944,7 +986,7 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
 // instances at 80 VGPRs (6 waves per SIMD; measured faster than 5); the FP64
 // instances, whose transcendentals are longer, get 4 waves per SIMD.
 template <int KERN, bool F32>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 4))) void k_tile(Batch b) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 3))) void k_tile(Batch b) {
     __shared__ TileSmem<KERN, F32> sm;
     bool far;
     const int blk = xcd_split_block(blockIdx.x, gridDim.x, b.prefix2[b.n], far);
