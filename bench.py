@@ -68,6 +68,7 @@ def parse():
     ap.add_argument("--serve", action="store_true", help="serving stream instead (2,000 requests)")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rho", type=float, nargs="*", default=[0.5, 0.8])
+    ap.add_argument("--streams", type=int, default=3, help="serving: compute streams")
     ap.add_argument("--sweep", action="store_true",
                     help="runtime vs error over degree, MAC, leaf size and form (Fig. 7 analogue)")
     ap.add_argument("--sweep-E", type=int, default=330)
@@ -562,7 +563,8 @@ def serve_bench(args):
     results = []
     samples = config_subset(n, 50, 5007)
     for rho in args.rho:
-        srv = Server(budget_bytes=budget, theta=theta, leaf=leaf, fp32=True, max_batch=32)
+        srv = Server(budget_bytes=budget, theta=theta, leaf=leaf, fp32=True, max_batch=32,
+                     n_streams=args.streams)
         # warm the plan cache: one request per (E, p)
         warm, seen = [], set()
         for i, (E, k, p, c) in enumerate(mix):
@@ -582,6 +584,12 @@ def serve_bench(args):
         makespan = time.perf_counter() - t0
         st = srv.sched.stats()
         lat = latency_stats(done)
+        by_e = {}
+        for E in E_CHOICES:
+            sel = [r for r in done if r.geometry[1] == E]
+            if sel:
+                by_e[str(E)] = dict(latency_stats(sel),
+                                    solo_ms=float(np.mean([solo[(E, r.kernel, r.p)] for r in sel])) * 1e3)
         # accuracy and alone-vs-mix identity on 50 sampled requests
         by_id = {r.id: r for r in done}
         worst, same = 0.0, True
@@ -604,10 +612,13 @@ def serve_bench(args):
                         "throughput_n2eq_per_s": n2 / makespan,
                         "mean_batch": float(np.mean(srv.batch_sizes)),
                         "max_batch": int(max(srv.batch_sizes)),
+                        "max_concurrent_batches": srv.max_concurrent,
+                        "latency_by_E": by_e, "host_s": srv.host_s,
+                        "p99_over_mean_service": lat["p99_ms"] / (mean_service * 1e3),
                         "sched": st, "sample_max_rel_l2": worst, "alone_equals_mix": same})
         srv.close()
     line = {"metric": "serving: p50/p99 latency and throughput of a CSFMM request stream",
-            "n_requests": n, "capacity_req_per_s": capacity, "mean_solo_service_ms":
+            "n_requests": n, "streams": args.streams, "capacity_req_per_s": capacity, "mean_solo_service_ms":
             mean_service * 1e3, "budget_bytes": budget, "theta": theta, "leaf": leaf,
             "form": "fp32", "n_gpus": 1, "data": "synthetic",
             "config": {"workload": "2,000 requests, E in {16..512} (N 1,536..1,572,864), "

@@ -233,6 +233,7 @@ int csfmm_workspace_create(csfmm_plan_t plan, void* stream, csfmm_workspace_t* o
                                                         /* waits for `stream` */
 int csfmm_workspace_destroy(csfmm_workspace_t ws);     /* waits for the device; NULL is OK */
 int64_t csfmm_workspace_bytes(csfmm_plan_t plan);       /* device bytes of one workspace */
+int64_t csfmm_workspace_device_bytes(csfmm_workspace_t ws); /* bytes this workspace holds */
 int csfmm_eval_many(int n_req, const csfmm_plan_t* plans, const csfmm_workspace_t* workspaces,
                     const int* kernel_ids, const double* const* weights, double* const* outs,
                     void* stream);
@@ -240,10 +241,13 @@ int csfmm_eval_many(int n_req, const csfmm_plan_t* plans, const csfmm_workspace_
 /*
  * Continuous-batching scheduler (host only; it decides, the caller executes).
  * Requests are submitted with a plan key (equal keys share one resident plan),
- * the device bytes of that plan and of one workspace (csfmm_workspace_bytes).
- * csfmm_sched_step(now) admits waiting requests with t_arrival <= now in
- * arrival order into one batch of at most max_batch while their memory fits
- * the budget, and reports what the caller must do before launching it:
+ * the device bytes of that plan and of one workspace (csfmm_workspace_bytes)
+ * and a cost estimate (>= 0, any unit, e.g. points).  csfmm_sched_step(now)
+ * starts one batch of at most max_batch with the oldest waiting request
+ * (t_arrival <= now) and adds, in arrival order, waiting requests whose cost
+ * is within a factor 4 of its cost while their memory fits the budget
+ * (others wait for a later batch, which the caller may run on another stream
+ * beside this one), and reports what the caller must do before launching it:
  *   evict_keys  destroy these resident plans and their workspaces (idle, LRU)
  *   build_keys  build these plans
  *   new_ws_keys create one more workspace for each listed plan key
@@ -251,8 +255,9 @@ int csfmm_eval_many(int n_req, const csfmm_plan_t* plans, const csfmm_workspace_
  *   reject_ids  these requests can never fit the budget
  * A resident plan keeps a pool of workspaces as large as its peak number of
  * requests in flight; csfmm_sched_complete returns one to the pool. The oldest
- * waiting request is never overtaken. Every array is caller owned; cap_* is
- * its room (new_ws_keys has room for cap_launch).
+ * waiting request starts every batch, and within a cost class no request
+ * overtakes an older one. Every array is caller owned; cap_* is its room
+ * (new_ws_keys has room for cap_launch).
  */
 typedef struct csfmm_sched_s* csfmm_sched_t;
 typedef struct csfmm_sched_decision {
@@ -270,7 +275,7 @@ typedef struct csfmm_sched_stats {
 int csfmm_sched_create(int64_t hbm_budget_bytes, int max_batch, csfmm_sched_t* out);
 int csfmm_sched_destroy(csfmm_sched_t s);
 int csfmm_sched_submit(csfmm_sched_t s, int64_t req_id, uint64_t plan_key, int64_t plan_bytes,
-                       int64_t ws_bytes, double t_arrival);
+                       int64_t ws_bytes, double t_arrival, double cost);
 int csfmm_sched_step(csfmm_sched_t s, double now, csfmm_sched_decision* d);
 int csfmm_sched_complete(csfmm_sched_t s, int64_t req_id, double now);
 int csfmm_sched_get_stats(csfmm_sched_t s, csfmm_sched_stats* out);

@@ -71,6 +71,7 @@ EXPORTED = (
     "csfmm_plan_timing", "csfmm_plan_timing_read", "csfmm_workspace_create",
     "csfmm_workspace_destroy", "csfmm_workspace_bytes", "csfmm_eval_many",
     "csfmm_eval_treecode", "csfmm_bve_rk4_step", "csfmm_direct_noalloc",
+    "csfmm_workspace_device_bytes",
 )
 
 STAGES = ("p2m", "m2m", "near_pp", "pc_far", "l2l_l2p")
@@ -111,13 +112,16 @@ def load_library(path=LIB_PATH):
     L.csfmm_workspace_destroy.argtypes = [vp]
     L.csfmm_workspace_bytes.argtypes = [vp]
     L.csfmm_workspace_bytes.restype = ctypes.c_int64
+    L.csfmm_workspace_device_bytes.argtypes = [vp]
+    L.csfmm_workspace_device_bytes.restype = ctypes.c_int64
     L.csfmm_eval_many.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp),
                                   ctypes.POINTER(vp), vp]
     L.csfmm_plan_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTED:
         f = getattr(L, name)
-        if name not in ("csfmm_estimate_bytes", "csfmm_last_error", "csfmm_workspace_bytes"):
+        if name not in ("csfmm_estimate_bytes", "csfmm_last_error", "csfmm_workspace_bytes",
+                        "csfmm_workspace_device_bytes"):
             f.restype = ctypes.c_int
     _lib = L
     return L
@@ -321,6 +325,11 @@ class Workspace:
         if self._h is None:
             raise RuntimeError("workspace was destroyed")
         return self._h
+
+    @property
+    def device_bytes(self):
+        """Device bytes this workspace holds."""
+        return int(_lib.csfmm_workspace_device_bytes(self.handle))
 
     def close(self):
         if getattr(self, "_h", None) is not None and _lib is not None:

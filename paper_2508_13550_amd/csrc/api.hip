@@ -231,6 +231,8 @@ int64_t csfmm_estimate_bytes(int64_t n_t, int64_t n_s, int p, int leaf_size, uns
     b += (ct + cs) * (7 * 4 + 4 * 8 + 3 * KS * 8);  // cell arrays, geometry, proxies
     b += cs * KS * 8 + 3 * ct * KS * 8;          // proxy weights, proxy potentials
     b += 4 * (ct + 1) * 4 * 4 + ct * 4 * 160;    // list offsets and entries (~40 per cell per kind)
+    b += (ct + cs) * 8 + ct * 2 * 4;             // leaf gaps, PP heads (overlapping, close)
+    if (flags & CSFMM_FP32_FORM) b += ct * 4 * (3 + 64);  // symmetric PP split of same-set plans
     b += 8 * KS * round_up(4 * KS, 16) * 8;      // interpolation operators
     return b;
 }
@@ -252,12 +254,20 @@ int csfmm_workspace_destroy(csfmm_workspace_t ws) {
     return CSFMM_OK;
 }
 
+int64_t csfmm_workspace_device_bytes(csfmm_workspace_t ws) {
+    return ws ? ws->arena.bytes : -1;
+}
+
+// The bytes workspace_create allocates for this plan, term by term.
 int64_t csfmm_workspace_bytes(csfmm_plan_t plan) {
     if (!plan) return -1;
-    return int64_t(sizeof(double)) *
-           (plan->ns + int64_t(plan->st->ncells) * plan->KS +
-            int64_t(3) * plan->tt.ncells * plan->KS + int64_t(6) * plan->nt) +
-           int64_t(sizeof(csfmm::ReqView));
+    int64_t b = int64_t(sizeof(double)) *
+                    (plan->ns + int64_t(plan->st->ncells) * plan->KS +
+                     int64_t(3) * plan->tt.ncells * plan->KS + int64_t(6) * plan->nt) +
+                int64_t(sizeof(csfmm::ReqView));
+    if (csfmm::sym_path_possible(plan))
+        b += int64_t(sizeof(float)) * plan->lists.sym.n_own * csfmm::kWaveLeaf;
+    return b;
 }
 
 int csfmm_eval_many(int n_req, const csfmm_plan_t* plans, const csfmm_workspace_t* workspaces,

@@ -2,9 +2,13 @@
 //
 // The scheduler decides; the caller executes.  Requests arrive with a plan
 // key (the geometry and method parameters of their plan), the device bytes of
-// that plan and of one eval workspace.  Each step admits queued requests in
-// arrival order into the next packed launch while their memory fits the HBM
-// budget:
+// that plan and of one eval workspace, and an estimate of their cost.  Each
+// step starts a batch (one packed launch) with the oldest waiting request and
+// adds, in arrival order, the waiting requests of the same cost class (within
+// a factor kClassRatio of its cost) while their memory fits the HBM budget;
+// requests of other classes wait for a later batch, which the caller may run
+// beside this one on another stream, so a small request is not held for the
+// length of a large one's launches:
 //   * a plan stays resident after its requests finish (plan cache); a request
 //     whose plan is resident needs no plan build;
 //   * each resident plan owns a pool of workspaces as large as the largest
@@ -13,8 +17,8 @@
 //   * when memory is short, resident plans with nothing in flight are evicted
 //     least recently used first; plans with requests in flight are never
 //     evicted;
-//   * admission is first-come first-served: when the oldest waiting request
-//     does not fit, no younger request overtakes it;
+//   * within a class admission is first-come first-served, and when the
+//     oldest waiting request does not fit, no younger request overtakes it;
 //   * a request that cannot fit even in an empty device is rejected.
 // Completions return the request's workspace to its plan's pool.
 #include <cstdint>
@@ -41,7 +45,11 @@ struct Req {
     uint64_t key;
     int64_t plan_bytes, ws_bytes;
     double t_arrival;
+    double cost;
 };
+
+// Requests within this factor of the batch head's cost share its batch.
+constexpr double kClassRatio = 4.0;
 
 }  // namespace
 
@@ -98,9 +106,9 @@ int csfmm_sched_destroy(csfmm_sched_t s) {
 }
 
 int csfmm_sched_submit(csfmm_sched_t s, int64_t req_id, uint64_t plan_key, int64_t plan_bytes,
-                       int64_t ws_bytes, double t_arrival) {
-    if (!s || plan_bytes < 0 || ws_bytes < 0) return CSFMM_E_INVALID;
-    s->queue.push_back(Req{req_id, plan_key, plan_bytes, ws_bytes, t_arrival});
+                       int64_t ws_bytes, double t_arrival, double cost) {
+    if (!s || plan_bytes < 0 || ws_bytes < 0 || !(cost >= 0.0)) return CSFMM_E_INVALID;
+    s->queue.push_back(Req{req_id, plan_key, plan_bytes, ws_bytes, t_arrival, cost});
     s->st.submitted += 1;
     return CSFMM_OK;
 }
@@ -108,25 +116,32 @@ int csfmm_sched_submit(csfmm_sched_t s, int64_t req_id, uint64_t plan_key, int64
 int csfmm_sched_step(csfmm_sched_t s, double now, csfmm_sched_decision* d) {
     if (!s || !d) return CSFMM_E_INVALID;
     d->n_launch = d->n_build = d->n_evict = d->n_reject = d->n_new_ws = 0;
-    while (!s->queue.empty() && d->n_launch < s->max_batch && d->n_launch < d->cap_launch) {
-        const Req q = s->queue.front();
+    double c0 = -1.0;  // cost of the batch's first request
+    size_t pos = 0;    // queue position examined next
+    while (pos < s->queue.size() && d->n_launch < s->max_batch && d->n_launch < d->cap_launch) {
+        const Req q = s->queue[pos];
         if (q.t_arrival > now) break;
+        if (c0 >= 0.0 && (q.cost > c0 * kClassRatio || q.cost * kClassRatio < c0)) {
+            ++pos;  // another class: a later batch takes it
+            continue;
+        }
         auto it = s->plans.find(q.key);
         const bool resident = it != s->plans.end();
         const bool free_ws = resident && it->second.inflight < it->second.pool;
         const int64_t need = (resident ? 0 : q.plan_bytes) + (free_ws ? 0 : q.ws_bytes);
         if (q.plan_bytes + q.ws_bytes > s->budget) {
-            s->queue.pop_front();
+            s->queue.erase(s->queue.begin() + pos);
             if (d->n_reject < d->cap_reject) d->reject_ids[d->n_reject++] = q.id;
             s->st.rejected += 1;
             continue;
         }
         if (s->used + need > s->budget &&
             !s->make_room(need, q.key, d->evict_keys, &d->n_evict, d->cap_evict))
-            break;  // wait for completions; nobody overtakes the oldest request
+            break;  // wait for completions; nobody in the class overtakes
         if (!resident && d->n_build >= d->cap_build) break;
         if (!free_ws && d->n_new_ws >= d->cap_launch) break;
-        s->queue.pop_front();
+        s->queue.erase(s->queue.begin() + pos);
+        if (c0 < 0.0) c0 = q.cost;
         PlanEntry& e = s->plans[q.key];
         if (!resident) {
             e.plan_bytes = q.plan_bytes;

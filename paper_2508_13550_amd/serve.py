@@ -1,13 +1,18 @@
 """Serving loop: continuous batching of CSFMM evaluations on one GPU.
 
 Requests (targets, sources, kernel, degree, weights) arrive over time.  The
-native scheduler (csfmm_sched_*, see include/csfmm.h) admits them in arrival
-order while their memory fits the HBM budget; plans stay resident in a cache
-keyed by geometry and parameters, each with a pool of eval workspaces.  Every
-step launches all admitted requests in one packed csfmm_eval_many (one launch
-per phase) on the compute stream; requests that arrive while a batch runs join
-the next one, so their work overlaps on the device.  Plans are built on a
-separate stream.  Completion times come from HIP events.
+native scheduler (csfmm_sched_*, see include/csfmm.h) forms batches: the
+oldest waiting request and the waiting requests of its cost class, while their
+memory fits the HBM budget; plans stay resident in a cache keyed by geometry
+and parameters, each with a pool of eval workspaces.  A batch is one packed
+csfmm_eval_many (one launch per phase).  The executor keeps several compute
+streams of equal priority; whenever one is free it asks the scheduler for the
+next batch and launches it there, so batches run beside each other on the
+device: requests that arrive while others are on the GPU are admitted as
+streams, slots and memory free up, and a small request need not wait for a
+large one's launches.  Each launch waits (on the device) for the stream that
+produced its requests' inputs.  Plans are built on a separate stream.
+Completion times come from HIP events.
 """
 
 import ctypes
@@ -48,7 +53,7 @@ def _declare(L):
     L.csfmm_sched_create.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.POINTER(vp)]
     L.csfmm_sched_destroy.argtypes = [vp]
     L.csfmm_sched_submit.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64,
-                                     ctypes.c_int64, ctypes.c_double]
+                                     ctypes.c_int64, ctypes.c_double, ctypes.c_double]
     L.csfmm_sched_step.argtypes = [vp, ctypes.c_double, ctypes.POINTER(Decision)]
     L.csfmm_sched_complete.argtypes = [vp, ctypes.c_int64, ctypes.c_double]
     L.csfmm_sched_get_stats.argtypes = [vp, ctypes.POINTER(SchedStats)]
@@ -74,9 +79,9 @@ class Scheduler:
         self._evict = (ctypes.c_uint64 * cap)()
         self._reject = (ctypes.c_int64 * cap)()
 
-    def submit(self, req_id, plan_key, plan_bytes, ws_bytes, t_arrival):
+    def submit(self, req_id, plan_key, plan_bytes, ws_bytes, t_arrival, cost=1.0):
         _check(self.L.csfmm_sched_submit(self._h, int(req_id), int(plan_key), int(plan_bytes),
-                                         int(ws_bytes), float(t_arrival)))
+                                         int(ws_bytes), float(t_arrival), float(cost)))
 
     def step(self, now):
         d = Decision(self._launch, self.cap, 0, self._build, self.cap, 0, self._neww, 0,
@@ -118,11 +123,14 @@ def estimate_cells(n, leaf):
 
 
 def workspace_bytes_estimate(n_t, n_s, p, leaf):
-    """Upper estimate of one eval workspace (same terms as csfmm_workspace_bytes)."""
+    """Upper estimate of one eval workspace (the terms of csfmm_workspace_bytes):
+    sorted weights, proxy weights and potentials, two near-field arrays and,
+    for same-set plans in the FP32 form, the column sums of the symmetric PP
+    pairs (64 floats per owned pair, at most 16 pairs per leaf)."""
     K = (p + 1) ** 2
     KS = (K + 3) // 4 * 4
-    return 8 * (n_s + estimate_cells(n_s, leaf) * KS + 3 * estimate_cells(n_t, leaf) * KS
-                + 6 * n_t) + 1024
+    ct, cs = estimate_cells(n_t, leaf), estimate_cells(n_s, leaf)
+    return (8 * (n_s + cs * KS + 3 * ct * KS + 6 * n_t) + 4 * 64 * 16 * ct + 1024)
 
 
 @dataclass
@@ -137,6 +145,7 @@ class Request:
     t_arrival: float = 0.0
     out: object = None
     t_done: float = field(default=float("nan"))
+    ready: object = None         # event on the stream that produced the inputs
 
     @property
     def n_t(self):
@@ -148,28 +157,31 @@ class Request:
 
 
 class Server:
-    """Executes the scheduler's decisions on the GPU."""
+    """Executes the scheduler's decisions on the GPU, one batch per free
+    compute stream (all of the default priority)."""
 
     def __init__(self, budget_bytes, theta=0.6, leaf=128, fp32=True, max_batch=32,
-                 clock=time.perf_counter):
+                 n_streams=3, clock=time.perf_counter):
         from . import estimate_bytes
         self._estimate_bytes = estimate_bytes
         self.theta, self.leaf, self.fp32 = float(theta), int(leaf), bool(fp32)
         self.sched = Scheduler(budget_bytes, max_batch)
         self.clock = clock
-        self.compute = torch.cuda.Stream()
+        self.streams = [torch.cuda.Stream() for _ in range(int(n_streams))]
         self.plan_stream = torch.cuda.Stream()
         self.plans = {}          # key -> Plan
         self.pools = {}          # key -> [free Workspace]
         self.requests = {}       # id -> Request (waiting or in flight)
         self.key_of = {}         # id -> plan key
-        self.inflight = []       # [(event, [request ids], {id: workspace})]
+        self.busy = {}           # stream index -> (event, [request ids], {id: workspace})
         self.done = []
         self.rejected = []
         self.batch_sizes = []
+        self.max_concurrent = 0  # most batches in flight at once
+        self.host_s = 0.0        # host time spent scheduling and launching
         torch.cuda.synchronize()
         self._ref = torch.cuda.Event(enable_timing=True)
-        self._ref.record(self.compute)
+        self._ref.record(self.streams[0])
         torch.cuda.synchronize()
         self._t_ref = self.clock()
 
@@ -177,19 +189,34 @@ class Server:
         key = plan_key(req.geometry, req.p, self.theta, self.leaf, self.fp32)
         pb = self._estimate_bytes(req.n_t, req.n_s, req.p, self.leaf, self.fp32)
         wb = workspace_bytes_estimate(req.n_t, req.n_s, req.p, self.leaf)
+        # the inputs may still be in flight on the caller's stream
+        req.ready = torch.cuda.Event()
+        req.ready.record(torch.cuda.current_stream())
         self.requests[req.id] = req
         self.key_of[req.id] = key
-        self.sched.submit(req.id, key, pb, wb, req.t_arrival)
+        self.sched.submit(req.id, key, pb, wb, req.t_arrival, cost=req.n_t + req.n_s)
 
     def _build(self, key, req):
+        self.plan_stream.wait_event(req.ready)
         with torch.cuda.stream(self.plan_stream):
             self.plans[key] = Plan(req.targets, req.sources, kernel=req.kernel, p=req.p,
                                    theta=self.theta, leaf_size=self.leaf, fp32=self.fp32)
         self.pools[key] = []
 
     def step(self, now=None):
-        """One scheduling step: evict, build, launch; returns the launched ids."""
+        """One scheduling step: if a compute stream is free, evict, build and
+        launch the scheduler's next batch there; returns the launched ids."""
+        t0 = time.perf_counter()
+        try:
+            return self._step(now)
+        finally:
+            self.host_s += time.perf_counter() - t0
+
+    def _step(self, now):
         self.poll()
+        free = [i for i in range(len(self.streams)) if i not in self.busy]
+        if not free:
+            return []
         now = self.clock() if now is None else now
         d = self.sched.step(now)
         for key in d["evict"]:
@@ -211,32 +238,36 @@ class Server:
             for key in d["new_ws"]:
                 self.pools[key].append(Workspace(self.plans[key]))
         batch, used = [], {}
+        si = free[0]
+        stream = self.streams[si]
+        stream.wait_stream(self.plan_stream)   # plans and workspaces built there
         for rid in d["launch"]:
             key = self.key_of[rid]
             req = self.requests[rid]
             ws = self.pools[key].pop()
             used[rid] = ws
+            stream.wait_event(req.ready)
             batch.append((self.plans[key], ws, req.kernel, req.weights))
-        self.plan_stream.synchronize()
-        with torch.cuda.stream(self.compute):
+        with torch.cuda.stream(stream):
             outs = eval_many(batch)
             ev = torch.cuda.Event(enable_timing=True)
-            ev.record(self.compute)
+            ev.record(stream)
         for rid, o in zip(d["launch"], outs):
             self.requests[rid].out = o
-        self.inflight.append((ev, list(d["launch"]), used))
+        self.busy[si] = (ev, list(d["launch"]), used)
         self.batch_sizes.append(len(d["launch"]))
+        self.max_concurrent = max(self.max_concurrent, len(self.busy))
         return list(d["launch"])
 
     def poll(self, wait=False):
-        """Retire finished batches (in launch order); returns the finished requests."""
+        """Retire finished batches (in any order); returns the finished requests."""
         fin = []
-        while self.inflight:
-            ev, ids, used = self.inflight[0]
+        for si in sorted(self.busy):
+            ev, ids, used = self.busy[si]
             if wait:
                 ev.synchronize()
             elif not ev.query():
-                break
+                continue
             t_done = self._t_ref + self._ref.elapsed_time(ev) / 1e3
             for rid in ids:
                 req = self.requests.pop(rid)
@@ -244,7 +275,7 @@ class Server:
                 self.pools[self.key_of[rid]].append(used[rid])
                 self.sched.complete(rid, t_done)
                 fin.append(req)
-            self.inflight.pop(0)
+            del self.busy[si]
         self.done.extend(fin)
         return fin
 
@@ -262,9 +293,9 @@ class Server:
                 i += 1
             launched = self.step(now)
             if not launched:
-                if self.inflight:
+                if self.busy:
                     self.poll()
-                if i < len(pending) and not self.inflight:
+                if i < len(pending) and not self.busy:
                     time.sleep(min(idle_sleep, max(0.0, pending[i].t_arrival - self.clock())))
         self.poll(wait=True)
         return self.done

@@ -140,7 +140,8 @@ def test_served_stream_under_tight_budget():
 def test_served_stream_at_full_request_sizes():
     """The serving workload's request sizes: E in {16, ..., 512} (N up to
     1,572,864), all three kernels, p in {6, 8}, 36 requests arriving faster
-    than they are served.  Every result equals, bit for bit, the request
+    than they are served, so that batches run beside each other on the
+    executor's streams.  Every result equals, bit for bit, the request
     evaluated alone on its resident plan; sampled requests of each kernel, the
     largest among them, match the oracle on 1,024 targets within 1e-5."""
     from workloads import config_subset
@@ -159,13 +160,14 @@ def test_served_stream_at_full_request_sizes():
     print("sched", st, "latency", latency_stats(done), "batches", srv.batch_sizes, flush=True)
     assert len(done) == n and st["completed"] == n and st["rejected"] == 0
     assert st["evictions"] == 0
+    assert srv.max_concurrent >= 2   # batches ran beside each other
     from paper_2508_13550_amd.serve import plan_key
     by_id = {r.id: r for r in done}
     for r in done:
         pl = srv.plans[plan_key(r.geometry, r.p, 0.6, 128, True)]
         alone = pl.eval(r.weights, kernel=r.kernel)
         assert torch.equal(alone, r.out), r.id
-    # oracle check: for each kernel the largest request, and two more
+    # oracle check: for each kernel its largest request and its first one
     picks = set()
     for k in (1, 2, 3):
         ids = [i for i, m in enumerate(mix) if m[1] == k]
@@ -182,3 +184,30 @@ def test_served_stream_at_full_request_sizes():
         print("request %d E=%d kernel %d p=%d rel L2 %.3e" % (i, E, r.kernel, r.p, err), flush=True)
         assert err < 1e-5
     srv.close()
+
+
+@pytest.mark.parametrize("E,p", [(16, 6), (64, 8), (256, 6), (512, 8)])
+def test_admission_estimates_cover_the_bytes_held(E, p):
+    """The scheduler admits by estimates made before a plan exists: they must
+    cover what the plan and a workspace then hold, in both forms (the FP32
+    same-set plans of E >= 256 hold the symmetric PP slots); the plan's own
+    workspace figure is exact."""
+    from paper_2508_13550_amd.serve import workspace_bytes_estimate
+    T = grid(E)[3]
+    n = T.shape[0]
+    for fp32 in (False, True):
+        pl = cs.Plan(T, None, kernel=1, p=p, theta=0.6, leaf_size=128, fp32=fp32)
+        ws = cs.Workspace(pl)
+        st = pl.stats()
+        est_plan = cs.estimate_bytes(n, n, p, 128, fp32)
+        est_ws = workspace_bytes_estimate(n, n, p, 128)
+        print("E=%d p=%d fp32=%s plan %d <= %d, workspace %d <= %d, sym pairs %d"
+              % (E, p, fp32, st["device_bytes"], est_plan, ws.device_bytes, est_ws,
+                 st["pp_sym_pairs"]), flush=True)
+        assert cs.workspace_bytes(pl) == ws.device_bytes
+        assert st["device_bytes"] <= est_plan
+        assert ws.device_bytes <= est_ws
+        if fp32 and E >= 256:
+            assert st["pp_sym_pairs"] > 0
+        ws.close()
+        pl.close()

@@ -113,3 +113,31 @@ def test_random_stream_invariants():
     st = s.stats()
     assert st["completed"] == n and st["queued"] == 0 and st["in_flight"] == 0
     assert st["plan_hits"] + st["plan_misses"] == n
+
+
+def test_cost_classes_form_separate_batches():
+    """A batch is the oldest waiting request and the waiting requests within a
+    factor 4 of its cost; the others wait for the next batch, which the
+    executor may run beside it, so small requests are not held behind a large
+    one; within a class the order is first-come."""
+    s = Scheduler(budget_bytes=10000 * MB, max_batch=8)
+    costs = [1e6, 1e3, 2e3, 3e6, 1.5e3, 8e5]
+    for i, c in enumerate(costs):
+        s.submit(i, plan_key=i, plan_bytes=10 * MB, ws_bytes=1 * MB, t_arrival=0.0, cost=c)
+    assert s.step(0.0)["launch"] == [0, 3, 5]   # the head (1e6) and its class
+    assert s.step(0.0)["launch"] == [1, 2, 4]   # the next oldest (1e3) and its class
+    assert s.step(0.0)["launch"] == []
+    assert s.stats()["batches"] == 2
+
+
+def test_cost_class_never_overtakes_the_oldest_on_memory():
+    s = Scheduler(budget_bytes=300 * MB, max_batch=8)
+    s.submit(0, 1, 200 * MB, 10 * MB, 0.0, cost=1e6)
+    s.submit(1, 2, 200 * MB, 10 * MB, 0.0, cost=1e3)   # does not fit beside plan 1
+    s.submit(2, 3, 20 * MB, 10 * MB, 0.0, cost=1e3)
+    assert s.step(0.0)["launch"] == [0]
+    # the oldest waiting request (1) does not fit: no batch starts, 2 waits too
+    assert s.step(0.0)["launch"] == []
+    s.complete(0, 1.0)
+    d = s.step(1.0)
+    assert d["evict"] == [1] and d["launch"] == [1, 2]
