@@ -28,8 +28,17 @@ Readings taken where the paper is silent or ambiguous:
     eta = atan(x.e_b / x.n).
   * A cluster with more than N0 particles is split into its four quadrants
     (also when some are empty) unless it is at the deepest level MAX_LEVEL;
-    a leaf is a cluster without children ("small" = leaf).  Clusters are not
-    shrunk: every cluster is its exact cubed-sphere cell.
+    a leaf is a cluster without children ("small" = leaf).  Without
+    shrinking every cluster is its exact cubed-sphere cell.
+  * Shrinking (§3, last remark on nonuniform particles; optional): the tree
+    keeps the same quadrants and the same points per cluster, but the box of a
+    non-empty cluster -- what its centre, radius, proxy points and local
+    coordinates refer to -- is the smallest (xi, eta) rectangle holding its
+    points, each half width at least SHRINK_FLOOR times the cell's half width
+    (so that a cluster of one point, or of points on one grid line, keeps an
+    interval to interpolate on).  The interpolation identity of §6 then holds
+    with each child's own box, so the parent-child operators of eqs.
+    (upwardpass2) and (downward_2) are computed per cluster.
   * Cluster centre = image of the (xi, eta) midpoint; radius = largest chord
     distance from the centre to the four corners; R = chord distance between
     centres.  Well separated means (r_t + r_s)^2 < MAC^2 R^2 (strict).
@@ -60,6 +69,7 @@ import numpy as np
 MAX_LEVEL = 20
 PI_4 = math.pi / 4.0
 PI_2 = math.pi / 2.0
+SHRINK_FLOOR = 2.0 ** -20
 
 # (normal, e_a, e_b) for faces +x, +y, -x, -y, +z, -z, with e_a x e_b = normal
 FACE_FRAMES = np.array([
@@ -202,7 +212,8 @@ class Cell:
     """A cluster: one cubed-sphere cell (face, level, i, j) and its points."""
 
     __slots__ = ("face", "level", "i", "j", "idx", "children", "parent", "id",
-                 "xi_mid", "eta_mid", "half", "center", "radius", "proxies")
+                 "xi_mid", "eta_mid", "half", "half_xi", "half_eta", "center", "radius",
+                 "proxies")
 
     def __init__(self, face, level, i, j, idx, parent):
         self.face, self.level, self.i, self.j = face, level, i, j
@@ -213,7 +224,17 @@ class Cell:
         d = PI_2 / 2 ** level
         self.xi_mid = -PI_4 + (i + 0.5) * d
         self.eta_mid = -PI_4 + (j + 0.5) * d
-        self.half = 0.5 * d
+        self.half = 0.5 * d          # the cell's half width
+        self.half_xi = self.half     # the box's half widths (the cell unless shrunk)
+        self.half_eta = self.half
+
+    def shrink(self, xi, eta):
+        """Make the box the smallest rectangle holding the angles (xi, eta)
+        of the cluster's points (half widths floored, see the module notes)."""
+        lo, hi = float(np.min(xi)), float(np.max(xi))
+        self.xi_mid, self.half_xi = 0.5 * (lo + hi), max(0.5 * (hi - lo), SHRINK_FLOOR * self.half)
+        lo, hi = float(np.min(eta)), float(np.max(eta))
+        self.eta_mid, self.half_eta = 0.5 * (lo + hi), max(0.5 * (hi - lo), SHRINK_FLOOR * self.half)
 
     @property
     def key(self):
@@ -228,15 +249,16 @@ class Cell:
         return len(self.idx)
 
     def local(self, xi, eta):
-        """Local coordinates in [-1,1]^2 of angles inside this cell."""
-        return (xi - self.xi_mid) / self.half, (eta - self.eta_mid) / self.half
+        """Local coordinates in [-1,1]^2 of angles inside this cluster's box."""
+        return (xi - self.xi_mid) / self.half_xi, (eta - self.eta_mid) / self.half_eta
 
 
 class Tree:
     """Forest of six quadtrees over the cubed sphere (§3)."""
 
-    def __init__(self, points, N0, n):
+    def __init__(self, points, N0, n, shrink=False):
         self.points = np.asarray(points, dtype=np.float64)
+        self.shrink = bool(shrink)
         self.N0 = int(N0)
         self.n = int(n)
         self.face, self.xi, self.eta = face_and_angles(self.points)
@@ -262,24 +284,27 @@ class Tree:
         self.cells = [C for lev in self.levels for C in lev]
         for k, C in enumerate(self.cells):
             C.id = k
+            if self.shrink and C.count > 0:
+                C.shrink(self.xi[C.idx], self.eta[C.idx])
             self._geometry(C)
 
     def _geometry(self, C):
-        """Centre, radius (chord to the farthest corner) and proxy points."""
+        """Centre, radius (chord to the farthest corner) and proxy points of
+        the cluster's box."""
         f = np.array([C.face])
         C.center = angles_to_sphere(f, np.array([C.xi_mid]), np.array([C.eta_mid]))[0]
-        cx = C.xi_mid + C.half * np.array([-1.0, -1.0, 1.0, 1.0])
-        cy = C.eta_mid + C.half * np.array([-1.0, 1.0, -1.0, 1.0])
+        cx = C.xi_mid + C.half_xi * np.array([-1.0, -1.0, 1.0, 1.0])
+        cy = C.eta_mid + C.half_eta * np.array([-1.0, 1.0, -1.0, 1.0])
         corners = angles_to_sphere(np.full(4, C.face), cx, cy)
         C.radius = float(np.max(np.sqrt(np.sum((corners - C.center) ** 2, axis=1))))
-        s = chebyshev_points(self.n)
-        px = np.repeat(C.xi_mid + C.half * s, self.n + 1)
-        py = np.tile(C.eta_mid + C.half * s, self.n + 1)
+        sx, sy = self.proxy_angles(C)
+        px = np.repeat(sx, self.n + 1)
+        py = np.tile(sy, self.n + 1)
         C.proxies = angles_to_sphere(np.full(px.shape[0], C.face), px, py)
 
     def proxy_angles(self, C):
         s = chebyshev_points(self.n)
-        return C.xi_mid + C.half * s, C.eta_mid + C.half * s
+        return C.xi_mid + C.half_xi * s, C.eta_mid + C.half_eta * s
 
     @property
     def leaves(self):
@@ -359,14 +384,14 @@ def dual_traversal(ttree, stree, theta):
 class FMM:
     """One CSFMM evaluation: phi_i = sum_j K(x_i, y_j) w_j, approximated."""
 
-    def __init__(self, targets, sources, kernel, n, theta, N0):
+    def __init__(self, targets, sources, kernel, n, theta, N0, shrink=False):
         self.kernel = int(kernel)
         self.n = int(n)
         self.theta = float(theta)
         self.N0 = int(N0)
         self.same = sources is None
-        self.ttree = Tree(targets, N0, n)
-        self.stree = self.ttree if self.same else Tree(sources, N0, n)
+        self.ttree = Tree(targets, N0, n, shrink)
+        self.stree = self.ttree if self.same else Tree(sources, N0, n, shrink)
         self.lists = dual_traversal(self.ttree, self.stree, self.theta)
 
     @property
@@ -460,9 +485,9 @@ class FMM:
         return out
 
 
-def fmm(targets, sources, weights, kernel, n, theta, N0, sample=None):
+def fmm(targets, sources, weights, kernel, n, theta, N0, sample=None, shrink=False):
     """Convenience wrapper: build the trees and lists, then evaluate."""
-    F = FMM(targets, sources, kernel, n, theta, N0)
+    F = FMM(targets, sources, kernel, n, theta, N0, shrink)
     return F.evaluate(weights, sample=sample)
 
 
