@@ -64,13 +64,20 @@ enum csfmm_kernel {
                                 (the ratio is named, not given, in §2.4); one output */
 };
 
-/* Precision forms. */
+/* Precision forms, and cluster shrinking (a plan option). */
 enum csfmm_flags {
-    CSFMM_FP64 = 0,     /* every step in FP64 */
-    CSFMM_FP32_FORM = 1 /* kernel evaluations (PP, PC, CP, CC, direct) in FP32 on
-                           coordinates recentred at the target cell in FP64;
-                           partial sums added into FP64; geometry, mapping,
-                           interpolation and final sums in FP64 */
+    CSFMM_FP64 = 0,      /* every step in FP64 */
+    CSFMM_FP32_FORM = 1, /* kernel evaluations (PP, PC, CP, CC, direct) in FP32 on
+                            coordinates recentred at the target cell in FP64;
+                            partial sums added into FP64; geometry, mapping,
+                            interpolation and final sums in FP64 */
+    CSFMM_SHRINK = 2     /* csfmm_plan only (paper §3, the remark on nonuniform
+                            particles): each non-empty cluster's box -- centre,
+                            radius, proxies, local coordinates -- is the smallest
+                            (xi, eta) rectangle holding its points, half widths at
+                            least 2^-20 of its cell's; the tree keeps its quadrants,
+                            and the operators of eqs. (upwardpass2) and
+                            (downward_2) become per cluster */
 };
 
 typedef struct csfmm_stats {

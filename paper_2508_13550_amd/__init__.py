@@ -25,6 +25,7 @@ KERNELS = {"poisson": POISSON, "biot_savart": BIOT_SAVART, "inv_dist": INV_DIST,
 
 FP64 = 0
 FP32_FORM = 1
+SHRINK = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcsfmm.so")
@@ -170,7 +171,7 @@ class Plan:
     """csfmm_plan: trees, proxies, interpolation operators and lists."""
 
     def __init__(self, targets, sources=None, kernel=POISSON, p=8, theta=0.7, leaf_size=64,
-                 fp32=False):
+                 fp32=False, shrink=False):
         _require_gpu()
         self.targets = _points(targets, "targets")
         self.sources = None if sources is None else _points(sources, "sources")
@@ -179,13 +180,15 @@ class Plan:
         self.theta = float(theta)
         self.leaf_size = int(leaf_size)
         self.fp32 = bool(fp32)
+        self.shrink = bool(shrink)
         self.n_t = self.targets.shape[0]
         self.n_s = self.n_t if self.sources is None else self.sources.shape[0]
         h = ctypes.c_void_p()
         src_ptr = None if self.sources is None else self.sources.data_ptr()
         _check(_lib.csfmm_plan(self.targets.data_ptr(), self.n_t, src_ptr, self.n_s,
                                self.kernel, self.p, self.theta, self.leaf_size,
-                               FP32_FORM if self.fp32 else FP64, _stream(), ctypes.byref(h)))
+                               (FP32_FORM if self.fp32 else FP64) | (SHRINK if self.shrink else 0),
+                               _stream(), ctypes.byref(h)))
         self._h = h
 
     @property

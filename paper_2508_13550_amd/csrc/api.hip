@@ -65,7 +65,7 @@ int csfmm_plan(const double* targets, int64_t n_t, const double* sources, int64_
         set_error("leaf_size must be >= 1 (got %d)", leaf_size);
         return CSFMM_E_INVALID;
     }
-    if (flags & ~unsigned(CSFMM_FP32_FORM)) {
+    if (flags & ~unsigned(CSFMM_FP32_FORM | CSFMM_SHRINK)) {
         set_error("unknown flags 0x%x", flags);
         return CSFMM_E_INVALID;
     }

@@ -94,6 +94,12 @@ struct Tree {
     // per leaf (in `leaves` order): [0] = number of cells on the path from the
     // root to the leaf, then those cells, root first; stride kAncStride
     int32_t* leaf_anc = nullptr;
+    // [ncells][4] box of each cell: xi_mid, eta_mid, half_xi, half_eta (the
+    // cell itself, or its points' bounding rectangle with shrinking)
+    double* box = nullptr;
+    // shrinking: [ncells][2][p+1][p+1] 1-D factors of the parent-to-child
+    // operator (xi, eta): the parent's polynomial k at the child's node m
+    double* ops = nullptr;
     double* center = nullptr;  // [ncells][3]
     double* radius = nullptr;  // [ncells]
     // [ncells] leaves: a lower bound on the geodesic distance of the leaf's
@@ -147,8 +153,9 @@ struct ReqView {
     const int32_t* off[4];
     const int32_t* src[4];
     const int32_t *novl, *ncl, *far_targets;
-    // fixed operators
+    // fixed operators, and the per-cell factors of shrunk trees (else NULL)
     const double *bm2m, *lag1d;
+    const double *t_ops, *s_ops;
     // workspace
     double *ws, *wbar, *psi, *phinear, *phipc;
     int64_t nt, ns, psi_stride;

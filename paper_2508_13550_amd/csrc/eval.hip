@@ -237,6 +237,79 @@ __global__ __launch_bounds__(256) void k_m2m(Batch b) {
     }
 }
 
+// e3 M2M (eq. upwardpass2) of shrunk plans, one level: every parent has its
+// own operator (the children's boxes differ), so instead of one GEMM a wave
+// applies it to one parent (four per block) as two 1-D passes per child with
+// the child's own factors A_xi, A_eta (A[m][k]: the parent's polynomial k at
+// the child's node m):
+//   t[k1][m2] = sum_m1 A_xi[m1][k1] wbar_c[m1][m2],
+//   wbar_P[k1][k2] += sum_m2 A_eta[m2][k2] t[k1][m2].
+template <int P1>
+__global__ __launch_bounds__(256) void k_m2m_cells(Batch b) {
+    constexpr int K = P1 * P1;
+    constexpr int kRegs = (K + 63) / 64;
+    __shared__ double wlds[4][4][K];  // per wave: child weights, t, A_xi, A_eta
+    int r, local;
+    locate(b, r, local);
+    const ReqView& V = *b.v[r];
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    const int idx = 4 * local + wave;
+    if (idx >= b.a1[r]) return;  // the whole wave leaves
+    const int par = V.s_parents[b.a0[r] + idx];
+    const int ch0 = V.s_child0[par];
+    const int KS = V.KS;
+    double* wc = wlds[wave][0];
+    double* tb = wlds[wave][1];
+    double* ax = wlds[wave][2];
+    double* ay = wlds[wave][3];
+    double out[kRegs];
+#pragma unroll
+    for (int i = 0; i < kRegs; ++i) out[i] = 0.0;
+    for (int q = 0; q < 4; ++q) {
+        const int c = ch0 + q;
+        const double* src = V.wbar + int64_t(c) * KS;
+        const double* op = V.s_ops + int64_t(c) * 2 * K;
+        for (int k = lane; k < K; k += 64) {
+            wc[k] = src[k];
+            ax[k] = op[k];
+            ay[k] = op[K + k];
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < kRegs; ++i) {
+            const int e = lane + 64 * i;
+            if (e < K) {
+                const int k1 = e / P1, m2 = e % P1;
+                double t = 0.0;
+#pragma unroll
+                for (int m1 = 0; m1 < P1; ++m1) t = fma(ax[m1 * P1 + k1], wc[m1 * P1 + m2], t);
+                tb[e] = t;
+            }
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < kRegs; ++i) {
+            const int e = lane + 64 * i;
+            if (e < K) {
+                const int k1 = e / P1, k2 = e % P1;
+                double t = out[i];
+#pragma unroll
+                for (int m2 = 0; m2 < P1; ++m2) t = fma(ay[m2 * P1 + k2], tb[k1 * P1 + m2], t);
+                out[i] = t;
+            }
+        }
+        wave_lds_sync();
+    }
+    double* wb = V.wbar + int64_t(par) * KS;
+#pragma unroll
+    for (int i = 0; i < kRegs; ++i) {
+        const int e = lane + 64 * i;
+        if (e < K) wb[e] = out[i];
+    }
+    for (int k = K + lane; k < KS; k += 64) wb[k] = 0.0;
+}
+
 // e6-e8: L2L (eq. downward_2) down the leaf's ancestors, L2P (eq.
 // downward_1) at the leaf, near field (PP, PC) and scatter to the caller's
 // order; one target leaf per wave (four per block: blocks of one wave made the
@@ -261,6 +334,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VD == 1 && 
     __shared__ double s[P1], beta[P1];
     __shared__ double A1[2][P1][P1];
     __shared__ double psw[4][VD][K], tbw[4][VD][K];
+    __shared__ double opw[4][2][K];  // shrunk plans: the child's own factors
     __shared__ int ancw[4][kAncStride];
     int r, local;
     locate(b, r, local);
@@ -306,6 +380,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VD == 1 && 
         const int ch = anc[l], par = anc[l - 1];
         const int q = ch - V.t_child0[par];
         const int bi = q >> 1, bj = q & 1;
+        // the 1-D factors of this level: fixed by the child's quadrant, or the
+        // child's own (shrunk boxes)
+        const double* Ax = &A1[bi][0][0];
+        const double* Ay = &A1[bj][0][0];
+        if (V.t_ops) {
+            const double* src = V.t_ops + int64_t(ch) * 2 * K;
+            for (int k = tid; k < 2 * K; k += 64) (&opw[wave][0][0])[k] = src[k];
+            wave_lds_sync();
+            Ax = &opw[wave][0][0];
+            Ay = &opw[wave][1][0];
+        }
 #pragma unroll
         for (int i = 0; i < kRegs; ++i) cur[i] = nxt[i];
         if (l < na) load_own(anc[l + 1], nxt);  // one level ahead
@@ -316,7 +401,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VD == 1 && 
                 const int d = k / K, e = k % K, n1 = e / P1, m2 = e % P1;
                 double t = 0.0;
 #pragma unroll
-                for (int m1 = 0; m1 < P1; ++m1) t = fma(A1[bi][n1][m1], ps[d][m1 * P1 + m2], t);
+                for (int m1 = 0; m1 < P1; ++m1) t = fma(Ax[n1 * P1 + m1], ps[d][m1 * P1 + m2], t);
                 tb[d][e] = t;
             }
         }
@@ -328,7 +413,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VD == 1 && 
                 const int d = k / K, e = k % K, n1 = e / P1, n2 = e % P1;
                 double t = cur[i];
 #pragma unroll
-                for (int m2 = 0; m2 < P1; ++m2) t = fma(A1[bj][n2][m2], tb[d][n1 * P1 + m2], t);
+                for (int m2 = 0; m2 < P1; ++m2) t = fma(Ay[n2 * P1 + m2], tb[d][n1 * P1 + m2], t);
                 ps[d][e] = t;
             }
         }
@@ -486,18 +571,41 @@ int max_source_depth(const EvalReq* reqs, int n) {
     return maxd;
 }
 
-// e3 M2M by levels, deepest parents first: parent levels lhi down to llo
+// e3 M2M by levels, deepest parents first: parent levels lhi down to llo;
+// plans with fixed operators in one MFMA launch per level, shrunk plans
+// (per-cell operators) in one launch per level and degree
 int launch_m2m(Batch& b, const EvalReq* reqs, int n, hipStream_t s, int lhi, int llo) {
     int64_t blk[kMaxBatch];
+    bool any_shrunk = false;
+    for (int r = 0; r < n; ++r) any_shrunk = any_shrunk || reqs[r].plan->st->ops != nullptr;
     for (int l = lhi; l >= std::max(llo, 0); --l) {
         for (int r = 0; r < n; ++r) {
             const Tree& S = *reqs[r].plan->st;
             const int np = l < S.depth ? S.parents_begin[l + 1] - S.parents_begin[l] : 0;
             b.a0[r] = l < S.depth ? S.parents_begin[l] : 0;
             b.a1[r] = np;
-            blk[r] = mfma_tiles(np, reqs[r].plan->nb1);
+            blk[r] = S.ops ? 0 : mfma_tiles(np, reqs[r].plan->nb1);
         }
         RCX(launch_batched(b, blk, [&](unsigned g) { k_m2m<<<g, 256, 0, s>>>(b); }));
+        if (!any_shrunk) continue;
+        for (int P1 = 2; P1 <= kMaxP1; ++P1) {
+            bool any = false;
+            for (int r = 0; r < n; ++r) {
+                const Tree& S = *reqs[r].plan->st;
+                blk[r] = (S.ops && reqs[r].plan->p + 1 == P1) ? (int64_t(b.a1[r]) + 3) / 4 : 0;
+                any = any || blk[r] > 0;
+            }
+            if (!any) continue;
+            switch (P1) {
+#define X(Q)                                                                                   \
+    case Q:                                                                                    \
+        RCX(launch_batched(b, blk, [&](unsigned g) { k_m2m_cells<Q><<<g, 256, 0, s>>>(b); })); \
+        break;
+                CSFMM_P1_CASES(X)
+#undef X
+                default: break;
+            }
+        }
     }
     return CSFMM_OK;
 }
@@ -746,6 +854,8 @@ int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** ou
     v.far_targets = P->lists.far_targets;
     v.bm2m = P->bm2m;
     v.lag1d = P->lag1d;
+    v.t_ops = T.ops;
+    v.s_ops = S.ops;
     v.ws = W->ws; v.wbar = W->wbar; v.psi = W->psi; v.phinear = W->phinear; v.phipc = W->phipc;
     v.nt = P->nt; v.ns = P->ns;
     v.psi_stride = int64_t(T.ncells) * P->KS;

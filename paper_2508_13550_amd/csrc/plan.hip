@@ -368,19 +368,69 @@ __global__ void k_compact(const int32_t* __restrict__ flag, const int32_t* __res
 
 // §4: centre, radius (largest chord distance to a corner) and the (p+1)^2
 // proxy points of every cell; proxies stored [cell][3][KS], zero padded.
-__global__ void k_cell_geometry(int n, const int32_t* __restrict__ level,
-                                const int32_t* __restrict__ face, const int32_t* __restrict__ ci,
-                                const int32_t* __restrict__ cj, int p, int KS,
+// The box of every cell (xi_mid, eta_mid, half_xi, half_eta): its cell, or
+// with shrinking (paper §3, the remark on nonuniform particles) the smallest
+// (xi, eta) rectangle holding its points, each half width at least
+// kShrinkFloor of the cell's.  One block per cell reduces its points' angles.
+constexpr double kShrinkFloor = 1.0 / 1048576.0;  // 2^-20
+__global__ __launch_bounds__(128) void k_cell_box(
+    int n, const int32_t* __restrict__ level, const int32_t* __restrict__ ci,
+    const int32_t* __restrict__ cj, const int32_t* __restrict__ begin,
+    const int32_t* __restrict__ count, const double* __restrict__ xi,
+    const double* __restrict__ eta, bool shrink, double* __restrict__ box) {
+    __shared__ double red[4][128];
+    const int c = blockIdx.x;
+    if (c >= n) return;
+    const double d = kPi2 / double(1u << level[c]);
+    const double half = 0.5 * d;
+    double xm = -kPi4 + (double(ci[c]) + 0.5) * d, ym = -kPi4 + (double(cj[c]) + 0.5) * d;
+    double hx = half, hy = half;
+    const int b = begin[c], m = count[c];
+    if (shrink && m > 0) {
+        double lo_x = xi[b], hi_x = xi[b], lo_y = eta[b], hi_y = eta[b];
+        for (int k = threadIdx.x; k < m; k += blockDim.x) {
+            lo_x = fmin(lo_x, xi[b + k]);
+            hi_x = fmax(hi_x, xi[b + k]);
+            lo_y = fmin(lo_y, eta[b + k]);
+            hi_y = fmax(hi_y, eta[b + k]);
+        }
+        red[0][threadIdx.x] = lo_x;
+        red[1][threadIdx.x] = hi_x;
+        red[2][threadIdx.x] = lo_y;
+        red[3][threadIdx.x] = hi_y;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if (int(threadIdx.x) < w) {
+                red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+                red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+                red[2][threadIdx.x] = fmin(red[2][threadIdx.x], red[2][threadIdx.x + w]);
+                red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + w]);
+            }
+            __syncthreads();
+        }
+        xm = 0.5 * (red[0][0] + red[1][0]);
+        hx = fmax(0.5 * (red[1][0] - red[0][0]), kShrinkFloor * half);
+        ym = 0.5 * (red[2][0] + red[3][0]);
+        hy = fmax(0.5 * (red[3][0] - red[2][0]), kShrinkFloor * half);
+    }
+    if (threadIdx.x == 0) {
+        box[4 * int64_t(c)] = xm;
+        box[4 * int64_t(c) + 1] = ym;
+        box[4 * int64_t(c) + 2] = hx;
+        box[4 * int64_t(c) + 3] = hy;
+    }
+}
+
+__global__ void k_cell_geometry(int n, const int32_t* __restrict__ face,
+                                const double* __restrict__ box, int p, int KS,
                                 double* __restrict__ center, double* __restrict__ radius,
                                 double* __restrict__ prox) {
 #pragma clang fp contract(off)
     const int c = blockIdx.x;
     if (c >= n) return;
-    const int f = face[c], l = level[c];
-    const double d = kPi2 / double(1u << l);
-    const double half = 0.5 * d;
-    const double xm = -kPi4 + (double(ci[c]) + 0.5) * d;
-    const double ym = -kPi4 + (double(cj[c]) + 0.5) * d;
+    const int f = face[c];
+    const double xm = box[4 * int64_t(c)], ym = box[4 * int64_t(c) + 1];
+    const double hx = box[4 * int64_t(c) + 2], hy = box[4 * int64_t(c) + 3];
     __shared__ double cen[3];
     if (threadIdx.x == 0) {
         gnomonic(f, xm, ym, cen);
@@ -388,7 +438,7 @@ __global__ void k_cell_geometry(int n, const int32_t* __restrict__ level,
         for (int q = 0; q < 4; ++q) {
             const double sx = (q >> 1) ? 1.0 : -1.0, sy = (q & 1) ? 1.0 : -1.0;
             double v[3];
-            gnomonic(f, xm + half * sx, ym + half * sy, v);
+            gnomonic(f, xm + hx * sx, ym + hy * sy, v);
             const double dx = v[0] - cen[0], dy = v[1] - cen[1], dz = v[2] - cen[2];
             r = fmax(r, sqrt(dx * dx + dy * dy + dz * dz));
         }
@@ -405,7 +455,7 @@ __global__ void k_cell_geometry(int n, const int32_t* __restrict__ level,
             const double s1 = cos(double(k1) * kPi / double(p));
             const double s2 = cos(double(k2) * kPi / double(p));
             double v[3];
-            gnomonic(f, xm + half * s1, ym + half * s2, v);
+            gnomonic(f, xm + hx * s1, ym + hy * s2, v);
             pc[k] = v[0];
             pc[KS + k] = v[1];
             pc[2 * KS + k] = v[2];
@@ -417,8 +467,8 @@ __global__ void k_cell_geometry(int n, const int32_t* __restrict__ level,
     }
 }
 
-// Local coordinates (u, v) in [-1,1]^2 of every point in its leaf (§4), and
-// the leaf's gap: a lower bound on the geodesic distance from its points to
+// Local coordinates (u, v) in [-1,1]^2 of every point in its leaf's box (§4),
+// and the leaf's gap: a lower bound on the geodesic distance from its points to
 // the leaf's boundary.  The cell edges xi = const and eta = const are great
 // circles; a point at angle xi on its face lies at sin-distance
 // rho_a sin(xi - xi0) from the circle xi = xi0, rho_a^2 = (1 + A^2)/(1 + A^2 +
@@ -429,8 +479,9 @@ __global__ void k_leaf_local(const int32_t* __restrict__ leaves, int nleaves,
                              const int32_t* __restrict__ level, const int32_t* __restrict__ ci,
                              const int32_t* __restrict__ cj, const int32_t* __restrict__ begin,
                              const int32_t* __restrict__ count, const double* __restrict__ xi,
-                             const double* __restrict__ eta, double* __restrict__ u,
-                             double* __restrict__ v, double* __restrict__ gap) {
+                             const double* __restrict__ eta, const double* __restrict__ box,
+                             double* __restrict__ u, double* __restrict__ v,
+                             double* __restrict__ gap) {
     __shared__ unsigned gmin;
     const int L = blockIdx.x;
     if (L >= nleaves) return;
@@ -442,10 +493,13 @@ __global__ void k_leaf_local(const int32_t* __restrict__ leaves, int nleaves,
     const double xm = -kPi4 + (double(ci[c]) + 0.5) * d;
     const double ym = -kPi4 + (double(cj[c]) + 0.5) * d;
     const int b = begin[c], m = count[c];
+    const double bxm = box[4 * int64_t(c)], bym = box[4 * int64_t(c) + 1];
+    const double bhx = box[4 * int64_t(c) + 2], bhy = box[4 * int64_t(c) + 3];
     for (int k = threadIdx.x; k < m; k += blockDim.x) {
+        // local coordinates in the box; the gap is to the cell's edges
+        u[b + k] = (xi[b + k] - bxm) / bhx;
+        v[b + k] = (eta[b + k] - bym) / bhy;
         const double uu = (xi[b + k] - xm) / half, vv = (eta[b + k] - ym) / half;
-        u[b + k] = uu;
-        v[b + k] = vv;
         const double A = tan(xi[b + k]), B = tan(eta[b + k]);
         const double q = 1.0 + A * A + B * B;
         const double ga = sqrt((1.0 + A * A) / q) * sin(fmax(0.0, 1.0 - fabs(uu)) * half);
@@ -501,6 +555,27 @@ __global__ void k_build_ops(int p, int KS, int nb1, double* __restrict__ A1d,
         }
         bm2m[t] = val;
     }
+}
+
+// Shrinking: the 1-D factors of the parent-to-child operator of every cell
+// below a root, A_c[dim][m][k] = L_k^P((mid_c + half_c s_m - mid_P)/half_P),
+// the parent's polynomial k at the child's node m in the parent's box
+// (dim 0: xi, 1: eta); the non-shrunk plans use the two fixed factors.
+__global__ void k_cell_ops(int n, int p, const int32_t* __restrict__ parent,
+                           const double* __restrict__ box, double* __restrict__ ops) {
+    const int P1 = p + 1, K = P1 * P1;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(n) * 2 * K) return;
+    const int c = int(t / (2 * K)), r = int(t % (2 * K));
+    const int dim = r / K, m = (r % K) / P1, k = r % P1;
+    const int par = parent[c];
+    double val = 0.0;
+    if (par >= 0) {
+        const double s = cos(double(m) * kPi / double(p));
+        const double x = box[4 * int64_t(c) + dim] + box[4 * int64_t(c) + 2 + dim] * s;
+        val = lagrange1(p, k, (x - box[4 * int64_t(par) + dim]) / box[4 * int64_t(par) + 2 + dim]);
+    }
+    ops[t] = val;
 }
 
 // ------------------------------------------------------------- traversal
@@ -853,18 +928,29 @@ int build_tree(csfmm_plan_s* P, Tree& T, const double* pts, int64_t n, hipStream
     T.parents_begin.assign(levs.size() + 1, nparents);
     for (size_t l = 0; l < levs.size(); ++l) T.parents_begin[l] = hpo[T.level_begin[l]];
 
-    // geometry and proxies
+    // boxes (cells, or shrunk), geometry and proxies
+    const bool shrink = (P->flags & CSFMM_SHRINK) != 0;
+    RC(A.alloc(&T.box, int64_t(4) * nc));
+    k_cell_box<<<nc, 128, 0, s>>>(nc, T.level, T.ci, T.cj, T.begin, T.count, xi, eta, shrink,
+                                  T.box);
+    CSFMM_LAUNCH_CHECK();
     RC(A.alloc(&T.center, int64_t(3) * nc));
     RC(A.alloc(&T.radius, nc));
     RC(A.alloc(&T.prox, int64_t(3) * P->KS * nc));
-    k_cell_geometry<<<nc, 128, 0, s>>>(nc, T.level, T.face, T.ci, T.cj, P->p, P->KS, T.center,
-                                       T.radius, T.prox);
+    k_cell_geometry<<<nc, 128, 0, s>>>(nc, T.face, T.box, P->p, P->KS, T.center, T.radius,
+                                       T.prox);
     CSFMM_LAUNCH_CHECK();
     RC(A.alloc(&T.gap, nc));
     k_fill_f64<<<nblk(nc), kT, 0, s>>>(T.gap, nc, 0.0);
     k_leaf_local<<<nleaves, 128, 0, s>>>(T.leaves, nleaves, T.level, T.ci, T.cj, T.begin, T.count,
-                                         xi, eta, T.u, T.v, T.gap);
+                                         xi, eta, T.box, T.u, T.v, T.gap);
     CSFMM_LAUNCH_CHECK();
+    if (shrink) {
+        const int64_t K = int64_t(P->p + 1) * (P->p + 1);
+        RC(A.alloc(&T.ops, int64_t(nc) * 2 * K));
+        k_cell_ops<<<nblk(int64_t(nc) * 2 * K), kT, 0, s>>>(nc, P->p, T.parent, T.box, T.ops);
+        CSFMM_LAUNCH_CHECK();
+    }
     return CSFMM_OK;
 }
 

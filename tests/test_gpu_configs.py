@@ -153,3 +153,42 @@ def test_config4_distinct_inverse_distance(cfg4, fp32):
     assert err <= 1e-5
     assert em <= 1e-4
     torch.cuda.empty_cache()
+
+
+def _clustered_cloud(n_bg, n_per, centres, sigma, seed):
+    rng = np.random.default_rng(seed)
+    from workloads import random_sphere_points
+    pts = [random_sphere_points(n_bg, seed + 1)]
+    for c in random_sphere_points(centres, seed):
+        x = c + sigma * rng.standard_normal((n_per, 3))
+        pts.append(x / np.linalg.norm(x, axis=1, keepdims=True))
+    return np.concatenate(pts)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_clustered_cloud_with_shrinking(fp32):
+    """Nonuniform points at size (paper §3's remark on shrinking): 320,000
+    points in 16 Gaussian caps plus a uniform background, Poisson kernel,
+    p=8, theta 0.6, leaf 64, clusters shrunk to their points, against the
+    oracle's direct sum on 2,048 sampled targets; shrinking cuts the kernel
+    evaluations against the same plan without it."""
+    X = _clustered_cloud(64000, 16000, 16, 0.03, 71)
+    w = np.random.default_rng(72).standard_normal(X.shape[0]) / X.shape[0]
+    S = config_subset(X.shape[0], 2048, 73)
+    say("clustered cloud oracle on 2,048 targets")
+    ref = odirect(1, X[S], X, w)
+    Xd, W = tdev(X), tdev(w)
+    pl = cs.Plan(Xd, None, kernel=1, p=8, theta=0.6, leaf_size=64, fp32=fp32, shrink=True)
+    out = pl.eval(W).cpu().numpy()
+    st = pl.stats()
+    pl.close()
+    pl0 = cs.Plan(Xd, None, kernel=1, p=8, theta=0.6, leaf_size=64, fp32=fp32)
+    st0 = pl0.stats()
+    pl0.close()
+    err, em = rel_l2(out[S], ref), elem_max(out[S], ref)
+    ev = sum(st["evals_" + k] for k in ("pp", "pc", "cp", "cc"))
+    ev0 = sum(st0["evals_" + k] for k in ("pp", "pc", "cp", "cc"))
+    print("clustered fp32=%s rel L2 %.3e elem_max %.3e evals %d (unshrunk %d)"
+          % (fp32, err, em, ev, ev0), flush=True)
+    assert err <= 1e-5 and em <= 1e-4
+    assert ev < ev0

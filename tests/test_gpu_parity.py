@@ -89,7 +89,7 @@ def test_direct_distinct_and_ragged():
 
 # ------------------------------------------------------------------ plan internals
 
-def _compare_tree(plan, otree, which):
+def _compare_tree(plan, otree, which, gtol=4e-16):
     c = plan.cells(which)
     n = len(otree.cells)
     assert c["level"].shape[0] == n
@@ -111,11 +111,14 @@ def _compare_tree(plan, otree, which):
         assert np.array_equal(got, np.sort(C.idx))
     cen = np.array([C.center for C in otree.cells])
     rad = np.array([C.radius for C in otree.cells])
-    assert np.max(np.abs(c["center"] - cen)) < 4e-16
-    assert np.max(np.abs(c["radius"] - rad) / rad) < 1e-14
+    assert np.max(np.abs(c["center"] - cen)) < gtol
+    if gtol <= 4e-16:
+        assert np.max(np.abs(c["radius"] - rad) / rad) < 1e-14
+    else:  # shrunk boxes: radii down to ~1e-7 (one point), compare absolutely
+        assert np.max(np.abs(c["radius"] - rad)) < gtol
     prox = plan.proxies(which)
     oprox = np.array([C.proxies for C in otree.cells])
-    assert np.max(np.abs(prox - oprox)) < 4e-16
+    assert np.max(np.abs(prox - oprox)) < gtol
 
 
 def _compare_lists(plan, ofmm):
@@ -146,7 +149,19 @@ CASES = {
     # components at p = 12 (LDS near its limit); PC (p = 14) and CC (p = 12) present
     "high_p14": lambda: (cubed_sphere_grid(32)[0], None, 1, 14, 0.5, 64),
     "bs_p12": lambda: (cubed_sphere_grid(32)[0], None, 2, 12, 0.6, 64),
+    # cluster shrinking (paper §3): boxes from the points, per-cell operators;
+    # a clustered cloud, distinct sets (both trees shrunk), and the
+    # one-wave-per-leaf near field with symmetric pairs
+    "clustered_shrink": lambda: (_clustered(), None, 1, 4, 0.5, 12, True),
+    "distinct_shrink": lambda: (random_sphere_points(3000, 41), cubed_sphere_grid(16)[0], 2, 6,
+                                0.6, 40, True),
+    "grid_E96_leaf16_shrink": lambda: (cubed_sphere_grid(96)[0], None, 3, 4, 0.7, 16, True),
 }
+
+
+def _case(name):
+    c = CASES[name]()
+    return c if len(c) == 7 else c + (False,)
 
 
 def _clustered():
@@ -158,20 +173,24 @@ def _clustered():
 @pytest.fixture(scope="module", params=sorted(CASES))
 def case(request):
     name = request.param
-    T, S, k, p, th, leaf = CASES[name]()
-    _announce("plan case %s: n_t=%d n_s=%s kernel=%d p=%d theta=%g leaf=%d"
-              % (name, T.shape[0], None if S is None else S.shape[0], k, p, th, leaf))
-    ofmm = F.FMM(T, S, k, p, th, leaf)
-    plan = cs.Plan(tdev(T), None if S is None else tdev(S), kernel=k, p=p, theta=th, leaf_size=leaf)
+    T, S, k, p, th, leaf, shrink = _case(name)
+    _announce("plan case %s: n_t=%d n_s=%s kernel=%d p=%d theta=%g leaf=%d shrink=%s"
+              % (name, T.shape[0], None if S is None else S.shape[0], k, p, th, leaf, shrink))
+    ofmm = F.FMM(T, S, k, p, th, leaf, shrink=shrink)
+    plan = cs.Plan(tdev(T), None if S is None else tdev(S), kernel=k, p=p, theta=th,
+                   leaf_size=leaf, shrink=shrink)
+    plan.shrink_case = shrink
     yield name, T, S, k, p, th, leaf, ofmm, plan
     plan.close()
 
 
 def test_tree_and_geometry(case):
     name, T, S, k, p, th, leaf, ofmm, plan = case
-    _compare_tree(plan, ofmm.ttree, 0)
+    # shrunk boxes come from the points' angles (atan on two sides: an ulp)
+    gtol = 2e-15 if plan.shrink_case else 4e-16
+    _compare_tree(plan, ofmm.ttree, 0, gtol)
     if S is not None:
-        _compare_tree(plan, ofmm.stree, 1)
+        _compare_tree(plan, ofmm.stree, 1, gtol)
 
 
 def test_lists(case):
@@ -199,7 +218,7 @@ def test_lists(case):
     assert (st["pp_sym_pairs"], st["pp_one_way"]) == (0, 0)  # FP64 form: not built
     pp = set((Tc.id, Sc.id) for Tc, Sc in ofmm.lists["PP"])
     p32 = cs.Plan(tdev(T), None if S is None else tdev(S), kernel=k, p=p, theta=th,
-                  leaf_size=leaf, fp32=True)
+                  leaf_size=leaf, fp32=True, shrink=plan.shrink_case)
     s32 = p32.stats()
     p32.close()
     if S is None:
@@ -221,7 +240,7 @@ def test_cases_cover_both_near_field_paths():
     the parity cases hold both."""
     got = {}
     for name in ("config1", "random_leaf100", "grid_E96_leaf16"):
-        T, S, k, p, th, leaf = CASES[name]()
+        T, S, k, p, th, leaf, _ = _case(name)
         pl = cs.Plan(tdev(T), None if S is None else tdev(S), kernel=k, p=p, theta=th,
                      leaf_size=leaf, fp32=True)
         got[name] = pl.stats()
@@ -268,7 +287,7 @@ def test_fp32_form_close_to_fp64(case):
     src = T if S is None else S
     w = np.random.default_rng(4).standard_normal(src.shape[0])
     plan32 = cs.Plan(tdev(T), None if S is None else tdev(S), kernel=k, p=p, theta=th,
-                     leaf_size=leaf, fp32=True)
+                     leaf_size=leaf, fp32=True, shrink=plan.shrink_case)
     a = host(plan.eval(tdev(w)))
     b = host(plan32.eval(tdev(w)))
     plan32.close()
@@ -286,7 +305,7 @@ def test_fp32_near_field_matches_oracle(case):
     w = np.random.default_rng(5).standard_normal(src.shape[0])
     ref, stg = ofmm.evaluate(w, stages=True)
     plan32 = cs.Plan(tdev(T), None if S is None else tdev(S), kernel=k, p=p, theta=th,
-                     leaf_size=leaf, fp32=True)
+                     leaf_size=leaf, fp32=True, shrink=plan.shrink_case)
     out, wbar, psi, near = plan32.eval_stages(tdev(w))
     near = host(near)
     again = host(plan32.eval(tdev(w)))
