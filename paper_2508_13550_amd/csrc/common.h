@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -73,6 +74,92 @@ struct DevArena {
         for (void* q : ptrs) (void)hipFree(q);
         ptrs.clear();
         bytes = 0;
+    }
+};
+
+// Several arena arrays in one hipMalloc: add() records where each array's
+// pointer goes and its size, commit() allocates the sum (each array starting
+// on a 256-byte boundary) and hands out the pointers.  `bytes` grows by what
+// is allocated, padding included.
+struct ArenaGroup {
+    struct Item {
+        void** p;
+        size_t b;
+    };
+    std::vector<Item> items;
+    template <class T>
+    void add(T** p, int64_t n) {
+        *p = nullptr;
+        items.push_back(Item{(void**)p, sizeof(T) * size_t(n > 0 ? n : 1)});
+    }
+    int commit(DevArena& A) {
+        size_t total = 0;
+        for (const Item& it : items) total += (it.b + 255) / 256 * 256;
+        char* base = nullptr;
+        int rc = A.alloc(&base, int64_t(total));
+        if (rc != CSFMM_OK) return rc;
+        size_t o = 0;
+        for (const Item& it : items) {
+            *it.p = base + o;
+            o += (it.b + 255) / 256 * 256;
+        }
+        items.clear();
+        return CSFMM_OK;
+    }
+};
+
+// Stream-ordered scratch for one build step: requests are carved (256-byte
+// aligned) from chunks taken with hipMallocAsync on the stream, and every
+// chunk goes back to the stream's pool when the object dies, after the work
+// queued before that point.  A request larger than half a chunk gets a chunk
+// of its own, so the open chunk keeps serving small requests.
+struct Scratch {
+    struct Chunk {
+        char* base;
+        size_t cap, used;
+    };
+    static constexpr size_t kChunk = size_t(8) << 20;
+    hipStream_t s;
+    std::vector<Chunk> chunks;  // the open chunk is the last one
+    explicit Scratch(hipStream_t st) : s(st) {}
+    Scratch(const Scratch&) = delete;
+    Scratch& operator=(const Scratch&) = delete;
+    int take(size_t cap, char** q) {
+        void* v = nullptr;
+        hipError_t e = hipMallocAsync(&v, cap, s);
+        if (e != hipSuccess) {
+            set_error("hipMallocAsync of %lld bytes failed: %s", (long long)cap,
+                      hipGetErrorString(e));
+            (void)hipGetLastError();
+            return CSFMM_E_OOM;
+        }
+        *q = static_cast<char*>(v);
+        return CSFMM_OK;
+    }
+    template <class T>
+    int get(T** p, int64_t n) {
+        *p = nullptr;
+        const size_t b = (sizeof(T) * size_t(n > 0 ? n : 1) + 255) / 256 * 256;
+        char* q = nullptr;
+        if (b > kChunk / 2) {  // a full chunk of its own, placed before the open one
+            int rc = take(b, &q);
+            if (rc != CSFMM_OK) return rc;
+            chunks.insert(chunks.empty() ? chunks.end() : chunks.end() - 1, Chunk{q, b, b});
+            *p = reinterpret_cast<T*>(q);
+            return CSFMM_OK;
+        }
+        if (chunks.empty() || chunks.back().cap - chunks.back().used < b) {
+            int rc = take(kChunk, &q);
+            if (rc != CSFMM_OK) return rc;
+            chunks.push_back(Chunk{q, kChunk, 0});
+        }
+        Chunk& c = chunks.back();
+        *p = reinterpret_cast<T*>(c.base + c.used);
+        c.used += b;
+        return CSFMM_OK;
+    }
+    ~Scratch() {
+        for (const Chunk& c : chunks) (void)hipFreeAsync(c.base, s);
     }
 };
 
@@ -313,10 +400,16 @@ namespace csfmm {
 
 // ---- building blocks (sort_scan.hip)
 // exclusive scan of n int32 values; writes the total to *d_total (device)
+// unless it is null; in == out is allowed
 int scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* d_total,
-                       hipStream_t s);
+                       Scratch& S, hipStream_t s);
+// exclusive scans of m arrays of n int32 values each (m <= 8), totals to
+// d_totals[0..m) (device); one launch when n is small
+int scan_exclusive_multi(const int32_t* const* in, int32_t* const* out, int m, int64_t n,
+                         int32_t* d_totals, Scratch& S, hipStream_t s);
 // stable LSD radix sort of (key, value) pairs on the low `bits` bits of the keys
-int radix_sort_u64(uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream_t s);
+int radix_sort_u64(uint64_t* keys, int32_t* vals, int64_t n, int bits, Scratch& S,
+                   hipStream_t s);
 
 // ---- plan (plan.hip)
 int build_plan(csfmm_plan_s* P, const double* targets, const double* sources, hipStream_t s);

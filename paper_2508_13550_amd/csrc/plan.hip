@@ -210,12 +210,45 @@ __global__ void k_children(const uint64_t* __restrict__ keys, int n, int level,
     }
 }
 
-__global__ void k_leaf_flags(const int32_t* __restrict__ child0, int n, int32_t* __restrict__ leaf,
-                             int32_t* __restrict__ parent) {
+// The cell arrays of every level of the breadth-first build.
+struct LevelArrays {
+    int32_t nlev;
+    int32_t first[kMaxLevel + 2];  // first cell of each level, then the end
+    const int32_t* face[kMaxLevel + 1];
+    const int32_t* ci[kMaxLevel + 1];
+    const int32_t* cj[kMaxLevel + 1];
+    const int32_t* begin[kMaxLevel + 1];
+    const int32_t* count[kMaxLevel + 1];
+    const int32_t* child0[kMaxLevel + 1];
+};
+
+// Concatenates the levels into the tree's cell arrays, with each cell's level,
+// its parent (a cell writes the entries of its four children; roots get -1)
+// and its leaf / parent flags for the compactions that follow.
+__global__ void k_gather_levels(LevelArrays L, int nc, int32_t* __restrict__ level,
+                                int32_t* __restrict__ face, int32_t* __restrict__ ci,
+                                int32_t* __restrict__ cj, int32_t* __restrict__ begin,
+                                int32_t* __restrict__ count, int32_t* __restrict__ child0,
+                                int32_t* __restrict__ parent, int32_t* __restrict__ leaf_flag,
+                                int32_t* __restrict__ parent_flag) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    leaf[k] = child0[k] < 0 ? 1 : 0;
-    parent[k] = child0[k] < 0 ? 0 : 1;
+    if (k >= nc) return;
+    int l = 0;
+    while (l + 1 < L.nlev && k >= L.first[l + 1]) ++l;
+    const int j = k - L.first[l];
+    const int c0 = L.child0[l][j];
+    level[k] = l;
+    face[k] = L.face[l][j];
+    ci[k] = L.ci[l][j];
+    cj[k] = L.cj[l][j];
+    begin[k] = L.begin[l][j];
+    count[k] = L.count[l][j];
+    child0[k] = c0;
+    if (l == 0) parent[k] = -1;
+    if (c0 >= 0)
+        for (int q = 0; q < 4; ++q) parent[c0 + q] = k;
+    leaf_flag[k] = c0 < 0 ? 1 : 0;
+    parent_flag[k] = c0 < 0 ? 0 : 1;
 }
 
 __global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
@@ -226,8 +259,6 @@ __global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
 __global__ void k_zero_u64(unsigned long long* p, int n) {
     if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
 }
-
-// *a = v
 
 // *a = *b = *c = 0 (the element past the entries of three kind arrays)
 __global__ void k_zero_i32x3(int32_t* __restrict__ a, int32_t* __restrict__ b,
@@ -337,15 +368,6 @@ __global__ void k_count_evals(int kind, const int32_t* __restrict__ off,
 }
 
 // parent[c] = the cell whose four children include c; -1 for the roots
-__global__ void k_parent_of(const int32_t* __restrict__ child0, int n, int32_t* __restrict__ parent) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    if (k < 6) parent[k] = -1;
-    const int c0 = child0[k];
-    if (c0 >= 0)
-        for (int q = 0; q < 4; ++q) parent[c0 + q] = k;
-}
-
 // Path from the root to every leaf (see Tree::leaf_anc).
 __global__ void k_leaf_paths(const int32_t* __restrict__ leaves, int nleaves,
                              const int32_t* __restrict__ parent, int32_t* __restrict__ anc) {
@@ -757,28 +779,6 @@ __global__ void k_far_flags(const int32_t* __restrict__ ocp, const int32_t* __re
 
 // ------------------------------------------------------------- host helpers
 
-struct Scratch {
-    hipStream_t s;
-    std::vector<void*> ptrs;
-    explicit Scratch(hipStream_t st) : s(st) {}
-    template <class T>
-    int get(T** p, int64_t n) {
-        if (n <= 0) n = 1;
-        hipError_t e = hipMallocAsync((void**)p, sizeof(T) * size_t(n), s);
-        if (e != hipSuccess) {
-            set_error("hipMallocAsync of %lld bytes failed: %s", (long long)(sizeof(T) * n),
-                      hipGetErrorString(e));
-            (void)hipGetLastError();
-            return CSFMM_E_OOM;
-        }
-        ptrs.push_back((void*)*p);
-        return CSFMM_OK;
-    }
-    ~Scratch() {
-        for (void* q : ptrs) (void)hipFreeAsync(q, s);
-    }
-};
-
 #define RC(x)                              \
     do {                                   \
         int rc_ = (x);                     \
@@ -807,13 +807,17 @@ int build_tree(csfmm_plan_s* P, Tree& T, const double* pts, int64_t n, hipStream
     RC(S.get(&eta, n));
     k_face_key<<<nblk(n), kT, 0, s>>>(pts, n, keys, idx, xi0, eta0);
     CSFMM_LAUNCH_CHECK();
-    RC(radix_sort_u64(keys, idx, n, 3 + 2 * kMaxLevel, s));
-    RC(A.alloc(&T.x, n));
-    RC(A.alloc(&T.y, n));
-    RC(A.alloc(&T.z, n));
-    RC(A.alloc(&T.u, n));
-    RC(A.alloc(&T.v, n));
-    RC(A.alloc(&T.perm, n));
+    RC(radix_sort_u64(keys, idx, n, 3 + 2 * kMaxLevel, S, s));
+    {
+        ArenaGroup G;
+        G.add(&T.x, n);
+        G.add(&T.y, n);
+        G.add(&T.z, n);
+        G.add(&T.u, n);
+        G.add(&T.v, n);
+        G.add(&T.perm, n);
+        RC(G.commit(A));
+    }
     k_gather_points<<<nblk(n), kT, 0, s>>>(pts, idx, xi0, eta0, n, T.x, T.y, T.z, xi, eta);
     CSFMM_LAUNCH_CHECK();
     CSFMM_HIP_TRY(hipMemcpyAsync(T.perm, idx, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
@@ -844,7 +848,7 @@ int build_tree(csfmm_plan_s* P, Tree& T, const double* pts, int64_t n, hipStream
         RC(S.get(&off, cur.n));
         k_split_flags<<<nblk(cur.n), kT, 0, s>>>(cur.count, cur.n, P->leaf, l, flag);
         CSFMM_LAUNCH_CHECK();
-        RC(scan_exclusive_i32(flag, off, cur.n, dtot, s));
+        RC(scan_exclusive_i32(flag, off, cur.n, dtot, S, s));
         int32_t nsplit = 0;
         RC(read_i32(dtot, &nsplit, s));
         Lev nx{4 * nsplit};
@@ -873,81 +877,94 @@ int build_tree(csfmm_plan_s* P, Tree& T, const double* pts, int64_t n, hipStream
     T.level_begin.assign(levs.size() + 1, 0);
     for (size_t l = 0; l < levs.size(); ++l) T.level_begin[l + 1] = T.level_begin[l] + levs[l].n;
     const int nc = T.ncells;
-    RC(A.alloc(&T.level, nc));
-    RC(A.alloc(&T.face, nc));
-    RC(A.alloc(&T.ci, nc));
-    RC(A.alloc(&T.cj, nc));
-    RC(A.alloc(&T.begin, nc));
-    RC(A.alloc(&T.count, nc));
-    RC(A.alloc(&T.child0, nc));
-    std::vector<int32_t> hl(nc);
-    for (size_t l = 0; l < levs.size(); ++l) {
-        const int32_t o = T.level_begin[l], m = levs[l].n;
-        for (int k = 0; k < m; ++k) hl[o + k] = int32_t(l);
-        const size_t b = sizeof(int32_t) * m;
-        CSFMM_HIP_TRY(hipMemcpyAsync(T.face + o, levs[l].face, b, hipMemcpyDeviceToDevice, s));
-        CSFMM_HIP_TRY(hipMemcpyAsync(T.ci + o, levs[l].ci, b, hipMemcpyDeviceToDevice, s));
-        CSFMM_HIP_TRY(hipMemcpyAsync(T.cj + o, levs[l].cj, b, hipMemcpyDeviceToDevice, s));
-        CSFMM_HIP_TRY(hipMemcpyAsync(T.begin + o, levs[l].begin, b, hipMemcpyDeviceToDevice, s));
-        CSFMM_HIP_TRY(hipMemcpyAsync(T.count + o, levs[l].count, b, hipMemcpyDeviceToDevice, s));
-        CSFMM_HIP_TRY(hipMemcpyAsync(T.child0 + o, levs[l].child0, b, hipMemcpyDeviceToDevice, s));
+    const bool shrink = (P->flags & CSFMM_SHRINK) != 0;
+    {
+        ArenaGroup G;
+        G.add(&T.level, nc);
+        G.add(&T.face, nc);
+        G.add(&T.ci, nc);
+        G.add(&T.cj, nc);
+        G.add(&T.begin, nc);
+        G.add(&T.count, nc);
+        G.add(&T.child0, nc);
+        G.add(&T.parent, nc);
+        G.add(&T.box, int64_t(4) * nc);
+        G.add(&T.center, int64_t(3) * nc);
+        G.add(&T.radius, nc);
+        G.add(&T.prox, int64_t(3) * P->KS * nc);
+        G.add(&T.gap, nc);
+        if (shrink) G.add(&T.ops, int64_t(nc) * 2 * (P->p + 1) * (P->p + 1));
+        RC(G.commit(A));
     }
-    CSFMM_HIP_TRY(hipMemcpyAsync(T.level, hl.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s));
-    CSFMM_HIP_TRY(hipStreamSynchronize(s));  // hl goes out of scope
-
-    // leaves and parents (non-leaf cells, grouped by level)
+    // cells of all levels in one array each; leaves and parents (non-leaf
+    // cells, grouped by level)
     int32_t *lf, *pf, *lo, *po;
     RC(S.get(&lf, nc));
     RC(S.get(&pf, nc));
     RC(S.get(&lo, nc));
     RC(S.get(&po, nc));
-    k_leaf_flags<<<nblk(nc), kT, 0, s>>>(T.child0, nc, lf, pf);
-    CSFMM_LAUNCH_CHECK();
-    RC(A.alloc(&T.parent, nc));
-    k_parent_of<<<nblk(nc), kT, 0, s>>>(T.child0, nc, T.parent);
-    CSFMM_LAUNCH_CHECK();
-    RC(scan_exclusive_i32(lf, lo, nc, dtot, s));
-    int32_t nleaves = 0;
-    RC(read_i32(dtot, &nleaves, s));
-    RC(scan_exclusive_i32(pf, po, nc, dtot, s));
-    int32_t nparents = 0;
-    RC(read_i32(dtot, &nparents, s));
+    {
+        if (levs.size() > size_t(kMaxLevel + 1)) {
+            set_error("tree deeper than %d levels", kMaxLevel);
+            return CSFMM_E_INTERNAL;
+        }
+        LevelArrays L{};
+        L.nlev = int32_t(levs.size());
+        for (size_t l = 0; l < levs.size(); ++l) {
+            L.first[l] = T.level_begin[l];
+            L.face[l] = levs[l].face;
+            L.ci[l] = levs[l].ci;
+            L.cj[l] = levs[l].cj;
+            L.begin[l] = levs[l].begin;
+            L.count[l] = levs[l].count;
+            L.child0[l] = levs[l].child0;
+        }
+        L.first[levs.size()] = nc;
+        k_gather_levels<<<nblk(nc), kT, 0, s>>>(L, nc, T.level, T.face, T.ci, T.cj, T.begin,
+                                                T.count, T.child0, T.parent, lf, pf);
+        CSFMM_LAUNCH_CHECK();
+    }
+    {
+        const int32_t* fin[2] = {lf, pf};
+        int32_t* fout[2] = {lo, po};
+        RC(scan_exclusive_multi(fin, fout, 2, nc, dtot, S, s));
+    }
+    // the two totals and the parents' offset at each level start, in one read
+    std::vector<int32_t> hpo(nc + 2);
+    CSFMM_HIP_TRY(hipMemcpyAsync(hpo.data(), po, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+    CSFMM_HIP_TRY(hipMemcpyAsync(hpo.data() + nc, dtot, sizeof(int32_t) * 2,
+                                 hipMemcpyDeviceToHost, s));
+    CSFMM_HIP_TRY(hipStreamSynchronize(s));
+    const int32_t nleaves = hpo[nc], nparents = hpo[nc + 1];
+    T.parents_begin.assign(levs.size() + 1, nparents);
+    for (size_t l = 0; l < levs.size(); ++l) T.parents_begin[l] = hpo[T.level_begin[l]];
     T.nleaves = nleaves;
-    RC(A.alloc(&T.leaves, nleaves));
-    RC(A.alloc(&T.parents, nparents));
+    {
+        ArenaGroup G;
+        G.add(&T.leaves, nleaves);
+        G.add(&T.parents, nparents);
+        G.add(&T.leaf_anc, int64_t(nleaves) * kAncStride);
+        RC(G.commit(A));
+    }
     k_compact<<<nblk(nc), kT, 0, s>>>(lf, lo, nc, T.leaves);
     k_compact<<<nblk(nc), kT, 0, s>>>(pf, po, nc, T.parents);
     CSFMM_LAUNCH_CHECK();
-    RC(A.alloc(&T.leaf_anc, int64_t(nleaves) * kAncStride));
     k_leaf_paths<<<nblk(nleaves), kT, 0, s>>>(T.leaves, nleaves, T.parent, T.leaf_anc);
     CSFMM_LAUNCH_CHECK();
-    // per-level offsets into `parents`: exclusive-scan value at each level start
-    std::vector<int32_t> hpo(nc);
-    CSFMM_HIP_TRY(hipMemcpyAsync(hpo.data(), po, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
-    CSFMM_HIP_TRY(hipStreamSynchronize(s));
-    T.parents_begin.assign(levs.size() + 1, nparents);
-    for (size_t l = 0; l < levs.size(); ++l) T.parents_begin[l] = hpo[T.level_begin[l]];
 
     // boxes (cells, or shrunk), geometry and proxies
-    const bool shrink = (P->flags & CSFMM_SHRINK) != 0;
-    RC(A.alloc(&T.box, int64_t(4) * nc));
     k_cell_box<<<nc, 128, 0, s>>>(nc, T.level, T.ci, T.cj, T.begin, T.count, xi, eta, shrink,
                                   T.box);
     CSFMM_LAUNCH_CHECK();
-    RC(A.alloc(&T.center, int64_t(3) * nc));
-    RC(A.alloc(&T.radius, nc));
-    RC(A.alloc(&T.prox, int64_t(3) * P->KS * nc));
     k_cell_geometry<<<nc, 128, 0, s>>>(nc, T.face, T.box, P->p, P->KS, T.center, T.radius,
                                        T.prox);
     CSFMM_LAUNCH_CHECK();
-    RC(A.alloc(&T.gap, nc));
     k_fill_f64<<<nblk(nc), kT, 0, s>>>(T.gap, nc, 0.0);
     k_leaf_local<<<nleaves, 128, 0, s>>>(T.leaves, nleaves, T.level, T.ci, T.cj, T.begin, T.count,
                                          xi, eta, T.box, T.u, T.v, T.gap);
     CSFMM_LAUNCH_CHECK();
     if (shrink) {
         const int64_t K = int64_t(P->p + 1) * (P->p + 1);
-        RC(A.alloc(&T.ops, int64_t(nc) * 2 * K));
         k_cell_ops<<<nblk(int64_t(nc) * 2 * K), kT, 0, s>>>(nc, P->p, T.parent, T.box, T.ops);
         CSFMM_LAUNCH_CHECK();
     }
@@ -962,11 +979,19 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
     TravTree tt{T.level, T.count, T.child0, T.center, T.radius};
     TravTree st{Sx.level, Sx.count, Sx.child0, Sx.center, Sx.radius};
 
-    struct Chunk {
-        int32_t *t, *s;
-        int32_t n;
+    // the four lists grow in place: each traversal step appends its pairs of
+    // each kind, and a full buffer moves to one of twice the size
+    struct Grow {
+        int32_t *t = nullptr, *s = nullptr;
+        int64_t n = 0, cap = 0;
     };
-    std::vector<Chunk> out[4];
+    Grow out[4];
+    const int64_t cap0 = 16 * int64_t(std::max(T.ncells, Sx.ncells)) + 1024;
+    for (int k = 0; k < 4; ++k) {
+        RC(S.get(&out[k].t, cap0));
+        RC(S.get(&out[k].s, cap0));
+        out[k].cap = cap0;
+    }
     int32_t *ft, *fs;
     int32_t nf = 36;
     RC(S.get(&ft, nf));
@@ -974,7 +999,7 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
     k_root_pairs<<<1, 64, 0, s>>>(ft, fs);
     CSFMM_LAUNCH_CHECK();
     int32_t* dtot;
-    RC(S.get(&dtot, 5));
+    RC(S.get(&dtot, 8));
     for (int iter = 0; nf > 0; ++iter) {
         if (iter > 4 * kMaxLevel + 8) {
             set_error("traversal did not terminate");
@@ -989,67 +1014,76 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
         k_classify<<<nblk(nf), kT, 0, s>>>(ft, fs, nf, tt, st, P->theta, act, c[0], c[1], c[2],
                                            c[3], c[4]);
         CSFMM_LAUNCH_CHECK();
-        for (int k = 0; k < 5; ++k) RC(scan_exclusive_i32(c[k], o[k], nf, dtot + k, s));
+        RC(scan_exclusive_multi(c, o, 5, nf, dtot, S, s));
         int32_t tot[5];
         CSFMM_HIP_TRY(hipMemcpyAsync(tot, dtot, sizeof(tot), hipMemcpyDeviceToHost, s));
         CSFMM_HIP_TRY(hipStreamSynchronize(s));
-        Chunk ch[4];
         for (int k = 0; k < 4; ++k) {
-            ch[k].n = tot[k];
-            RC(S.get(&ch[k].t, tot[k]));
-            RC(S.get(&ch[k].s, tot[k]));
-            if (tot[k] > 0) out[k].push_back(ch[k]);
+            Grow& g = out[k];
+            if (g.n + tot[k] <= g.cap) continue;
+            const int64_t cap = std::max<int64_t>(2 * g.cap, g.n + tot[k]);
+            int32_t *t2, *s2;
+            RC(S.get(&t2, cap));
+            RC(S.get(&s2, cap));
+            if (g.n > 0) {
+                CSFMM_HIP_TRY(hipMemcpyAsync(t2, g.t, sizeof(int32_t) * g.n,
+                                             hipMemcpyDeviceToDevice, s));
+                CSFMM_HIP_TRY(hipMemcpyAsync(s2, g.s, sizeof(int32_t) * g.n,
+                                             hipMemcpyDeviceToDevice, s));
+            }
+            g.t = t2;
+            g.s = s2;
+            g.cap = cap;
         }
         int32_t *nt, *ns;
         RC(S.get(&nt, tot[4]));
         RC(S.get(&ns, tot[4]));
         k_emit<<<nblk(nf), kT, 0, s>>>(ft, fs, nf, act, o[0], o[1], o[2], o[3], o[4], T.child0,
-                                       Sx.child0, ch[0].t, ch[0].s, ch[1].t, ch[1].s, ch[2].t,
-                                       ch[2].s, ch[3].t, ch[3].s, nt, ns,
+                                       Sx.child0, out[0].t + out[0].n, out[0].s + out[0].n,
+                                       out[1].t + out[1].n, out[1].s + out[1].n,
+                                       out[2].t + out[2].n, out[2].s + out[2].n,
+                                       out[3].t + out[3].n, out[3].s + out[3].n, nt, ns,
                                        Caps{{tot[0], tot[1], tot[2], tot[3], tot[4]}});
         CSFMM_LAUNCH_CHECK();
+        for (int k = 0; k < 4; ++k) out[k].n += tot[k];
         ft = nt;
         fs = ns;
         nf = tot[4];
     }
 
-    // concatenate, sort by (target, source), CSR by target cell
+    // sort by (target, source), CSR by target cell
     const int64_t nsc = Sx.ncells;
     const int64_t maxkey = int64_t(T.ncells) * 3 * nsc;
     const CellIds tcid{T.level, T.face, T.ci, T.cj};
     const CellIds scid{Sx.level, Sx.face, Sx.ci, Sx.cj};
     const CloseGeom cg{T.gap, Sx.gap, T.radius, Sx.radius};
     const bool classify_close = (P->flags & CSFMM_FP32_FORM) != 0;
-    RC(A.alloc(&P->lists.novl, T.ncells));
-    RC(A.alloc(&P->lists.ncl, T.ncells));
+    {
+        ArenaGroup G;
+        G.add(&P->lists.novl, T.ncells);
+        G.add(&P->lists.ncl, T.ncells);
+        for (int k = 0; k < 4; ++k) {
+            P->lists.cnt[k] = out[k].n;
+            G.add(&P->lists.off[k], int64_t(T.ncells) + 1);
+            G.add(&P->lists.src[k], out[k].n);
+        }
+        RC(G.commit(A));
+    }
     int bits = 1;
     while (bits < 63 && (int64_t(1) << bits) < maxkey) ++bits;
     for (int k = 0; k < 4; ++k) {
-        int64_t cnt = 0;
-        for (auto& c : out[k]) cnt += c.n;
-        P->lists.cnt[k] = cnt;
-        int32_t *lt, *ls;
-        RC(S.get(&lt, cnt));
-        RC(S.get(&ls, cnt));
-        int64_t pos = 0;
-        for (auto& c : out[k]) {
-            CSFMM_HIP_TRY(hipMemcpyAsync(lt + pos, c.t, sizeof(int32_t) * c.n, hipMemcpyDeviceToDevice, s));
-            CSFMM_HIP_TRY(hipMemcpyAsync(ls + pos, c.s, sizeof(int32_t) * c.n, hipMemcpyDeviceToDevice, s));
-            pos += c.n;
-        }
+        const int64_t cnt = out[k].n;
         uint64_t* keys;
         int32_t* vals;
         RC(S.get(&keys, cnt));
         RC(S.get(&vals, cnt));
         if (cnt > 0) {
-            k_pair_keys<<<nblk(cnt), kT, 0, s>>>(lt, ls, cnt, nsc, k == kPP,
+            k_pair_keys<<<nblk(cnt), kT, 0, s>>>(out[k].t, out[k].s, cnt, nsc, k == kPP,
                                                  k == kPP && classify_close, tcid, scid, cg,
                                                  keys, vals);
             CSFMM_LAUNCH_CHECK();
-            RC(radix_sort_u64(keys, vals, cnt, bits, s));
+            RC(radix_sort_u64(keys, vals, cnt, bits, S, s));
         }
-        RC(A.alloc(&P->lists.off[k], int64_t(T.ncells) + 1));
-        RC(A.alloc(&P->lists.src[k], cnt));
         const int64_t m = std::max<int64_t>(cnt, int64_t(T.ncells) + 1);
         k_csr_from_keys<<<nblk(m), kT, 0, s>>>(keys, cnt, nsc, T.ncells, P->lists.off[k],
                                                P->lists.src[k],
@@ -1063,13 +1097,7 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
     RC(S.get(&fo, T.ncells));
     k_far_flags<<<nblk(T.ncells), kT, 0, s>>>(P->lists.off[kCP], P->lists.off[kCC], T.ncells, ff);
     CSFMM_LAUNCH_CHECK();
-    RC(scan_exclusive_i32(ff, fo, T.ncells, dtot, s));
-    int32_t nfar = 0;
-    RC(read_i32(dtot, &nfar, s));
-    P->lists.n_far_targets = nfar;
-    RC(A.alloc(&P->lists.far_targets, nfar));
-    k_compact<<<nblk(T.ncells), kT, 0, s>>>(ff, fo, T.ncells, P->lists.far_targets);
-    CSFMM_LAUNCH_CHECK();
+    RC(scan_exclusive_i32(ff, fo, T.ncells, dtot, S, s));
 
     // evaluation counts of the four lists (integer sums on the device)
     unsigned long long* dev_ev;
@@ -1084,20 +1112,15 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
     // and the largest target leaf (selects the near-field tile path)
     k_max_leaf<<<nblk(T.nleaves), kT, 0, s>>>(T.leaves, T.nleaves, T.count, dev_ev + 4);
     CSFMM_LAUNCH_CHECK();
-    unsigned long long hev[6];
-    CSFMM_HIP_TRY(hipMemcpyAsync(hev, dev_ev, sizeof(hev), hipMemcpyDeviceToHost, s));
-    CSFMM_HIP_TRY(hipStreamSynchronize(s));
-    for (int k = 0; k < 4; ++k) P->lists.evals[k] = int64_t(hev[k]);
-    T.max_leaf = int32_t(hev[4]);
-    P->lists.n_close = int64_t(hev[5]);
 
     // symmetric split of the PP entries (same-set plans in the FP32 form, the
-    // form whose evals use it)
-    if (P->same && (P->flags & CSFMM_FP32_FORM)) {
-        SymPP& Y = P->lists.sym;
-        const int nc = T.ncells;
-        const int64_t ne = P->lists.cnt[kPP];
-        int32_t *ko, *kr, *k1, *rev, *eo, *er, *e1;
+    // form whose evals use it): kinds and their scans now, the fill after the read
+    const bool sym = P->same && (P->flags & CSFMM_FP32_FORM);
+    const int nc = T.ncells;
+    const int64_t ne = P->lists.cnt[kPP];
+    int32_t *ko = nullptr, *kr = nullptr, *k1 = nullptr, *rev = nullptr;
+    int32_t *eo = nullptr, *er = nullptr, *e1 = nullptr;
+    if (sym) {
         RC(S.get(&ko, ne + 1));
         RC(S.get(&kr, ne + 1));
         RC(S.get(&k1, ne + 1));
@@ -1105,33 +1128,55 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
         RC(S.get(&eo, ne + 1));
         RC(S.get(&er, ne + 1));
         RC(S.get(&e1, ne + 1));
-        const int32_t *off = P->lists.off[kPP], *src = P->lists.src[kPP];
         k_zero_i32x3<<<1, 1, 0, s>>>(ko + ne, kr + ne, k1 + ne);
-        k_sym_kinds<<<nblk(int64_t(nc) * 64), kT, 0, s>>>(nc, off, src, P->lists.novl,
-                                                          P->lists.ncl, ko, kr, k1, rev);
+        k_sym_kinds<<<nblk(int64_t(nc) * 64), kT, 0, s>>>(nc, P->lists.off[kPP], P->lists.src[kPP],
+                                                          P->lists.novl, P->lists.ncl, ko, kr, k1,
+                                                          rev);
         CSFMM_LAUNCH_CHECK();
-        int32_t tot[3];
-        RC(scan_exclusive_i32(ko, eo, ne + 1, dtot, s));
-        RC(read_i32(dtot, &tot[0], s));
-        RC(scan_exclusive_i32(kr, er, ne + 1, dtot, s));
-        RC(read_i32(dtot, &tot[1], s));
-        RC(scan_exclusive_i32(k1, e1, ne + 1, dtot, s));
-        RC(read_i32(dtot, &tot[2], s));
-        if (tot[0] != tot[1]) {
-            set_error("symmetric PP pairs: %d owned but %d received", tot[0], tot[1]);
-            return CSFMM_E_HIP;
+        const int32_t* kin[3] = {ko, kr, k1};
+        int32_t* kout[3] = {eo, er, e1};
+        RC(scan_exclusive_multi(kin, kout, 3, ne + 1, dtot + 1, S, s));
+    }
+
+    // one read: far targets, the sym totals, the evaluation counts
+    struct {
+        int32_t tot[4];
+        unsigned long long ev[6];
+    } h;
+    CSFMM_HIP_TRY(hipMemcpyAsync(h.tot, dtot, sizeof(h.tot), hipMemcpyDeviceToHost, s));
+    CSFMM_HIP_TRY(hipMemcpyAsync(h.ev, dev_ev, sizeof(h.ev), hipMemcpyDeviceToHost, s));
+    CSFMM_HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < 4; ++k) P->lists.evals[k] = int64_t(h.ev[k]);
+    T.max_leaf = int32_t(h.ev[4]);
+    P->lists.n_close = int64_t(h.ev[5]);
+    const int32_t nfar = h.tot[0];
+    P->lists.n_far_targets = nfar;
+    SymPP& Y = P->lists.sym;
+    {
+        ArenaGroup G;
+        G.add(&P->lists.far_targets, nfar);
+        if (sym) {
+            if (h.tot[1] != h.tot[2]) {
+                set_error("symmetric PP pairs: %d owned but %d received", h.tot[1], h.tot[2]);
+                return CSFMM_E_INTERNAL;
+            }
+            Y.n_own = h.tot[1];
+            Y.n_one = h.tot[3];
+            G.add(&Y.own_off, int64_t(nc) + 1);
+            G.add(&Y.recv_off, int64_t(nc) + 1);
+            G.add(&Y.one_off, int64_t(nc) + 1);
+            G.add(&Y.own_src, Y.n_own);
+            G.add(&Y.recv_slot, Y.n_own);
+            G.add(&Y.one_src, Y.n_one);
         }
-        Y.n_own = tot[0];
-        Y.n_one = tot[2];
-        RC(A.alloc(&Y.own_off, int64_t(nc) + 1));
-        RC(A.alloc(&Y.recv_off, int64_t(nc) + 1));
-        RC(A.alloc(&Y.one_off, int64_t(nc) + 1));
-        RC(A.alloc(&Y.own_src, std::max<int64_t>(Y.n_own, 1)));
-        RC(A.alloc(&Y.recv_slot, std::max<int64_t>(Y.n_own, 1)));
-        RC(A.alloc(&Y.one_src, std::max<int64_t>(Y.n_one, 1)));
+        RC(G.commit(A));
+    }
+    k_compact<<<nblk(T.ncells), kT, 0, s>>>(ff, fo, T.ncells, P->lists.far_targets);
+    CSFMM_LAUNCH_CHECK();
+    if (sym) {
         k_sym_fill<<<nblk(std::max<int64_t>(ne, int64_t(nc) + 1)), kT, 0, s>>>(
-            nc, ne, off, src, ko, kr, k1, rev, eo, er, e1, Y.own_off, Y.own_src, Y.recv_off,
-            Y.recv_slot, Y.one_off, Y.one_src);
+            nc, ne, P->lists.off[kPP], P->lists.src[kPP], ko, kr, k1, rev, eo, er, e1, Y.own_off,
+            Y.own_src, Y.recv_off, Y.recv_slot, Y.one_off, Y.one_src);
         CSFMM_LAUNCH_CHECK();
         Y.on = true;
     }

@@ -1,9 +1,13 @@
 // Device-wide exclusive scan and stable LSD radix sort for wave64 (gfx950).
 //
-// Scan: three passes (block sums, scan of the block sums in one workgroup,
-// block scans plus offsets).  Sort: 8-bit digits; per pass a digit histogram
-// per tile, a scan of the [digit][tile] counts, and a stable scatter in which
-// each wavefront ranks equal digits with eight ballots.
+// Scan: up to 65,536 values in one launch (one 1024-thread workgroup per
+// array walks the array in tiles of 8,192, carrying the running sum), beyond
+// that three passes (block sums, scan of the block sums in one workgroup,
+// block scans plus offsets).  Plan building runs many short scans (cells of a
+// level, traversal frontiers, digit counts), where the launches, not the
+// bytes, are the cost.  Sort: 8-bit digits; per pass a digit histogram per
+// tile, a scan of the [digit][tile] counts, and a stable scatter in which each
+// wavefront ranks equal digits with eight ballots.
 #include "common.h"
 
 namespace csfmm {
@@ -28,6 +32,63 @@ __device__ int block_inclusive_scan(int v, int* lds_wave /*[4]*/) {
     for (int w = 0; w < wave; ++w) off += lds_wave[w];
     __syncthreads();
     return v + off;
+}
+
+// Small scans: one workgroup per array, tiles of kSmallTile values.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallItems = 8;
+constexpr int kSmallTile = kSmallThreads * kSmallItems;
+constexpr int64_t kSmallMax = int64_t(kSmallTile) * 8;
+constexpr int kMaxArrays = 8;
+
+struct ScanArrays {
+    const int32_t* in[kMaxArrays];
+    int32_t* out[kMaxArrays];
+};
+
+// Each thread scans its own kSmallItems consecutive values and writes only
+// them, after reading them, so in == out is safe.
+__global__ __launch_bounds__(kSmallThreads) void k_scan_small(ScanArrays a, int64_t n,
+                                                              int32_t* __restrict__ totals) {
+    __shared__ int lw[kSmallThreads / 64];
+    const int32_t* in = a.in[blockIdx.x];
+    int32_t* out = a.out[blockIdx.x];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int carry = 0;
+    for (int64_t t0 = 0; t0 < n; t0 += kSmallTile) {
+        const int64_t base = t0 + int64_t(threadIdx.x) * kSmallItems;
+        int v[kSmallItems];
+        int s = 0;
+#pragma unroll
+        for (int k = 0; k < kSmallItems; ++k) {
+            v[k] = (base + k < n) ? in[base + k] : 0;
+            s += v[k];
+        }
+        int inc = s;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += t;
+        }
+        if (lane == 63) lw[wave] = inc;
+        __syncthreads();
+        int off = 0, tile = 0;
+        for (int w = 0; w < kSmallThreads / 64; ++w) {
+            const int x = lw[w];
+            off += (w < wave) ? x : 0;
+            tile += x;
+        }
+        __syncthreads();
+        int run = carry + off + inc - s;
+#pragma unroll
+        for (int k = 0; k < kSmallItems; ++k) {
+            if (base + k < n) out[base + k] = run;
+            run += v[k];
+        }
+        carry += tile;
+    }
+    if (threadIdx.x == 0 && totals) totals[blockIdx.x] = carry;
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __restrict__ in,
@@ -155,44 +216,62 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_scatter(
 
 }  // namespace
 
-int scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* d_total,
-                       hipStream_t s) {
+int scan_exclusive_multi(const int32_t* const* in, int32_t* const* out, int m, int64_t n,
+                         int32_t* d_totals, Scratch& S, hipStream_t s) {
+    if (m < 1 || m > kMaxArrays) {
+        set_error("scan of %d arrays (1..%d)", m, kMaxArrays);
+        return CSFMM_E_INTERNAL;
+    }
     if (n <= 0) {
-        if (d_total) CSFMM_HIP_TRY(hipMemsetAsync(d_total, 0, sizeof(int32_t), s));
+        if (d_totals) CSFMM_HIP_TRY(hipMemsetAsync(d_totals, 0, sizeof(int32_t) * m, s));
+        return CSFMM_OK;
+    }
+    if (n <= kSmallMax) {
+        ScanArrays a{};
+        for (int k = 0; k < m; ++k) {
+            a.in[k] = in[k];
+            a.out[k] = out[k];
+        }
+        k_scan_small<<<dim3(unsigned(m)), dim3(kSmallThreads), 0, s>>>(a, n, d_totals);
+        CSFMM_LAUNCH_CHECK();
         return CSFMM_OK;
     }
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    int32_t* sums = nullptr;
-    CSFMM_HIP_TRY(hipMallocAsync((void**)&sums, sizeof(int32_t) * nb, s));
-    k_scan_reduce<<<dim3(unsigned(nb)), dim3(kScanThreads), 0, s>>>(in, n, sums);
-    k_scan_sums<<<1, kScanThreads, 0, s>>>(sums, nb, d_total);
-    k_scan_apply<<<dim3(unsigned(nb)), dim3(kScanThreads), 0, s>>>(in, out, n, sums);
-    hipError_t e = hipGetLastError();
-    (void)hipFreeAsync(sums, s);
-    if (e != hipSuccess) {
-        set_error("scan launch failed: %s", hipGetErrorString(e));
-        return CSFMM_E_HIP;
+    for (int k = 0; k < m; ++k) {
+        int32_t* sums = nullptr;
+        int rc = S.get(&sums, nb);
+        if (rc != CSFMM_OK) return rc;
+        k_scan_reduce<<<dim3(unsigned(nb)), dim3(kScanThreads), 0, s>>>(in[k], n, sums);
+        k_scan_sums<<<1, kScanThreads, 0, s>>>(sums, nb, d_totals ? d_totals + k : nullptr);
+        k_scan_apply<<<dim3(unsigned(nb)), dim3(kScanThreads), 0, s>>>(in[k], out[k], n, sums);
+        CSFMM_LAUNCH_CHECK();
     }
     return CSFMM_OK;
 }
 
-int radix_sort_u64(uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream_t s) {
+int scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* d_total,
+                       Scratch& S, hipStream_t s) {
+    return scan_exclusive_multi(&in, &out, 1, n, d_total, S, s);
+}
+
+int radix_sort_u64(uint64_t* keys, int32_t* vals, int64_t n, int bits, Scratch& S,
+                   hipStream_t s) {
     if (n <= 1) return CSFMM_OK;
     const int passes = (bits + 7) / 8;
     const int64_t nb = (n + kSortTile - 1) / kSortTile;
     uint64_t* k2 = nullptr;
     int32_t* v2 = nullptr;
     int32_t* hist = nullptr;
-    CSFMM_HIP_TRY(hipMallocAsync((void**)&k2, sizeof(uint64_t) * n, s));
-    CSFMM_HIP_TRY(hipMallocAsync((void**)&v2, sizeof(int32_t) * n, s));
-    CSFMM_HIP_TRY(hipMallocAsync((void**)&hist, sizeof(int32_t) * 256 * nb, s));
+    int rc = S.get(&k2, n);
+    if (rc == CSFMM_OK) rc = S.get(&v2, n);
+    if (rc == CSFMM_OK) rc = S.get(&hist, 256 * nb);
+    if (rc != CSFMM_OK) return rc;
     uint64_t *ka = keys, *kb = k2;
     int32_t *va = vals, *vb = v2;
-    int rc = CSFMM_OK;
     for (int p = 0; p < passes && rc == CSFMM_OK; ++p) {
         const int shift = 8 * p;
         k_digit_hist<<<dim3(unsigned(nb)), dim3(kSortThreads), 0, s>>>(ka, n, shift, nb, hist);
-        rc = scan_exclusive_i32(hist, hist, 256 * nb, nullptr, s);
+        rc = scan_exclusive_i32(hist, hist, 256 * nb, nullptr, S, s);
         if (rc != CSFMM_OK) break;
         k_digit_scatter<<<dim3(unsigned(nb)), dim3(kSortThreads), 0, s>>>(ka, va, kb, vb, n, shift,
                                                                           nb, hist);
@@ -212,9 +291,6 @@ int radix_sort_u64(uint64_t* keys, int32_t* vals, int64_t n, int bits, hipStream
             rc = CSFMM_E_HIP;
         }
     }
-    (void)hipFreeAsync(k2, s);
-    (void)hipFreeAsync(v2, s);
-    (void)hipFreeAsync(hist, s);
     return rc;
 }
 
