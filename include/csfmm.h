@@ -92,11 +92,12 @@ typedef struct csfmm_stats {
     int64_t evals_pp, evals_pc, evals_cp, evals_cc; /* kernel evaluations per eval */
     int64_t device_bytes;                  /* device memory the plan holds */
     int64_t max_leaf_t;                    /* most points in a target leaf */
-    int64_t pp_sym_pairs, pp_one_way;      /* same-set FP32-form plans: PP entries of distinct
-                                              leaves that hold both ways, counted once
-                                              per pair, and those that hold one way
-                                              (the FP32 form evaluates a pair once for
-                                              both directions); 0 otherwise */
+    int64_t pp_sym_pairs, pp_one_way;      /* same-set plans: PP entries of distinct leaves
+                                              that hold both ways, counted once per pair,
+                                              and those that hold one way (on the
+                                              one-wave-per-leaf near field the scalar
+                                              kernels evaluate a pair once for both
+                                              directions); 0 otherwise */
     int64_t pp_close;                      /* FP32 form: PP entries of non-overlapping
                                               leaves whose points may come so close that
                                               the expanded squared distance would lose

@@ -232,7 +232,7 @@ int64_t csfmm_estimate_bytes(int64_t n_t, int64_t n_s, int p, int leaf_size, uns
     b += cs * KS * 8 + 3 * ct * KS * 8;          // proxy weights, proxy potentials
     b += 4 * (ct + 1) * 4 * 4 + ct * 4 * 160;    // list offsets and entries (~40 per cell per kind)
     b += (ct + cs) * 8 + ct * 2 * 4;             // leaf gaps, PP heads (overlapping, close)
-    if (flags & CSFMM_FP32_FORM) b += ct * 4 * (3 + 64);  // symmetric PP split of same-set plans
+    b += ct * 4 * (3 + 64);                      // symmetric PP split (same-set plans)
     b += 8 * KS * round_up(4 * KS, 16) * 8;      // interpolation operators
     return b;
 }
@@ -266,7 +266,7 @@ int64_t csfmm_workspace_bytes(csfmm_plan_t plan) {
                      int64_t(3) * plan->tt.ncells * plan->KS + int64_t(6) * plan->nt) +
                 int64_t(sizeof(csfmm::ReqView));
     if (csfmm::sym_path_possible(plan))
-        b += int64_t(sizeof(float)) * plan->lists.sym.n_own * csfmm::kWaveLeaf;
+        b += csfmm::sym_value_bytes(plan) * plan->lists.sym.n_own * csfmm::kWaveLeaf;
     return b;
 }
 

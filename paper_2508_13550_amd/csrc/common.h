@@ -249,8 +249,9 @@ struct ReqView {
     int32_t p, K, KS, nb1;
     int32_t nleaves_t, nleaves_s;
     // symmetric PP split (SymPP) and its column-sum slots [n_own][kWaveLeaf]
+    // (float in the FP32 form, double in FP64)
     const int32_t *own_off, *own_src, *recv_off, *recv_slot, *one_off, *one_src;
-    float* sym_col;
+    void* sym_col;
 };
 
 // Target leaves of at most this many points take the one-wave-per-leaf path of
@@ -352,7 +353,8 @@ struct csfmm_workspace_s {
     double* psi = nullptr;      // [3][ncells_t][KS]
     double* phinear = nullptr;  // [3][nt] PP near field
     double* phipc = nullptr;    // [3][nt] PC near field
-    float* sym_col = nullptr;   // [n_own][kWaveLeaf] column sums of symmetric PP pairs
+    void* sym_col = nullptr;    // [n_own][kWaveLeaf] column sums of symmetric PP pairs
+                                // (float in the FP32 form, double in FP64)
     csfmm::ReqView* dview = nullptr;  // device copy of dview_host
     csfmm::ReqView dview_host{};
     // side stream of the PP near field, with its fork and join events
@@ -384,12 +386,15 @@ inline bool leaf_wave_path(const csfmm::Tree& tt) {
     return tt.max_leaf <= kWaveLeaf && int64_t(tt.nleaves) >= 8 * int64_t(device_cus());
 }
 
-// The symmetric PP path: same-set plan in the FP32 form whose target leaves
-// take the one-wave-per-leaf path; an eval uses it for the scalar kernels
+// The symmetric PP path: same-set plan (either form) whose target leaves take
+// the one-wave-per-leaf path; an eval uses it for the scalar kernels
 // (K(x, y) = K(y, x)), not for Biot-Savart.
 inline bool sym_path_possible(const csfmm_plan_s* P) {
-    return P->lists.sym.on && (P->flags & CSFMM_FP32_FORM) && leaf_wave_path(P->tt) &&
-           P->lists.sym.n_own > 0;
+    return P->lists.sym.on && leaf_wave_path(P->tt) && P->lists.sym.n_own > 0;
+}
+// bytes of one column-sum value of the symmetric PP path
+inline int64_t sym_value_bytes(const csfmm_plan_s* P) {
+    return (P->flags & CSFMM_FP32_FORM) ? 4 : 8;
 }
 inline bool sym_path(const csfmm_plan_s* P, int kernel) {
     return sym_path_possible(P) && kernel != CSFMM_K_BIOT_SAVART;
@@ -436,7 +441,7 @@ int run_treecode(csfmm_plan_s* P, int kernel, const double* weights, double* out
 
 // ---- tile engine (tile.hip): b holds requests of one kernel and form
 int launch_tile_batch(const Batch& b, int kernel, bool fp32, hipStream_t s);
-int launch_sym_merge(const Batch& b, int kernel, hipStream_t s);
+int launch_sym_merge(const Batch& b, int kernel, bool fp32, hipStream_t s);
 
 // Cubed sphere treecode (paper §7, Algorithm 1): one traversal of the source
 // tree per target particle, FP64.

@@ -701,7 +701,7 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
             // column sums of the symmetric pairs, once every pair is done
             bool any_sym = false;
             for (int q = 0; q < g.n; ++q) any_sym = any_sym || g.sym[q];
-            if (any_sym) RCX(launch_sym_merge(g, kv.first.first, side));
+            if (any_sym) RCX(launch_sym_merge(g, kv.first.first, kv.first.second != 0, side));
         }
         RCX(mark(Timing::kMain + 1));
         CSFMM_HIP_TRY(hipEventRecord(W0->join, side));
@@ -820,8 +820,11 @@ int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** ou
     if (rc == CSFMM_OK) rc = W->arena.alloc(&W->psi, int64_t(3) * T.ncells * P->KS);
     if (rc == CSFMM_OK) rc = W->arena.alloc(&W->phinear, int64_t(3) * P->nt);
     if (rc == CSFMM_OK) rc = W->arena.alloc(&W->phipc, int64_t(3) * P->nt);
-    if (rc == CSFMM_OK && sym_path_possible(P))
-        rc = W->arena.alloc(&W->sym_col, P->lists.sym.n_own * kWaveLeaf);
+    if (rc == CSFMM_OK && sym_path_possible(P)) {
+        char* c = nullptr;
+        rc = W->arena.alloc(&c, sym_value_bytes(P) * P->lists.sym.n_own * kWaveLeaf);
+        W->sym_col = c;
+    }
     if (rc == CSFMM_OK) rc = W->arena.alloc(&W->dview, 1);
     if (rc != CSFMM_OK) {
         delete W;

@@ -1113,9 +1113,9 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
     k_max_leaf<<<nblk(T.nleaves), kT, 0, s>>>(T.leaves, T.nleaves, T.count, dev_ev + 4);
     CSFMM_LAUNCH_CHECK();
 
-    // symmetric split of the PP entries (same-set plans in the FP32 form, the
-    // form whose evals use it): kinds and their scans now, the fill after the read
-    const bool sym = P->same && (P->flags & CSFMM_FP32_FORM);
+    // symmetric split of the PP entries (same-set plans): kinds and their
+    // scans now, the fill after the read
+    const bool sym = P->same;
     const int nc = T.ncells;
     const int64_t ne = P->lists.cnt[kPP];
     int32_t *ko = nullptr, *kr = nullptr, *k1 = nullptr, *rev = nullptr;

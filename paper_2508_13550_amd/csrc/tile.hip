@@ -712,82 +712,141 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
 }
 
 // One wave's LDS on the symmetric PP path: one partner leaf staged (up to 64
-// sources) and a 64 x 16 tile of column terms.  It overlays the wave's
-// stage of the other phases (SymLds is the larger of the two).
-constexpr int kSymCols = 16;           // columns reduced per tile
-constexpr int kSymCol = kWaveLeaf + 4;  // tile column stride in floats (no bank conflicts)
+// sources) and a tile of column terms, 64 rows (target lanes) by sym_cols
+// columns (sources): 16 FP32 or 8 FP64 columns, 4 KB either way.  It overlays
+// the wave's stage of the other phases.
+template <bool F32>
+constexpr int sym_cols() {
+    return F32 ? 16 : 8;
+}
+// tile column stride in values: the rows plus a pad that keeps the 16-byte
+// reads of one column's lanes on distinct banks
+template <bool F32>
+constexpr int sym_stride() {
+    return kWaveLeaf + (F32 ? 4 : 2);
+}
+template <bool F32>
 struct SymLds {
-    StageT<true, kWaveLeaf> st;
-    float m[kSymCols * kSymCol];  // column c, row i (target lane): m[kSymCol c + i]
+    StageT<F32, kWaveLeaf> st;
+    Real<F32> m[sym_cols<F32>() * sym_stride<F32>()];  // column c, row i: m[stride c + i]
 };
 template <bool F32>
 constexpr int wave_lds_bytes() {
-    return F32 && sizeof(SymLds) > sizeof(WaveStage<F32>) ? int(sizeof(SymLds))
-                                                           : int(sizeof(WaveStage<F32>));
+    return sizeof(SymLds<F32>) > sizeof(WaveStage<F32>) ? int(sizeof(SymLds<F32>))
+                                                         : int(sizeof(WaveStage<F32>));
 }
 
-// x of another lane of the same quad of four lanes (DPP quad_perm CTRL)
+// x of another lane of the same row of 16 lanes (DPP control CTRL: a
+// quad_perm, or row_half_mirror 0x141, lane i <- lane 7 - i of its eight)
 template <int CTRL>
-__device__ __forceinline__ float dpp_quad(float x) {
+__device__ __forceinline__ float dpp_row(float x) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
                                                                  CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double x) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(u)), CTRL, 0xf, 0xf,
+                                                             true));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(u >> 32)), CTRL, 0xf,
+                                                             0xf, true));
+    return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+
+// Kernel value of a symmetric PP pair (scalar kernels, cells that do not
+// overlap): the FP32 form takes the expanded squared distance (the close
+// entries stay one way), FP64 exact differences; unscaled as in eval_pair.
+template <int KERN, bool F32>
+__device__ __forceinline__ Real<F32> sym_value(const TargetRegs& T, Real<F32> sx, Real<F32> sy,
+                                               Real<F32> sz, Real<F32> s2) {
+    if constexpr (F32) {
+        return kernel_value_f32<KERN>(expanded_d2(T, sx, sy, sz, s2));
+    } else {
+        (void)s2;
+        const double dx = sx - T.tx, dy = sy - T.ty, dz = sz - T.tz;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if constexpr (KERN == CSFMM_K_POISSON_LOG)
+            return log(r2);
+        else if constexpr (KERN == CSFMM_K_BIHARMONIC)
+            return dilog_1m(r2);
+        else if constexpr (KERN == CSFMM_K_SAL)
+            return sal_bracket(r2);
+        else
+            return rsq64(r2);
+    }
 }
 
 __device__ __forceinline__ void wave_sync();
 
 // One symmetric PP pair on the wave of its owner A: for every staged source j
-// of the partner B (nj, a multiple of 16, padded with weightless sources) the
-// kernel value g_ij at every lane's target i of A serves both directions: the
-// row sum p_i += w_j g_ij and the column sum col_j = sum_i wA_i g_ij.  The
-// column terms of 16 sources go through the LDS tile (column-major): lane i
-// writes its term of each column as it is computed, then lane l sums rows
-// 16 (l % 4) .. + 15 of column l / 4 and a quad reduction joins the four
-// partial sums; col_j goes to colout[j] for j < nB.
-template <int KERN>
-__device__ __forceinline__ void run_sym(SymLds& S, int base, int nj, int nB,
-                                        const TargetRegs& T, float wA, float* p,
-                                        float* __restrict__ colout) {
+// of the partner B (nj, a multiple of the tile's C columns, padded with
+// weightless sources) the kernel value g_ij at every lane's target i of A
+// serves both directions: the row sum p_i += w_j g_ij and the column sum
+// col_j = sum_i wA_i g_ij.  The column terms of C sources go through the LDS
+// tile (column-major): lane i writes its term of each column as it is
+// computed, then the 64/C lanes of a column each sum C consecutive rows of
+// it (lane l: column l / (64/C), rows C (l % (64/C)) ..) and a DPP tree joins
+// their partial sums (quads; in FP64 then the two quads of eight lanes), in
+// an order that does not depend on scheduling; col_j goes to colout[j] for
+// j < nB.
+template <int KERN, bool F32>
+__device__ __forceinline__ void run_sym(SymLds<F32>& S, int base, int nj, int nB,
+                                        const TargetRegs& T, Real<F32> wA, Real<F32>* p,
+                                        Real<F32>* __restrict__ colout) {
+    using R = Real<F32>;
+    using R4 = typename std::conditional<F32, float4, double4>::type;
+    constexpr int C = sym_cols<F32>(), LPC = 64 / C, SD = sym_stride<F32>();
     const int lane = threadIdx.x & 63;
     nj = __builtin_amdgcn_readfirstlane(nj);
-    for (int j0 = 0; j0 < nj; j0 += kSymCols) {
+    for (int j0 = 0; j0 < nj; j0 += C) {
         // the next group of four sources is read while the current one is
         // evaluated
         const auto* Qp = &S.st.b[(base + j0) >> 2];
-        float4 cur[5], nxt[5];
+        R4 cur[5], nxt[5];
 #pragma unroll
         for (int k = 0; k < 4; ++k) cur[k] = Qp[0].p[k];
         cur[4] = Qp[0].w;
 #pragma unroll
-        for (int q = 0; q < kSymCols / 4; ++q) {
-            if (q + 1 < kSymCols / 4) {
+        for (int q = 0; q < C / 4; ++q) {
+            if (q + 1 < C / 4) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) nxt[k] = Qp[q + 1].p[k];
                 nxt[4] = Qp[q + 1].w;
             }
-            const float ws[4] = {cur[4].x, cur[4].y, cur[4].z, cur[4].w};
+            const R ws[4] = {cur[4].x, cur[4].y, cur[4].z, cur[4].w};
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const float4 sp = cur[u];
-                const float g = kernel_value_f32<KERN>(expanded_d2(T, sp.x, sp.y, sp.z, sp.w));
-                p[0] = fmaf(ws[u], g, p[0]);
+                const R4 sp = cur[u];
+                const R g = sym_value<KERN, F32>(T, sp.x, sp.y, sp.z, sp.w);
+                p[0] = fma(ws[u], g, p[0]);
                 // column term, stored at once (no registers held for the tile)
-                S.m[kSymCol * (4 * q + u) + lane] = wA * g;
+                S.m[SD * (4 * q + u) + lane] = wA * g;
             }
 #pragma unroll
             for (int k = 0; k < 5; ++k) cur[k] = nxt[k];
         }
         wave_sync();
-        const int col = lane >> 2, r0 = lane & 3;
-        const float4* cp = reinterpret_cast<const float4*>(&S.m[kSymCol * col + 16 * r0]);
-        float4 v[4];
+        const int col = lane / LPC, r0 = lane % LPC;
+        R sum;
+        if constexpr (F32) {
+            const float4* cp = reinterpret_cast<const float4*>(&S.m[SD * col + C * r0]);
+            float4 v[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = cp[k];
-        float part[4];
+            for (int k = 0; k < 4; ++k) v[k] = cp[k];
+            float part[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) part[k] = (v[k].x + v[k].y) + (v[k].z + v[k].w);
-        float sum = (part[0] + part[1]) + (part[2] + part[3]);
-        sum += dpp_quad<0xB1>(sum);  // quad_perm [1,0,3,2]
-        sum += dpp_quad<0x4E>(sum);  // quad_perm [2,3,0,1]
+            for (int k = 0; k < 4; ++k) part[k] = (v[k].x + v[k].y) + (v[k].z + v[k].w);
+            sum = (part[0] + part[1]) + (part[2] + part[3]);
+        } else {
+            const double2* cp = reinterpret_cast<const double2*>(&S.m[SD * col + C * r0]);
+            double2 v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = cp[k];
+            sum = ((v[0].x + v[0].y) + (v[1].x + v[1].y)) + ((v[2].x + v[2].y) + (v[3].x + v[3].y));
+        }
+        sum += dpp_row<0xB1>(sum);  // quad_perm [1,0,3,2]
+        sum += dpp_row<0x4E>(sum);  // quad_perm [2,3,0,1]
+        if constexpr (!F32) sum += dpp_row<0x141>(sum);  // row_half_mirror: the other quad
         if (r0 == 0 && j0 + col < nB) colout[j0 + col] = sum;
         wave_sync();
     }
@@ -802,17 +861,21 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // The symmetric pairs owned by target leaf T (one wave, lane = target of T),
-// one partner leaf (at most 64 points) at a time, padded to a multiple of 16;
-// the loads of the next partner are in flight while the current one is
-// evaluated.  Row sums into acc, column sums to the pair's slot of sym_col.
-template <int KERN>
+// one partner leaf (at most 64 points) at a time, padded to a multiple of the
+// tile's columns; the loads of the next partner are in flight while the
+// current one is evaluated.  Row sums into acc, column sums to the pair's
+// slot of sym_col.
+template <int KERN, bool F32>
 __device__ __forceinline__ void sym_pairs(const TileArgs& a, const ReqView& V, int T, int tb,
                                           int nT, double cx, double cy, double cz,
-                                          const TargetRegs& TR, double* acc, SymLds& S) {
+                                          const TargetRegs& TR, double* acc, SymLds<F32>& S) {
+    using R = Real<F32>;
+    constexpr int C = sym_cols<F32>();
     constexpr double scale = coord_scale<KERN>();
     const int lane = threadIdx.x & 63;
+    R* __restrict__ cols = static_cast<R*>(V.sym_col);
     // T's points as sources of the column direction (same set: same order)
-    const float wA = lane < nT ? float(gload_near(a.sw + tb, lane)) : 0.f;
+    const R wA = lane < nT ? R(gload_near(a.sw + tb, lane)) : R(0);
     const int o0 = gload(V.own_off, T), o1 = gload(V.own_off, T + 1);
     int cnt = 0;
     double yx = 0.0, yy = 0.0, yz = 0.0, yw = 0.0;
@@ -823,16 +886,16 @@ __device__ __forceinline__ void sym_pairs(const TileArgs& a, const ReqView& V, i
         if (cnt > 0) load_source(a, code, min(lane, cnt - 1), yx, yy, yz, yw);
     };
     if (o0 < o1) fetch(o0);
-    float p = 0.f;
+    R p = R(0);
     for (int k = o0; k < o1; ++k) {
-        const int n = cnt, npad = (n + kSymCols - 1) / kSymCols * kSymCols;
+        const int n = cnt, npad = (n + C - 1) / C * C;
         if (lane < n)
             S.st.put(lane, (yx - cx) * scale, (yy - cy) * scale, (yz - cz) * scale, yw);
         else if (lane < npad)
             S.st.put(lane, 2.0, 2.0, 2.0, 0.0);  // far, weightless
         wave_sync();
         if (k + 1 < o1) fetch(k + 1);
-        if (n > 0) run_sym<KERN>(S, 0, npad, n, TR, wA, &p, V.sym_col + int64_t(k) * kWaveLeaf);
+        if (n > 0) run_sym<KERN, F32>(S, 0, npad, n, TR, wA, &p, cols + int64_t(k) * kWaveLeaf);
         wave_sync();
     }
     acc[0] += double(p);
@@ -871,11 +934,11 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
     const int neb = a.use_b ? gload(a.off_b, T + 1) - eb0 : 0;
     const int nov = (a.use_a && a.novl) ? gload(a.novl, T) : 0;
     const int ncl = (a.use_a && a.ncl) ? gload(a.ncl, T) : 0;
-    // symmetric PP path (FP32 scalar kernels, PP launch): the distinct leaves'
-    // entries split into one-way entries (here, phases 1 and 2; the close ones
-    // lead the one-way list) and owned pairs (sym_pairs below); pairs owned by
-    // the partner come in through k_sym_merge
-    constexpr bool kSymKernel = F32 && KERN != CSFMM_K_BIOT_SAVART;
+    // symmetric PP path (scalar kernels, PP launch): the distinct leaves'
+    // entries split into one-way entries (here, phases 1 and 2; in the FP32
+    // form the close ones lead the one-way list) and owned pairs (sym_pairs
+    // below); pairs owned by the partner come in through k_sym_merge
+    constexpr bool kSymKernel = KERN != CSFMM_K_BIOT_SAVART;
     sym = kSymKernel && sym && a.use_a;
     const int32_t* list1 = sym ? V.one_src : a.src_a + ea0;
     const int base1 = sym ? gload(V.one_off, T) : nov;
@@ -965,8 +1028,8 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
     }
     if constexpr (kSymKernel) {
         if (sym)
-            sym_pairs<KERN>(a, V, T, tb, nT, cx, cy, cz, TR, acc,
-                            *reinterpret_cast<SymLds*>(lds));
+            sym_pairs<KERN, F32>(a, V, T, tb, nT, cx, cy, cz, TR, acc,
+                                 *reinterpret_cast<SymLds<F32>*>(lds));
     }
     if (active) {
         double o[VD];
@@ -1047,10 +1110,11 @@ __global__ __launch_bounds__(kThreads) void k_sym_merge(Batch b) {
     const int T = gload(V.t_leaves, leaf);
     const int nT = gload(V.t_count, T), tb = gload(V.t_begin, T);
     const int r0 = gload(V.recv_off, T), r1 = gload(V.recv_off, T + 1);
+    const Real<F32>* cols = static_cast<const Real<F32>*>(V.sym_col);
     double acc = 0.0;
     for (int k = r0; k < r1; ++k) {
         const int64_t slot = gload(V.recv_slot, k);
-        if (lane < nT) acc += double(V.sym_col[slot * kWaveLeaf + lane]);
+        if (lane < nT) acc += double(cols[slot * kWaveLeaf + lane]);
     }
     if (lane < nT && r1 > r0) {
         double o;
@@ -1426,20 +1490,23 @@ int scratch_address(double** out) {
 }  // namespace
 
 template <int KERN>
-int launch_sym_merge_t(const Batch& b, hipStream_t s) {
+int launch_sym_merge_t(const Batch& b, bool fp32, hipStream_t s) {
     const int nblocks = b.prefix[b.n];
     if (nblocks <= 0) return CSFMM_OK;
-    k_sym_merge<KERN, true><<<nblocks, kThreads, 0, s>>>(b);
+    if (fp32)
+        k_sym_merge<KERN, true><<<nblocks, kThreads, 0, s>>>(b);
+    else
+        k_sym_merge<KERN, false><<<nblocks, kThreads, 0, s>>>(b);
     CSFMM_LAUNCH_CHECK();
     return CSFMM_OK;
 }
 
-int launch_sym_merge(const Batch& b, int kernel, hipStream_t s) {
+int launch_sym_merge(const Batch& b, int kernel, bool fp32, hipStream_t s) {
     switch (kernel) {
-        case CSFMM_K_POISSON_LOG: return launch_sym_merge_t<1>(b, s);
-        case CSFMM_K_INV_DIST: return launch_sym_merge_t<3>(b, s);
-        case CSFMM_K_BIHARMONIC: return launch_sym_merge_t<4>(b, s);
-        case CSFMM_K_SAL: return launch_sym_merge_t<5>(b, s);
+        case CSFMM_K_POISSON_LOG: return launch_sym_merge_t<1>(b, fp32, s);
+        case CSFMM_K_INV_DIST: return launch_sym_merge_t<3>(b, fp32, s);
+        case CSFMM_K_BIHARMONIC: return launch_sym_merge_t<4>(b, fp32, s);
+        case CSFMM_K_SAL: return launch_sym_merge_t<5>(b, fp32, s);
         default:
             set_error("no symmetric PP path for kernel id %d", kernel);
             return CSFMM_E_INVALID;

@@ -125,12 +125,13 @@ def estimate_cells(n, leaf):
 def workspace_bytes_estimate(n_t, n_s, p, leaf):
     """Upper estimate of one eval workspace (the terms of csfmm_workspace_bytes):
     sorted weights, proxy weights and potentials, two near-field arrays and,
-    for same-set plans in the FP32 form, the column sums of the symmetric PP
-    pairs (64 floats per owned pair, at most 16 pairs per leaf)."""
+    for same-set plans, the column sums of the symmetric PP pairs (64 values
+    per owned pair, 4 bytes in the FP32 form and 8 in FP64, at most 16 pairs
+    per leaf)."""
     K = (p + 1) ** 2
     KS = (K + 3) // 4 * 4
     ct, cs = estimate_cells(n_t, leaf), estimate_cells(n_s, leaf)
-    return (8 * (n_s + cs * KS + 3 * ct * KS + 6 * n_t) + 4 * 64 * 16 * ct + 1024)
+    return (8 * (n_s + cs * KS + 3 * ct * KS + 6 * n_t) + 8 * 64 * 16 * ct + 1024)
 
 
 @dataclass

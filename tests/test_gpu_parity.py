@@ -142,8 +142,8 @@ CASES = {
     "sal_distinct": lambda: (random_sphere_points(2000, 43), cubed_sphere_grid(16)[0], 5, 6, 0.6, 40),
     # leaves of more than 64 points: the near field's block path
     "random_leaf100": lambda: (random_sphere_points(6000, 47), None, 1, 6, 0.7, 100),
-    # 6,144 leaves of 9 points: the one-wave-per-leaf path (and, in the FP32
-    # form, the symmetric PP pairs); the smaller cases keep the block path
+    # 6,144 leaves of 9 points: the one-wave-per-leaf path and the symmetric
+    # PP pairs (both forms); the smaller cases keep the block path
     "grid_E96_leaf16": lambda: (cubed_sphere_grid(96)[0], None, 1, 4, 0.7, 16),
     # high degrees: P2M with two leaves per block (p >= 12), L2P of three
     # components at p = 12 (LDS near its limit); PC (p = 14) and CC (p = 12) present
@@ -213,9 +213,8 @@ def test_lists(case):
     assert (st["evals_pp"], st["evals_pc"], st["evals_cp"], st["evals_cc"]) == \
         (want["PP"], want["PC"], want["CP"], want["CC"])
     assert st["max_leaf_t"] == max(C.count for C in ofmm.ttree.cells if C.is_leaf)
-    # same-set plans in the FP32 form: PP entries of distinct leaves split into
-    # pairs that hold both ways (once per pair) and one-way entries
-    assert (st["pp_sym_pairs"], st["pp_one_way"]) == (0, 0)  # FP64 form: not built
+    # same-set plans: PP entries of distinct leaves split into pairs that hold
+    # both ways (evaluated once per pair) and one-way entries
     pp = set((Tc.id, Sc.id) for Tc, Sc in ofmm.lists["PP"])
     p32 = cs.Plan(tdev(T), None if S is None else tdev(S), kernel=k, p=p, theta=th,
                   leaf_size=leaf, fp32=True, shrink=plan.shrink_case)
@@ -225,19 +224,21 @@ def test_lists(case):
         both = sum(1 for a, b in pp if a != b and (b, a) in pp)
         one = sum(1 for a, b in pp if a != b and (b, a) not in pp)
         assert both % 2 == 0
-        # a pair whose entries are close (exact differences) stays two one-way
-        # entries; the close rule is symmetric, so pairs split whole
+        assert (st["pp_sym_pairs"], st["pp_one_way"]) == (both // 2, one)  # FP64 form
+        # FP32 form: a pair whose entries are close (exact differences) stays
+        # two one-way entries; the close rule is symmetric, so pairs split whole
         lost = both // 2 - s32["pp_sym_pairs"]
         assert lost >= 0 and s32["pp_one_way"] == one + 2 * lost
         assert s32["pp_close"] >= 2 * lost
     else:
+        assert (st["pp_sym_pairs"], st["pp_one_way"]) == (0, 0)
         assert (s32["pp_sym_pairs"], s32["pp_one_way"]) == (0, 0)
 
 
 def test_cases_cover_both_near_field_paths():
     """Many leaves of at most 64 points take the one-wave-per-leaf near field
-    (and the symmetric PP pairs in the FP32 form), the others the block path:
-    the parity cases hold both."""
+    (and the symmetric PP pairs), the others the block path: the parity cases
+    hold both."""
     got = {}
     for name in ("config1", "random_leaf100", "grid_E96_leaf16"):
         T, S, k, p, th, leaf, _ = _case(name)

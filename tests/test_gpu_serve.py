@@ -189,9 +189,9 @@ def test_served_stream_at_full_request_sizes():
 @pytest.mark.parametrize("E,p", [(16, 6), (64, 8), (256, 6), (512, 8)])
 def test_admission_estimates_cover_the_bytes_held(E, p):
     """The scheduler admits by estimates made before a plan exists: they must
-    cover what the plan and a workspace then hold, in both forms (the FP32
-    same-set plans of E >= 256 hold the symmetric PP slots); the plan's own
-    workspace figure is exact."""
+    cover what the plan and a workspace then hold, in both forms (same-set
+    plans of E >= 256 hold the symmetric PP slots, 8 bytes a value in FP64);
+    the plan's own workspace figure is exact."""
     from paper_2508_13550_amd.serve import workspace_bytes_estimate
     T = grid(E)[3]
     n = T.shape[0]
@@ -207,7 +207,7 @@ def test_admission_estimates_cover_the_bytes_held(E, p):
         assert cs.workspace_bytes(pl) == ws.device_bytes
         assert st["device_bytes"] <= est_plan
         assert ws.device_bytes <= est_ws
-        if fp32 and E >= 256:
+        if E >= 256:
             assert st["pp_sym_pairs"] > 0
         ws.close()
         pl.close()
