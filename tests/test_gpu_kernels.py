@@ -77,3 +77,47 @@ def test_biharmonic_eigenrelation_full_size(grid256):
         e_fix = math.sqrt(np.sum((fixed - exact) ** 2 * A) / np.sum(exact ** 2 * A))
         print("raw %.3e  with diagonal %.3e" % (e_raw, e_fix), flush=True)
         assert e_fix < 5e-6 and e_fix < 0.05 * e_raw
+
+
+@pytest.mark.parametrize("kernel,tol", [(cs.POISSON, 1e-15), (cs.BIOT_SAVART, 2e-15),
+                                        (cs.INV_DIST, 1e-15), (cs.BIHARMONIC, 1e-14),
+                                        (cs.SAL, 1e-15)])
+def test_fp64_kernel_values_one_pair_at_a_time(kernel, tol):
+    """The FP64 kernel values of the library's own logarithm, reciprocal and
+    reciprocal square root, one (target, source) pair per output: one source,
+    200,000 targets at distances from 1e-9 to the antipode (and around the
+    zero of the Poisson logarithm, |x - y| = sqrt(2)), against the oracle's
+    libm values element by element: |got - ref| <= tol (|ref| + median |ref|)
+    (vector norms for Biot-Savart, plus the oracle's own rounding: it forms
+    x cross y, whose components lose about 4e-16 absolute, so about
+    4e-16 / |x - y| of |ref| for close pairs)."""
+    say("one-pair kernel values, kernel %d" % kernel)
+    from workloads import random_sphere_points
+    rng = np.random.default_rng(61)
+    y = np.array([[0.36, -0.48, 0.8]])
+    X = random_sphere_points(150000, 62)
+    # targets close to the source, down to 1e-9 away
+    d = 10.0 ** rng.uniform(-9, -1, 40000)
+    u = rng.standard_normal((40000, 3))
+    u -= (u @ y[0])[:, None] * y
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    Xc = y + d[:, None] * u
+    # targets near |x - y| = sqrt(2) (the great circle 90 degrees away)
+    Xq = u[:10000] + rng.uniform(-1e-6, 1e-6, (10000, 1)) * y
+    X = np.concatenate([X, Xc, Xq])
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    w = np.array([0.75])
+    got = cs.direct(tdev(X), tdev(y), tdev(w), kernel=kernel).cpu().numpy()
+    ref = odirect(kernel, X, y, w)
+    if kernel == cs.BIOT_SAVART:
+        err = np.linalg.norm(got - ref, axis=1)
+        mag = np.linalg.norm(ref, axis=1)
+    else:
+        err, mag = np.abs(got - ref), np.abs(ref)
+    bound = tol * (mag + np.median(mag))
+    if kernel == cs.BIOT_SAVART:
+        bound = bound + 1e-15 * mag / np.linalg.norm(X - y, axis=1)
+    worst = float(np.max(err / bound)) * tol
+    print("kernel %d worst scaled error %.3e (tol %.0e)" % (kernel, worst, tol), flush=True)
+    assert np.all(np.isfinite(got))
+    assert np.all(err <= bound)
