@@ -177,12 +177,13 @@ __device__ __forceinline__ float sal_bracket(float v) {
 //  FORM_EXACT  cells that do not overlap the target, exact differences and the
 //              zero check (FP32 form: the PP entries the plan marks close,
 //              whose points may come near each other across leaf edges)
-// In the FP32 form the scalar kernels take |t-s|^2 = |t|^2 + |s|^2 - 2 t.s for
+// In the FP32 form every kernel takes |t-s|^2 = |t|^2 + |s|^2 - 2 t.s for
 // FORM_NEAR and FORM_FAR (4 operations instead of 6; coordinates are recentred
 // at the target cell, and the plan's close-pair rule, or the MAC, bounds
 // (|t|^2 + |s|^2)/|t-s|^2, so the relative error of the squared distance stays
-// within a few hundred FP32 ulps); FORM_CHECK keeps exact differences so that
-// a coincident point gives exactly 0.
+// within a few hundred FP32 ulps; Biot-Savart's difference vector is then
+// assembled per group in run_group); FORM_CHECK keeps exact differences so
+// that a coincident point gives exactly 0.
 enum { FORM_CHECK = 0, FORM_NEAR = 1, FORM_FAR = 2, FORM_EXACT = 3 };
 
 struct TargetRegs {
@@ -456,6 +457,13 @@ __device__ __forceinline__ int group_len(int nq, int G) {
 
 // Sources base .. base + nj of a stage against TPT targets of one thread
 // (each staged source read once serves all of them).
+//
+// Biot-Savart in the FP32 form, FORM_NEAR and FORM_FAR: with f = w / |t-s|^2
+// from the expanded squared distance, the sum of f (s - t) is taken as
+// A - t B, A = sum f s, B = sum f (nine operations a pair instead of eleven);
+// coordinates are recentred at the target cell, so |s| and |t| stay within a
+// few times |s - t| on the pairs these forms see (the close-pair rule and the
+// MAC bound the ratio), and the cancellation in A - t B costs a few ulps.
 template <int KERN, bool F32, int FORM, int CAP, int TPT>
 __device__ __forceinline__ void run_group(const StageT<F32, CAP>& L, int base, int nj,
                                           const TargetRegs (&T)[TPT],
@@ -464,6 +472,38 @@ __device__ __forceinline__ void run_group(const StageT<F32, CAP>& L, int base, i
     // the loop control off the vector unit
     nj = __builtin_amdgcn_readfirstlane(nj);
     const typename StageT<F32, CAP>::Quad* Qp = &L.b[base >> 2];  // base: a multiple of four
+    if constexpr (F32 && KERN == CSFMM_K_BIOT_SAVART && (FORM == FORM_NEAR || FORM == FORM_FAR)) {
+        float A[TPT][3], B[TPT];
+#pragma unroll
+        for (int q = 0; q < TPT; ++q) {
+            A[q][0] = A[q][1] = A[q][2] = 0.f;
+            B[q] = 0.f;
+        }
+        for (int j = 0; j < nj; j += kUnroll) {
+            const auto& Q = *Qp++;
+            const float4 w4 = Q.w;
+            const float ws[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const float4 s = Q.p[u];
+#pragma unroll
+                for (int q = 0; q < TPT; ++q) {
+                    const float f = ws[u] * dev_rcp(expanded_d2(T[q], s.x, s.y, s.z, s.w));
+                    A[q][0] = fmaf(f, s.x, A[q][0]);
+                    A[q][1] = fmaf(f, s.y, A[q][1]);
+                    A[q][2] = fmaf(f, s.z, A[q][2]);
+                    B[q] += f;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < TPT; ++q) {
+            p[q][0] += fmaf(-T[q].fx, B[q], A[q][0]);
+            p[q][1] += fmaf(-T[q].fy, B[q], A[q][1]);
+            p[q][2] += fmaf(-T[q].fz, B[q], A[q][2]);
+        }
+        return;
+    }
     for (int j = 0; j < nj; j += kUnroll) {
         const auto& Q = *Qp++;
         const auto w4 = Q.w;
@@ -1070,11 +1110,14 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
 // a kTilePCFar launch the far-field blocks are the long ones and the short PC
 // blocks fill the tail.  Near-field blocks of a request marked in leaf_wave
 // take four target leaves, one per wave (tile_leaf_wave); the others take one
-// leaf over the whole block (tile_body).  The occupancy hint keeps the FP32
-// instances at 80 VGPRs (6 waves per SIMD; measured faster than 5); the FP64
-// instances, whose transcendentals are longer, get 4 waves per SIMD.
+// leaf over the whole block (tile_body).  The occupancy hint keeps the scalar
+// FP32 instances at 80 VGPRs (6 waves per SIMD; measured faster than 5),
+// Biot-Savart's FP32 instances (three components and the A - t B sums) at 96
+// (5 waves, which removes their spills; measured 1% faster than 6 on N =
+// 1,572,864); the FP64 instances, whose transcendentals are longer and which
+// hold two targets a thread, get 3 waves per SIMD.
 template <int KERN, bool F32>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 3))) void k_tile(Batch b) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? (KERN == CSFMM_K_BIOT_SAVART ? 5 : 6) : 3))) void k_tile(Batch b) {
     __shared__ TileSmem<KERN, F32> sm;
     bool far;
     const int blk = xcd_split_block(blockIdx.x, gridDim.x, b.prefix2[b.n], far);
@@ -1106,7 +1149,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 
 // target leaves per block, one a wave, the waves independent of each other
 // (measured faster than blocks of one wave).
 template <int KERN, bool F32>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 6 : 4))) void k_tile_wave(Batch b) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? (KERN == CSFMM_K_BIOT_SAVART ? 5 : 6) : 4))) void k_tile_wave(Batch b) {
     constexpr int kWaveBytes = wave_lds_bytes<F32>();
     __shared__ __attribute__((aligned(16))) char lds[(kThreads / 64) * kWaveBytes];
     int req, local;
