@@ -704,10 +704,15 @@ def roofline_of(r, fp32, record_name, kernel_desc):
     d = parts[dom]
     rec = recorded_traffic(record_name)
     traffic = None
-    if rec and dom == "pp":
+    if rec:
+        # the record is of this workload when its PP launch has this grid; the
+        # PC + far launch is its other k_tile dispatch
+        disp = rec.get("dispatches", [])
         g = pp_grid(st)
-        rows = [x for x in rec.get("dispatches", []) if x["grid_size"] == g and x["pp"]]
-        if rows:
+        pp_rows = [x for x in disp if x["grid_size"] == g and x["pp"]]
+        rows = pp_rows if dom == "pp" else [
+            x for x in disp if not x["pp"] and re.search(r"::k_tile<", x["kernel"])]
+        if pp_rows and rows:
             traffic = sum(x["traffic_bytes"] for x in rows)
     line = {"bound": "alu", "kernel": d["kernel"], "achieved": d["achieved"], "peak": peak,
             "unit": "TFLOP/s", "frac": d["frac"], "traffic": traffic,
