@@ -108,6 +108,15 @@ __device__ __forceinline__ double log64(double x) {
     for (int k = 9; k >= 1; --k) q = fma(q, z, 2.0 / (2 * k + 1));
     return fma(double(e), kLn2, fma(-s, f - z * q, f));
 }
+// FP64 ln(1 + x) for x > -1 by Kahan's correction of a logarithm (Goldberg,
+// "What every computer scientist should know about floating-point
+// arithmetic", Theorem 4): with u = 1 + x rounded, ln(1 + x) = ln(u) x/(u - 1)
+// (u - 1 is exact), and x itself when u rounds to 1; a few ulps with log64.
+__device__ __forceinline__ double log1p64(double x) {
+    const double u = 1.0 + x;
+    const double d = u - 1.0;
+    return d == 0.0 ? x : log64(u) * (x * rcp64(d));
+}
 __device__ __forceinline__ float dev_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float dev_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
@@ -129,7 +138,7 @@ constexpr double kPi2Over6 = 1.64493406684822643647;
 
 __device__ __forceinline__ double dilog_1m(double v) {
     v = fmin(v, 1.0);
-    const double l1 = log64(v), l2 = log1p(-v);
+    const double l1 = log64(v), l2 = log1p64(-v);
     const bool refl = v <= 0.5;
     const double w = refl ? -l2 : -l1;
     const double w2 = w * w;
