@@ -668,6 +668,7 @@ def measure(cs, torch, Td, Sd, W, kernel, p, theta, leaf, fp32, steps, warmup, s
     stage = {k: v / max(n, 1) for k, v in stage.items()}
     stage["near_pp_timed_region"] = st_t["near_pp"] / max(n_t, 1)
     stage["pc_far_timed_region"] = st_t["pc_far"] / max(n_t, 1)
+    stage["interaction_span_timed_region"] = st_t["interaction_span"] / max(n_t, 1)
     st = plan.stats()
     plan.close()
     got = out[torch.as_tensor(samp, device=out.device)].cpu().numpy()
@@ -686,12 +687,18 @@ def pp_grid(st):
 
 
 def roofline_of(r, fp32, record_name, kernel_desc):
-    """Roofline of the dominant stage (the longer of the PP launch and the PC +
-    far-field launch) from the HIP events of the timed region."""
+    """Roofline of the interaction launches, the dominant kernel: the PP
+    launch (side stream) and the PC + far-field launch (eval stream) run
+    concurrently, so their evaluations are taken together over the span
+    they occupy (the library's HIP events: PP start to the eval stream's join
+    with it, in the timed region); each launch's own rate over its own
+    event-timed duration is reported beside it."""
     st, stage = r["stats"], r["stage"]
     peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
     ev_far = st["evals_pc"] + st["evals_cp"] + st["evals_cc"]
     pp_ms, far_ms = stage["near_pp_timed_region"], stage["pc_far_timed_region"]
+    span = stage.get("interaction_span_timed_region", 0.0)
+    span = max(span, pp_ms, far_ms)  # the span holds both launches
     parts = {
         "pp": {"kernel": kernel_desc + ": PP near-field launch", "evals": st["evals_pp"],
                "ms": pp_ms},
@@ -700,8 +707,8 @@ def roofline_of(r, fp32, record_name, kernel_desc):
     for q in parts.values():
         q["achieved"] = q["evals"] * FLOP_PER_EVAL / (q["ms"] / 1e3) / 1e12 if q["ms"] > 0 else 0.0
         q["frac"] = q["achieved"] / peak
-    dom = "pp" if pp_ms >= far_ms else "pc_far"
-    d = parts[dom]
+    evals = st["evals_pp"] + ev_far
+    achieved = evals * FLOP_PER_EVAL / (span / 1e3) / 1e12 if span > 0 else 0.0
     rec = recorded_traffic(record_name)
     traffic = None
     if rec:
@@ -710,17 +717,15 @@ def roofline_of(r, fp32, record_name, kernel_desc):
         disp = rec.get("dispatches", [])
         g = pp_grid(st)
         pp_rows = [x for x in disp if x["grid_size"] == g and x["pp"]]
-        rows = pp_rows if dom == "pp" else [
-            x for x in disp if not x["pp"] and re.search(r"::k_tile<", x["kernel"])]
-        if pp_rows and rows:
-            traffic = sum(x["traffic_bytes"] for x in rows)
-    line = {"bound": "alu", "kernel": d["kernel"], "achieved": d["achieved"], "peak": peak,
-            "unit": "TFLOP/s", "frac": d["frac"], "traffic": traffic,
-            "flop_per_eval": FLOP_PER_EVAL, "evals_per_launch": d["evals"],
-            "avg_launch_ms": d["ms"], "dominant_stage": dom,
-            "other_stage": {k: v for k, v in parts[("pc_far" if dom == "pp" else "pp")].items()},
+        far_rows = [x for x in disp if not x["pp"] and re.search(r"::k_tile<", x["kernel"])]
+        if pp_rows and far_rows:
+            traffic = sum(x["traffic_bytes"] for x in pp_rows + far_rows)
+    return {"bound": "alu",
+            "kernel": kernel_desc + ": the PP launch and the PC + far launch, concurrent",
+            "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": traffic, "flop_per_eval": FLOP_PER_EVAL, "evals_per_step": evals,
+            "span_ms": span, "launches": parts,
             "traffic_record": record_name if traffic is not None else None}
-    return line
 
 
 def cpu_baseline_of(t_oracle, n_samp, n_src, what):
@@ -762,7 +767,8 @@ def poisson_lines(cs, torch, args):
                     "pp_close": r["stats"]["pp_close"], **e}
         if fp32 and p == 6:
             res[key]["roofline"] = roofline_of(r, True, POISSON_RECORD,
-                                               "k_tile_wave<Poisson,FP32> + k_sym_merge")
+                                               "Poisson FP32 (PP: k_tile_wave + k_sym_merge; "
+                                               "PC + far: k_tile)")
         say("poisson %s done: %.4f ms, rel L2 %.2e" % (key, r["ms"], e["rel_l2_err"]))
     res["fp32_over_fp64_speedup_p6"] = res["fp64_p6"]["ms_per_step"] / res["fp32_p6"]["ms_per_step"]
     res["workload"] = ("Poisson log kernel, equiangular cubed sphere 256x256 cells per face "

@@ -298,19 +298,21 @@ int csfmm_plan_stats(csfmm_plan_t plan, csfmm_stats* s);
 /*
  * Per-stage timing of csfmm_eval with HIP events recorded on the eval's
  * streams.  enable = 1 times every stage, 2 only the two interaction
- * launches, [2] and [3] below (two events on the side stream and two on the
- * eval stream around them; the other sums stay 0), 0 turns timing off;
- * turning it on resets the sums.
+ * launches, [2], [3] and [5] below (two events on the side stream around PP,
+ * two on the eval stream around [3] and one after its join with PP; the other
+ * sums stay 0), 0 turns timing off; turning it on resets the sums.
  * csfmm_plan_timing_read waits for the recorded events and returns the summed
- * milliseconds of the 5 stages over the timed evals:
+ * milliseconds of the 6 stages over the timed evals (stage_ms holds 6):
  *   [0] weight gather + P2M, [1] M2M (and zeroing the proxy potentials),
  *   [2] the PP near-field launch, which runs on the workspace's side stream
  *   concurrently with [0], [1] and [3], [3] PC near field and CP + CC far
  *   field in one launch, [4] L2L + L2P + scatter in one launch, including the
- *   wait for [2].
+ *   wait for [2], [5] the span of the two interaction launches: from the PP
+ *   launch's start on the side stream to the eval stream's join with it, after
+ *   both have ended (PP is queued first and starts first).
  */
 int csfmm_plan_timing(csfmm_plan_t plan, int enable);
-int csfmm_plan_timing_read(csfmm_plan_t plan, double* stage_ms /*[5]*/, int64_t* n_evals);
+int csfmm_plan_timing_read(csfmm_plan_t plan, double* stage_ms /*[6]*/, int64_t* n_evals);
 
 /* Upper estimate of the device bytes a plan of these sizes holds (for
  * admission control); -1 on bad arguments. */

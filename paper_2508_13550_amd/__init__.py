@@ -75,7 +75,7 @@ EXPORTED = (
     "csfmm_workspace_device_bytes",
 )
 
-STAGES = ("p2m", "m2m", "near_pp", "pc_far", "l2l_l2p")
+STAGES = ("p2m", "m2m", "near_pp", "pc_far", "l2l_l2p", "interaction_span")
 
 
 def load_library(path=LIB_PATH):

@@ -328,15 +328,17 @@ struct csfmm_plan_s {
     int32_t* tc_status = nullptr;  // treecode stack-overflow flag (device)
     // optional per-stage timing with HIP events (ring of event sets)
     struct Timing {
-        // P2M, M2M, PP (side stream), PC + CP + CC, L2L + L2P
-        static constexpr int kStages = 5;
+        // P2M, M2M, PP (side stream), PC + CP + CC, L2L + L2P, and the span of
+        // the two interaction launches (PP start to the eval stream's join)
+        static constexpr int kStages = 6;
         static constexpr int kMain = 5;   // events on the eval stream per slot
-        static constexpr int kEvents = kMain + 2;  // + PP start/end on the side stream
+        // + PP start/end on the side stream, + the join on the eval stream
+        static constexpr int kEvents = kMain + 3;
         static constexpr int kSlots = 32;
         int on = 0;  // 0 off, 1 every stage, 2 the PP and the PC + far-field launches only
         std::vector<hipEvent_t> ev;  // [kSlots][kEvents]
         std::vector<int> pending;    // slot recorded and not yet read
-        double sum_ms[kStages] = {0, 0, 0, 0, 0};
+        double sum_ms[kStages] = {0, 0, 0, 0, 0, 0};
         int64_t n = 0;
         int next = 0;
     } timing;

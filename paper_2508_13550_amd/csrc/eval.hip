@@ -485,7 +485,7 @@ using Timing = csfmm_plan_s::Timing;
 // With timing level 2 only the events around the two interaction launches
 // are recorded: [2, 3] (PC + far field) and [5, 6] (PP).
 bool event_recorded(int level, int k) {
-    return level == 1 || k == 2 || k == 3 || k == 5 || k == 6;
+    return level == 1 || k == 2 || k == 3 || k == 5 || k == 6 || k == 7;
 }
 int drain_slot(Timing& tm, int slot) {
     if (!tm.pending[slot]) return CSFMM_OK;
@@ -493,8 +493,9 @@ int drain_slot(Timing& tm, int slot) {
     const int level = tm.pending[slot];
     CSFMM_HIP_TRY(hipEventSynchronize(e[level == 1 ? Timing::kMain - 1 : 3]));
     CSFMM_HIP_TRY(hipEventSynchronize(e[Timing::kMain + 1]));
-    static constexpr int from[Timing::kStages] = {0, 1, 5, 2, 3};
-    static constexpr int to[Timing::kStages] = {1, 2, 6, 3, 4};
+    CSFMM_HIP_TRY(hipEventSynchronize(e[Timing::kMain + 2]));
+    static constexpr int from[Timing::kStages] = {0, 1, 5, 2, 3, 5};
+    static constexpr int to[Timing::kStages] = {1, 2, 6, 3, 4, 7};
     for (int k = 0; k < Timing::kStages; ++k) {
         if (!event_recorded(level, from[k]) || !event_recorded(level, to[k])) continue;
         float ms = 0.f;
@@ -642,7 +643,7 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
     hipStream_t side = W0->side;
     auto mark = [&](int k) -> int {
         if (ev && event_recorded(level, k))
-            CSFMM_HIP_TRY(hipEventRecord(ev[k], k < Timing::kMain ? s : side));
+            CSFMM_HIP_TRY(hipEventRecord(ev[k], (k < Timing::kMain || k == Timing::kMain + 2) ? s : side));
         return CSFMM_OK;
     };
     RCX(mark(0));
@@ -745,6 +746,7 @@ int run_chunk(const EvalReq* reqs, int n, hipStream_t s) {
     RCX(mark(3));
     // join the PP near field
     CSFMM_HIP_TRY(hipStreamWaitEvent(s, W0->join, 0));
+    RCX(mark(Timing::kMain + 2));
     // e7+e8 L2P, near field and scatter to the caller's order; one launch per
     // number of output components (blocks of the other group are empty)
     for (int vdl : {1, 3})

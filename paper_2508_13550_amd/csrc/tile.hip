@@ -1124,9 +1124,11 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
 // Biot-Savart's FP32 instances (three components and the A - t B sums) at 96
 // (5 waves, which removes their spills; measured 1% faster than 6 on N =
 // 1,572,864); the FP64 instances, whose transcendentals are longer and which
-// hold two targets a thread, get 3 waves per SIMD.
+// hold two targets a thread, get 3 waves per SIMD, but 1/|x-y| 4 (128 VGPRs,
+// 12 spilled outside the inner loops; 1.5% faster on 6,291,456 sources x
+// 1,000,000 targets, p = 10: 8.74 -> 8.61 ms).
 template <int KERN, bool F32>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? (KERN == CSFMM_K_BIOT_SAVART ? 5 : 6) : 3))) void k_tile(Batch b) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? (KERN == CSFMM_K_BIOT_SAVART ? 5 : 6) : (KERN == CSFMM_K_INV_DIST ? 4 : 3)))) void k_tile(Batch b) {
     __shared__ TileSmem<KERN, F32> sm;
     bool far;
     const int blk = xcd_split_block(blockIdx.x, gridDim.x, b.prefix2[b.n], far);
