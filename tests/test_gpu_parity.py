@@ -140,6 +140,10 @@ CASES = {
     "tiny_p1_leaf1": lambda: (cubed_sphere_grid(2)[0], None, 1, 1, 0.5, 1),
     "biharmonic_E32": lambda: (cubed_sphere_grid(32)[0], None, 4, 8, 0.7, 64),
     "sal_distinct": lambda: (random_sphere_points(2000, 43), cubed_sphere_grid(16)[0], 5, 6, 0.6, 40),
+    # distinct sets sharing points: the source grid points near +x among the
+    # targets (their leaves keep the zero test), random points elsewhere
+    "distinct_coincident": lambda: (np.concatenate([_grid16_near_x(), random_sphere_points(2000, 44)]),
+                                    cubed_sphere_grid(16)[0], 1, 6, 0.6, 40),
     # leaves of more than 64 points: the near field's block path
     "random_leaf100": lambda: (random_sphere_points(6000, 47), None, 1, 6, 0.7, 100),
     # 6,144 leaves of 9 points: the one-wave-per-leaf path and the symmetric
@@ -162,6 +166,11 @@ CASES = {
 def _case(name):
     c = CASES[name]()
     return c if len(c) == 7 else c + (False,)
+
+
+def _grid16_near_x():
+    P = cubed_sphere_grid(16)[0]
+    return P[P[:, 0] > 0.9]
 
 
 def _clustered():
@@ -233,6 +242,12 @@ def test_lists(case):
     else:
         assert (st["pp_sym_pairs"], st["pp_one_way"]) == (0, 0)
         assert (s32["pp_sym_pairs"], s32["pp_one_way"]) == (0, 0)
+    if name == "distinct_coincident":
+        # some target leaves hold a point equal to a source point, others not
+        leaves = [C for C in ofmm.ttree.cells if C.is_leaf and C.count > 0]
+        src = set(map(tuple, S))
+        hit = sum(1 for C in leaves if any(tuple(T[i]) in src for i in C.idx))
+        assert 0 < hit < len(leaves)
 
 
 def test_cases_cover_both_near_field_paths():
