@@ -58,6 +58,8 @@ def parse():
                     help="form of the headline line (the other one is reported beside it)")
     ap.add_argument("--quick", action="store_true",
                     help="headline form only (no other form, no Poisson lines, no CPU baseline)")
+    ap.add_argument("--poisson-cases", default="fp32_p6,fp32_p8,fp32_p10,fp64_p6",
+                    help="--poisson-only: which of the Poisson lines to run")
     ap.add_argument("--poisson-only", action="store_true",
                     help="only the Poisson N=393,216 lines (its kernels for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -754,7 +756,10 @@ def poisson_lines(cs, torch, args):
     W = torch.tensor(w, dtype=torch.float64, device=dev)
     steps = max(5, args.steps // 4)
     res = {}
-    for fp32, p in ((True, 6), (True, 8), (True, 10), (False, 6)):
+    cases = [(fp32, p) for fp32, p in ((True, 6), (True, 8), (True, 10), (False, 6))
+             if not args.poisson_only or
+             "%s_p%d" % ("fp32" if fp32 else "fp64", p) in args.poisson_cases.split(",")]
+    for fp32, p in cases:
         r = measure(cs, torch, T, None, W, 1, p, c["theta"], c["leaf"], fp32, steps,
                     max(2, args.warmup // 2), S)
         e = errors(r["got"], ref, A[S])
@@ -770,7 +775,9 @@ def poisson_lines(cs, torch, args):
                                                "Poisson FP32 (PP: k_tile_wave + k_sym_merge; "
                                                "PC + far: k_tile)")
         say("poisson %s done: %.4f ms, rel L2 %.2e" % (key, r["ms"], e["rel_l2_err"]))
-    res["fp32_over_fp64_speedup_p6"] = res["fp64_p6"]["ms_per_step"] / res["fp32_p6"]["ms_per_step"]
+    if "fp64_p6" in res and "fp32_p6" in res:
+        res["fp32_over_fp64_speedup_p6"] = (res["fp64_p6"]["ms_per_step"] /
+                                            res["fp32_p6"]["ms_per_step"])
     res["workload"] = ("Poisson log kernel, equiangular cubed sphere 256x256 cells per face "
                        "(N=%d), same set, band-limited n<=32 field (seed 2002), theta=%g, "
                        "leaf<=%d" % (N, c["theta"], c["leaf"]))
