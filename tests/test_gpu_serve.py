@@ -36,15 +36,18 @@ def weights(E, coef):
     return torch.tensor((Y @ coef) * A, dtype=torch.float64, device="cuda")
 
 
-def test_packed_mixed_near_field_paths_equal_alone_bitwise():
+@pytest.mark.parametrize("fp32", [True, False])
+def test_packed_mixed_near_field_paths_equal_alone_bitwise(fp32):
     """A request on the one-wave-per-leaf near field with symmetric PP pairs
     (6,144 leaves of 9 points) packed with requests on the block path (few
     leaves) and with Biot-Savart (no symmetric pairs): each result is bitwise
-    the request evaluated alone, whatever else shares its launches."""
-    say("eval_many: wave/symmetric path packed with block-path requests")
-    big = cs.Plan(grid(96)[3], None, kernel=1, p=4, theta=0.7, leaf_size=16, fp32=True)
-    small = cs.Plan(grid(16)[3], None, kernel=1, p=4, theta=0.7, leaf_size=16, fp32=True)
+    the request evaluated alone, whatever else shares its launches; both
+    forms (the FP64 form's symmetric tile has its own column layout)."""
+    say("eval_many: wave/symmetric path packed with block-path requests, fp32=%s" % fp32)
+    big = cs.Plan(grid(96)[3], None, kernel=1, p=4, theta=0.7, leaf_size=16, fp32=fp32)
+    small = cs.Plan(grid(16)[3], None, kernel=1, p=4, theta=0.7, leaf_size=16, fp32=fp32)
     assert big.stats()["near_wave"] == 1 and small.stats()["near_wave"] == 0
+    assert big.stats()["pp_sym_pairs"] > 0
     rng = np.random.default_rng(21)
     reqs = [(big, 1), (small, 1), (big, 3), (small, 2), (big, 2)]
     batch, alone = [], []
