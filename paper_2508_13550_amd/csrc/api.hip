@@ -258,15 +258,17 @@ int64_t csfmm_workspace_device_bytes(csfmm_workspace_t ws) {
     return ws ? ws->arena.bytes : -1;
 }
 
-// The bytes workspace_create allocates for this plan, term by term.
+// The bytes workspace_create allocates for this plan, array by array (each
+// starting on a 256-byte boundary of one allocation).
 int64_t csfmm_workspace_bytes(csfmm_plan_t plan) {
     if (!plan) return -1;
-    int64_t b = int64_t(sizeof(double)) *
-                    (plan->ns + int64_t(plan->st->ncells) * plan->KS +
-                     int64_t(3) * plan->tt.ncells * plan->KS + int64_t(6) * plan->nt) +
-                int64_t(sizeof(csfmm::ReqView));
+    auto padded = [](int64_t b) { return (std::max<int64_t>(b, 1) + 255) / 256 * 256; };
+    const int64_t d = int64_t(sizeof(double));
+    int64_t b = padded(d * plan->ns) + padded(d * plan->st->ncells * plan->KS) +
+                padded(d * 3 * plan->tt.ncells * plan->KS) + 2 * padded(d * 3 * plan->nt) +
+                padded(int64_t(sizeof(csfmm::ReqView)));
     if (csfmm::sym_path_possible(plan))
-        b += csfmm::sym_value_bytes(plan) * plan->lists.sym.n_own * csfmm::kWaveLeaf;
+        b += padded(csfmm::sym_value_bytes(plan) * plan->lists.sym.n_own * csfmm::kWaveLeaf);
     return b;
 }
 

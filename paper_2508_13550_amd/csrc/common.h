@@ -362,13 +362,23 @@ struct csfmm_workspace_s {
     // side stream of the PP near field, with its fork and join events
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
-    ~csfmm_workspace_s() {
-        if (fork) (void)hipEventDestroy(fork);
-        if (join) (void)hipEventDestroy(join);
-        if (side) (void)hipStreamDestroy(side);
-        arena.release();
-    }
+    ~csfmm_workspace_s();
 };
+
+namespace csfmm {
+// Side streams are kept for reuse (creating one takes longer than building a
+// small plan); a released stream has no work pending (destroying a workspace
+// waits for the device first).
+hipError_t acquire_side_stream(hipStream_t* s);
+void release_side_stream(hipStream_t s);
+}  // namespace csfmm
+
+inline csfmm_workspace_s::~csfmm_workspace_s() {
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) csfmm::release_side_stream(side);
+    arena.release();
+}
 
 inline csfmm_plan_s::~csfmm_plan_s() {
     for (hipEvent_t e : timing.ev) (void)hipEventDestroy(e);

@@ -12,6 +12,7 @@
 // request's result does not depend on what it is batched with.
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <utility>
 
@@ -806,6 +807,38 @@ int timing_collect(csfmm_plan_s* P) {
     return CSFMM_OK;
 }
 
+namespace {
+std::mutex g_side_mu;
+std::vector<hipStream_t> g_side_free[64];  // per device
+}  // namespace
+
+hipError_t acquire_side_stream(hipStream_t* s) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev >= 0 && dev < 64) {
+        std::lock_guard<std::mutex> lk(g_side_mu);
+        if (!g_side_free[dev].empty()) {
+            *s = g_side_free[dev].back();
+            g_side_free[dev].pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+}
+
+void release_side_stream(hipStream_t s) {
+    int dev = -1;
+    if (hipStreamGetDevice(s, &dev) == hipSuccess && dev >= 0 && dev < 64) {
+        std::lock_guard<std::mutex> lk(g_side_mu);
+        if (g_side_free[dev].size() < 64) {
+            g_side_free[dev].push_back(s);
+            return;
+        }
+    }
+    (void)hipStreamDestroy(s);
+}
+
 int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** out) {
     *out = nullptr;
     csfmm_workspace_s* W = new (std::nothrow) csfmm_workspace_s();
@@ -816,23 +849,23 @@ int workspace_create(csfmm_plan_s* P, hipStream_t stream, csfmm_workspace_s** ou
     W->plan = P;
     const Tree& T = P->tt;
     const Tree& S = *P->st;
-    int rc = CSFMM_OK;
-    if (rc == CSFMM_OK) rc = W->arena.alloc(&W->ws, P->ns);
-    if (rc == CSFMM_OK) rc = W->arena.alloc(&W->wbar, int64_t(S.ncells) * P->KS);
-    if (rc == CSFMM_OK) rc = W->arena.alloc(&W->psi, int64_t(3) * T.ncells * P->KS);
-    if (rc == CSFMM_OK) rc = W->arena.alloc(&W->phinear, int64_t(3) * P->nt);
-    if (rc == CSFMM_OK) rc = W->arena.alloc(&W->phipc, int64_t(3) * P->nt);
-    if (rc == CSFMM_OK && sym_path_possible(P)) {
-        char* c = nullptr;
-        rc = W->arena.alloc(&c, sym_value_bytes(P) * P->lists.sym.n_own * kWaveLeaf);
-        W->sym_col = c;
-    }
-    if (rc == CSFMM_OK) rc = W->arena.alloc(&W->dview, 1);
+    // one allocation (csfmm_workspace_bytes counts the same arrays)
+    ArenaGroup G;
+    char* sym = nullptr;
+    G.add(&W->ws, P->ns);
+    G.add(&W->wbar, int64_t(S.ncells) * P->KS);
+    G.add(&W->psi, int64_t(3) * T.ncells * P->KS);
+    G.add(&W->phinear, int64_t(3) * P->nt);
+    G.add(&W->phipc, int64_t(3) * P->nt);
+    if (sym_path_possible(P)) G.add(&sym, sym_value_bytes(P) * P->lists.sym.n_own * kWaveLeaf);
+    G.add(&W->dview, 1);
+    int rc = G.commit(W->arena);
     if (rc != CSFMM_OK) {
         delete W;
         return rc;
     }
-    hipError_t se = hipStreamCreateWithFlags(&W->side, hipStreamNonBlocking);
+    W->sym_col = sym;
+    hipError_t se = acquire_side_stream(&W->side);
     if (se == hipSuccess) se = hipEventCreateWithFlags(&W->fork, hipEventDisableTiming);
     if (se == hipSuccess) se = hipEventCreateWithFlags(&W->join, hipEventDisableTiming);
     if (se != hipSuccess) {

@@ -733,31 +733,37 @@ __device__ __forceinline__ bool pp_close(const CloseGeom& G, int t, int s) {
 // Sort key of a (target, source) entry: by target, then (PP only) the
 // overlapping entries, the close ones (classify_close) and the others, then by
 // source:  t*3ns + class*ns + s.
+// Sort key of list entry k: base + target * 3 ns + class * ns + source (class
+// 0 overlapping, 1 close, 2 other; only PP entries are classed); `base`
+// places the four lists one after the other in one sort.
 __global__ void k_pair_keys(const int32_t* __restrict__ t, const int32_t* __restrict__ s, int64_t n,
                             int64_t ns_cells, bool mark_overlap, bool classify_close, CellIds TC,
-                            CellIds SC, CloseGeom G, uint64_t* __restrict__ keys,
+                            CellIds SC, CloseGeom G, uint64_t base, uint64_t* __restrict__ keys,
                             int32_t* __restrict__ vals) {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const bool ovl = mark_overlap && cells_overlap(TC, t[k], SC, s[k]);
     const int cls = ovl ? 0 : ((classify_close && pp_close(G, t[k], s[k])) ? 1 : 2);
-    keys[k] = uint64_t(t[k]) * uint64_t(3 * ns_cells) + uint64_t(cls) * uint64_t(ns_cells) +
+    keys[k] = base + uint64_t(t[k]) * uint64_t(3 * ns_cells) + uint64_t(cls) * uint64_t(ns_cells) +
               uint64_t(s[k]);
     vals[k] = int32_t(k);
 }
 
+// CSR of one list from its sorted keys (with the list's `base` removed: base
+// is a multiple of 3 ns, so the source is the key mod ns as before)
 __global__ void k_csr_from_keys(const uint64_t* __restrict__ keys, int64_t n, int64_t ns_cells,
-                                int nt_cells, int32_t* __restrict__ off, int32_t* __restrict__ src,
-                                int32_t* __restrict__ novl, int32_t* __restrict__ ncl) {
+                                int nt_cells, uint64_t base, int32_t* __restrict__ off,
+                                int32_t* __restrict__ src, int32_t* __restrict__ novl,
+                                int32_t* __restrict__ ncl) {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint64_t ns3 = uint64_t(3 * ns_cells), ns1 = uint64_t(ns_cells);
     if (k < n) src[k] = int32_t((keys[k] % ns3) % ns1);
     if (k <= nt_cells) {
-        const int64_t b = lower_bound_u64(keys, 0, n, uint64_t(k) * ns3);
+        const int64_t b = lower_bound_u64(keys, 0, n, base + uint64_t(k) * ns3);
         off[k] = int32_t(b);
         if (novl && k < nt_cells) {
-            const int64_t b1 = lower_bound_u64(keys, b, n, uint64_t(k) * ns3 + ns1);
-            const int64_t b2 = lower_bound_u64(keys, b1, n, uint64_t(k) * ns3 + 2 * ns1);
+            const int64_t b1 = lower_bound_u64(keys, b, n, base + uint64_t(k) * ns3 + ns1);
+            const int64_t b2 = lower_bound_u64(keys, b1, n, base + uint64_t(k) * ns3 + 2 * ns1);
             novl[k] = int32_t(b1 - b);
             ncl[k] = int32_t(b2 - b1);
         }
@@ -1069,24 +1075,36 @@ int build_lists(csfmm_plan_s* P, hipStream_t s) {
         }
         RC(G.commit(A));
     }
+    // the four lists in one sort: list k's keys start at k * maxkey (a multiple
+    // of 3 ns), so after the sort they are the run [first[k], first[k] + cnt[k])
+    const bool one_sort = maxkey < (int64_t(1) << 60);
+    int64_t first[5] = {0, 0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k) first[k + 1] = first[k] + out[k].n;
+    const int64_t span = one_sort ? 4 * maxkey : maxkey;
     int bits = 1;
-    while (bits < 63 && (int64_t(1) << bits) < maxkey) ++bits;
+    while (bits < 63 && (int64_t(1) << bits) < span) ++bits;
+    uint64_t* keys;
+    int32_t* vals;
+    RC(S.get(&keys, first[4]));
+    RC(S.get(&vals, first[4]));
     for (int k = 0; k < 4; ++k) {
         const int64_t cnt = out[k].n;
-        uint64_t* keys;
-        int32_t* vals;
-        RC(S.get(&keys, cnt));
-        RC(S.get(&vals, cnt));
+        const uint64_t base = one_sort ? uint64_t(k) * uint64_t(maxkey) : 0;
         if (cnt > 0) {
             k_pair_keys<<<nblk(cnt), kT, 0, s>>>(out[k].t, out[k].s, cnt, nsc, k == kPP,
                                                  k == kPP && classify_close, tcid, scid, cg,
-                                                 keys, vals);
+                                                 base, keys + first[k], vals + first[k]);
             CSFMM_LAUNCH_CHECK();
-            RC(radix_sort_u64(keys, vals, cnt, bits, S, s));
+            if (!one_sort) RC(radix_sort_u64(keys + first[k], vals + first[k], cnt, bits, S, s));
         }
+    }
+    if (one_sort) RC(radix_sort_u64(keys, vals, first[4], bits, S, s));
+    for (int k = 0; k < 4; ++k) {
+        const int64_t cnt = out[k].n;
+        const uint64_t base = one_sort ? uint64_t(k) * uint64_t(maxkey) : 0;
         const int64_t m = std::max<int64_t>(cnt, int64_t(T.ncells) + 1);
-        k_csr_from_keys<<<nblk(m), kT, 0, s>>>(keys, cnt, nsc, T.ncells, P->lists.off[k],
-                                               P->lists.src[k],
+        k_csr_from_keys<<<nblk(m), kT, 0, s>>>(keys + first[k], cnt, nsc, T.ncells, base,
+                                               P->lists.off[k], P->lists.src[k],
                                                k == kPP ? P->lists.novl : nullptr,
                                                k == kPP ? P->lists.ncl : nullptr);
         CSFMM_LAUNCH_CHECK();
@@ -1215,8 +1233,12 @@ int build_plan(csfmm_plan_s* P, const double* targets, const double* sources, hi
     }
     // fixed interpolation operators
     P->nb1 = int(round_up(P->KS, 16));
-    RC(A.alloc(&P->lag1d, 2 * (P->p + 1) * (P->p + 1)));
-    RC(A.alloc(&P->bm2m, int64_t(4) * P->KS * P->nb1));
+    {
+        ArenaGroup G;
+        G.add(&P->lag1d, 2 * (P->p + 1) * (P->p + 1));
+        G.add(&P->bm2m, int64_t(4) * P->KS * P->nb1);
+        RC(G.commit(A));
+    }
     k_build_ops<<<1, 256, 0, s>>>(P->p, P->KS, P->nb1, P->lag1d, P->bm2m);
     CSFMM_LAUNCH_CHECK();
     RC(build_lists(P, s));
