@@ -149,6 +149,9 @@ CASES = {
     # 6,144 leaves of 9 points: the one-wave-per-leaf path and the symmetric
     # PP pairs (both forms); the smaller cases keep the block path
     "grid_E96_leaf16": lambda: (cubed_sphere_grid(96)[0], None, 1, 4, 0.7, 16),
+    # the same leaves for Biot-Savart (one direction at a time: no symmetric
+    # pairs for its vector kernel)
+    "bs_grid_E96_leaf16": lambda: (cubed_sphere_grid(96)[0], None, 2, 4, 0.7, 16),
     # high degrees: P2M with two leaves per block (p >= 12), L2P of three
     # components at p = 12 (LDS near its limit); PC (p = 14) and CC (p = 12) present
     "high_p14": lambda: (cubed_sphere_grid(32)[0], None, 1, 14, 0.5, 64),
@@ -397,7 +400,7 @@ def test_fp32_random_points(kernel):
     assert rel_l2(near, on) < 3e-5 and rel_max(near, on) < 1e-4
 
 
-@pytest.mark.parametrize("kernel", [1, 3])
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 def test_fp32_random_points_wave_path(kernel):
     """Many small leaves of uniform random points: the one-wave-per-leaf near
     field, its close entries in exact differences and one way, the others as
