@@ -20,6 +20,9 @@ _FACES = (
     ((0.0, 0.0, 1.0), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0)),
     ((0.0, 0.0, -1.0), (0.0, 1.0, 0.0), (1.0, 0.0, 0.0)),
 )
+# Public name of the face order: point f E^2 + i E + j of cubed_sphere_grid(E)
+# is the centre of cell (i, j) of face f, i along the first tangent.
+CUBE_FACES = _FACES
 
 
 def _solid_angle_corner(X, Y):
