@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--bve", action="store_true",
                     help="barotropic vorticity equation, Rossby-Haurwitz wave, RK4 (paper §12)")
     ap.add_argument("--bve-k", type=int, default=7)
+    ap.add_argument("--bve-e", type=int, default=165,
+                    help="cubed-sphere cells per face edge of the remeshed BVE runs")
     ap.add_argument("--configs", action="store_true",
                     help="the other workloads: Poisson E=32, Biot-Savart E=512, 1/|x-y| 6.3M x 1M")
     ap.add_argument("--extras", action="store_true",
@@ -401,7 +403,9 @@ def bve_bench(args):
     N = 163,842), RK4 with dt = 0.01 day to t = 1 day, velocity by CSFMM
     (MAC 0.7, n = 6, leaf 4n^2; FP64 and the FP32 form) and by the FP64 direct
     sum (timed over the first 10 steps, error after 100); every stage rebuilds
-    the plan.  Reports time per step and E_zeta at 1 day (eq. bveerr)."""
+    the plan.  Reports time per step and E_zeta at 1 day (eq. bveerr).  The
+    same run on the cubed-sphere grid remeshed after every step (§12) times
+    the step with its remesh, and the remesh alone over the first 10 steps."""
     import torch
     import paper_2508_13550_amd as cs
     from workloads import icosahedral_grid, rh_vorticity
@@ -434,13 +438,49 @@ def bve_bench(args):
         e = vorticity_error(x.cpu().numpy(), z.cpu().numpy())
         runs[name] = {"s_per_step": total / 100, "s_per_step_first10": t10 / 10,
                       "E_zeta_1day": e}
+    # remeshed after every step (csfmm_bve_remesh) on the cubed-sphere grid
+    from workloads import cubed_sphere_grid
+    E = args.bve_e
+    Pc, Ac = cubed_sphere_grid(E)
+    Nc = Pc.shape[0]
+    ac = torch.tensor(Ac, dtype=torch.float64, device="cuda")
+    g = torch.tensor(Pc, dtype=torch.float64, device="cuda")
+    for name, kw in (("csfmm_fp64_remeshed", dict(fp32=False, use_direct=False)),
+                     ("direct_fp64_remeshed", dict(fp32=False, use_direct=True))):
+        x = g.clone()
+        z = torch.tensor(rh_vorticity(Pc), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_rm = 0.0
+        for step in range(100):
+            cs.bve_rk4_step(x, z, ac, 0.01, p=6, theta=0.7, leaf_size=144, **kw)
+            if step < 10:
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+            cs.bve_remesh(g, E, x, z)
+            if step < 10:
+                torch.cuda.synchronize()
+                t_rm += time.perf_counter() - t1
+            if (step + 1) % 20 == 0:
+                print("bve %s step %d" % (name, step + 1), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        zc = z.cpu().numpy()
+        z0 = rh_vorticity(Pc)
+        e = float(np.sqrt(np.sum((zc - z0) ** 2 * Ac) / np.sum(z0 ** 2 * Ac)))
+        runs[name] = {"s_per_step": total / 100, "remesh_s_per_step_first10": t_rm / 10,
+                      "E_zeta_1day": e}
     line = {"metric": "BVE Rossby-Haurwitz wave: time per RK4 step and E_zeta at 1 day",
             "n_gpus": 1, "data": "synthetic",
             "config": {"workload": "icosahedral k=%d (N=%d), dt=0.01 day, 100 steps, "
-                                   "MAC 0.7, n=6, leaf 144" % (args.bve_k, N)},
+                                   "MAC 0.7, n=6, leaf 144; remeshed runs: cubed-sphere "
+                                   "E=%d (N=%d), remeshed after every step"
+                                   % (args.bve_k, N, E, Nc)},
             "runs": runs,
             "csfmm_speedup_over_direct": runs["direct_fp64"]["s_per_step"] /
-            runs["csfmm_fp64"]["s_per_step"]}
+            runs["csfmm_fp64"]["s_per_step"],
+            "csfmm_speedup_over_direct_remeshed": runs["direct_fp64_remeshed"]["s_per_step"] /
+            runs["csfmm_fp64_remeshed"]["s_per_step"]}
     print(json.dumps(line), flush=True)
 
 

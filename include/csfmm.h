@@ -190,6 +190,40 @@ int csfmm_bve_rk4_step(double* x, double* zeta, const double* area, int64_t n, d
                        int use_direct, void* stream);
 
 /*
+ * Remeshing of the vortex particles (paper §12: after every step, by local
+ * biquadratic interpolation) onto the equiangular cubed-sphere grid of E cells
+ * per face edge, N = 6 E^2.  The particles started the step at the cell
+ * centres and ended at x.  Each cell centre y takes the vorticity that the
+ * flow carried to it.  Its departure point a solves normalize(a + D(a)) = y,
+ * with D the biquadratic interpolant of the displacements x - grid, by 8
+ * fixed-point steps a <- normalize(y - D(a)) from a = y.  The new vorticity
+ * is q(a) - 2 omega z(y), with q the interpolant of the absolute vorticities
+ * zeta + 2 omega z(x).  Interpolation uses the 3 x 3 stencil of the nearest
+ * node on the face of the point, with the three-point Lagrange weights in
+ * the face angles.  Nodes beyond a face edge are ghosts: each lies on a node
+ * line of the neighbouring face, where its value comes from a stencil
+ * clamped to that face.
+ *   grid [N][3] device: the cell centres.  Point f E^2 + i E + j is the
+ *     centre of cell (i, j) of face f, at face angles
+ *     -pi/4 + (i + 1/2) pi/(2E) along e1 and -pi/4 + (j + 1/2) pi/(2E) along
+ *     e2.  The frames (n, e1, e2) of faces 0..5 are:
+ *       (+x, +y, +z), (-x, +z, +y), (+y, +z, +x),
+ *       (-y, +x, +z), (+z, +x, +y), (-z, +y, +x).
+ *     Must not overlap x.
+ *   x [N][3] device: the particles' end positions in grid order.  Set to
+ *     grid on return.
+ *   zeta [N] device: the particles' vorticity, replaced by the remeshed
+ *     vorticity at the cell centres.
+ *   omega: the rotation rate.
+ * Asynchronous on `stream`; the call allocates 32 N bytes of stream-ordered
+ * scratch.
+ * Errors: CSFMM_E_INVALID (NULL arrays, E outside [3, 16384], a non-finite
+ * omega, grid overlapping x), CSFMM_E_OOM, CSFMM_E_HIP.
+ */
+int csfmm_bve_remesh(const double* grid, int64_t E, double* x, double* zeta, double omega,
+                     void* stream);
+
+/*
  * Direct sum of paper eq. (nbodysum) over all pairs (the O(N^2) method of §1):
  * out[i] = sum_j K(x_i, y_j) w_j with exact coincidences omitted.
  *   targets [n_t][3], sources [n_s][3], weights [n_s], out [n_t] or [n_t][3].

@@ -33,9 +33,11 @@ Readings:
     on the nearest node and the product of the three-point Lagrange weights in
     the uniform angle spacing.  Stencil nodes beyond the face edge are ghost
     nodes at the same angle spacing; in the gnomonic projection a ghost node
-    lies on a node line of the neighbouring face, and its value is
+    lies on a node line of the face across that edge, and its value is
     interpolated there with the stencil clamped to that face (a quadratic
-    along the line).  (Stencils clamped at the edges instead, one-sided,
+    along the line).  A corner ghost (beyond both edges) is equidistant from
+    the faces across the two edges and takes the one across its first
+    angle's edge.  (Stencils clamped at the edges instead, one-sided,
     amplify a node-to-node zigzag when a step moves points more than a
     quarter cell, and remeshing every step makes that grow.)  After the
     remap the particles sit at the cell centres again.  parity pinned by
@@ -99,9 +101,10 @@ def _faces():
     return F[:, 0], F[:, 1], F[:, 2]
 
 
-def _face_angles(a):
+def _face_angles(a, f=None):
     n, e1, e2 = _faces()
-    f = np.argmax(a @ n.T, axis=1)
+    if f is None:
+        f = np.argmax(a @ n.T, axis=1)
     an = np.einsum("ij,ij->i", a, n[f])
     xi = np.arctan(np.einsum("ij,ij->i", a, e1[f]) / an)
     eta = np.arctan(np.einsum("ij,ij->i", a, e2[f]) / an)
@@ -117,12 +120,12 @@ def _stencil(ang, d, lo, hi):
     return c, _lagrange3((ang - (-np.pi / 4.0 + (c + 0.5) * d)) / d)
 
 
-def biquadratic_clamped(values, E, a):
-    """Biquadratic interpolation on the face of a, the stencil clamped to that
-    face (one-sided within a cell of its edges)."""
+def biquadratic_clamped(values, E, a, face=None):
+    """Biquadratic interpolation on the face of a (or on `face`), the stencil
+    clamped to that face (one-sided within a cell of its edges)."""
     E = int(E)
     d = (np.pi / 2.0) / E
-    f, xi, eta = _face_angles(a)
+    f, xi, eta = _face_angles(a, face)
     (ci, wi), (cj, wj) = _stencil(xi, d, 1, E - 2), _stencil(eta, d, 1, E - 2)
     V = np.asarray(values, dtype=np.float64)
     out = 0.0
@@ -138,8 +141,10 @@ def biquadratic(values, E, a):
     """Local biquadratic interpolation of grid values [6 E^2, ...] at unit
     vectors a [m, 3]: the 3 x 3 stencil centred on the nearest node of a's
     face; a stencil node beyond the face edge (angle index -1 or E) takes the
-    value at its own position, which lies on a node line of the neighbouring
-    face, by biquadratic_clamped there."""
+    value at its own position, which lies on a node line of the face across
+    that edge, by biquadratic_clamped there.  A corner node (both indices
+    beyond) is as far from the faces across either edge; it takes the face
+    across its first angle's edge, so that no rounding decides."""
     E = int(E)
     n, e1, e2 = _faces()
     d = (np.pi / 2.0) / E
@@ -159,20 +164,26 @@ def biquadratic(values, E, a):
                 ta = np.tan(-np.pi / 4.0 + (i[g] + 0.5) * d)
                 tb = np.tan(-np.pi / 4.0 + (j[g] + 0.5) * d)
                 p = n[f[g]] + ta[:, None] * e1[f[g]] + tb[:, None] * e2[f[g]]
-                v[g] = biquadratic_clamped(V, E, _project(p))
+                # the face across the edge: normal -e1 / +e1 if the first
+                # index is beyond, else -e2 / +e2
+                across = np.where((i[g] < 0)[:, None], -e1[f[g]],
+                                  np.where((i[g] >= E)[:, None], e1[f[g]],
+                                           np.where((j[g] < 0)[:, None], -e2[f[g]], e2[f[g]])))
+                v[g] = biquadratic_clamped(V, E, _project(p), face=np.argmax(across @ n.T, axis=1))
             w = wi[di] * wj[dj]
             out = out + (w[:, None] * v if V.ndim == 2 else w * v)
     return out
 
 
-def remesh(grid, E, x, zeta, omega=OMEGA, iters=REMESH_ITERS):
+def remesh(grid, E, x, zeta, omega=OMEGA, iters=REMESH_ITERS, sample=None):
     """Remap particles that started a step at the cell centres `grid`
     (cubed_sphere_grid(E) order) and ended at x with vorticity zeta back onto
     the cell centres; returns the new vorticity there (the positions are the
-    grid again)."""
-    y = np.asarray(grid, dtype=np.float64)
-    D = np.asarray(x, dtype=np.float64) - y
+    grid again), or at the cell centres grid[sample] only."""
+    Y = np.asarray(grid, dtype=np.float64)
+    D = np.asarray(x, dtype=np.float64) - Y
     q = np.asarray(zeta, dtype=np.float64) + 2.0 * omega * np.asarray(x)[:, 2]
+    y = Y if sample is None else Y[sample]
     a = y.copy()
     for _ in range(iters):
         a = _project(y - biquadratic(D, E, a))

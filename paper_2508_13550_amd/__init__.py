@@ -71,7 +71,7 @@ EXPORTED = (
     "csfmm_plan_proxies", "csfmm_plan_permutation", "csfmm_plan_list", "csfmm_eval_stages",
     "csfmm_plan_timing", "csfmm_plan_timing_read", "csfmm_workspace_create",
     "csfmm_workspace_destroy", "csfmm_workspace_bytes", "csfmm_eval_many",
-    "csfmm_eval_treecode", "csfmm_bve_rk4_step", "csfmm_direct_noalloc",
+    "csfmm_eval_treecode", "csfmm_bve_rk4_step", "csfmm_bve_remesh", "csfmm_direct_noalloc",
     "csfmm_workspace_device_bytes",
 )
 
@@ -97,6 +97,7 @@ def load_library(path=LIB_PATH):
     L.csfmm_bve_rk4_step.argtypes = [dp, dp, dp, i64, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_uint,
                                      ctypes.c_int, vp]
+    L.csfmm_bve_remesh.argtypes = [dp, i64, dp, dp, ctypes.c_double, vp]
     L.csfmm_direct.argtypes = [dp, i64, dp, i64, dp, ctypes.c_int, ctypes.c_uint, dp, vp]
     L.csfmm_direct_noalloc.argtypes = L.csfmm_direct.argtypes
     L.csfmm_plan_destroy.argtypes = [vp]
@@ -398,6 +399,25 @@ def bve_rk4_step(x, zeta, area, dt, omega=2.0 * 3.141592653589793, p=6, theta=0.
                                    float(omega), int(p), float(theta), int(leaf_size),
                                    FP32_FORM if fp32 else FP64, 1 if use_direct else 0,
                                    _stream()))
+    return x, zeta
+
+
+def bve_remesh(grid, E, x, zeta, omega=2.0 * 3.141592653589793):
+    """csfmm_bve_remesh: map particles that started a step at the cells of
+    the equiangular cubed-sphere grid `grid` (cubed_sphere_grid(E) order) back
+    onto them; x becomes grid and zeta the remeshed vorticity (in place)."""
+    _require_gpu()
+    E = int(E)
+    n = 6 * E * E
+    g = _points(grid, "grid")
+    xp = _points(x, "x")
+    z = _vec(zeta, n, "zeta")
+    if g.shape[0] != n or xp.shape[0] != n:
+        raise ValueError("grid and x must hold 6 E^2 = %d points" % n)
+    if xp.data_ptr() != x.data_ptr() or z.data_ptr() != zeta.data_ptr():
+        raise ValueError("x and zeta must be contiguous float64 CUDA tensors (updated in place)")
+    _check(_lib.csfmm_bve_remesh(g.data_ptr(), E, xp.data_ptr(), z.data_ptr(), float(omega),
+                                 _stream()))
     return x, zeta
 
 

@@ -58,3 +58,117 @@ def test_bve_csfmm_error_equals_direct(k):
     assert abs(e_fmm - e_dir) < 0.01 * e_dir
     assert np.abs(res[True][0] - res[False][0]).max() < 1e-5
     assert e_dir < (1.5e-2 if k == 4 else 1.5e-3)
+
+
+# ---- remeshing (csfmm_bve_remesh) against the oracle's remap
+
+import math
+
+from workloads import cubed_sphere_grid, config_subset
+
+
+def _moved(P, E, seed):
+    """End positions of a step: a rigid turn of about half a cell plus a
+    smooth swirl, and a smooth vorticity (seeded)."""
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal(3)
+    u /= np.linalg.norm(u)
+    ang = 0.5 * (math.pi / 2) / E
+    K = np.array([[0, -u[2], u[1]], [u[2], 0, -u[0]], [-u[1], u[0], 0]])
+    R = np.eye(3) + math.sin(ang) * K + (1 - math.cos(ang)) * K @ K
+    X = P @ R.T
+    X = X + 0.2 * ang * np.sin(3 * P[:, [1, 2, 0]])
+    X /= np.linalg.norm(X, axis=1)[:, None]
+    zeta = np.cos(2 * P[:, 0]) * P[:, 1] + rng.standard_normal() * P[:, 2]
+    # (a large matmul may hand back Fortran order; the binding updates in place)
+    return np.ascontiguousarray(X), np.ascontiguousarray(zeta)
+
+
+@pytest.mark.parametrize("E", [3, 16, 37])
+def test_remesh_matches_oracle(E):
+    """Every cell centre at E = 3 (all stencils reach ghost nodes), 16 and 37
+    (odd): the remeshed vorticity equals the oracle's to 1e-12 of its
+    largest value, and the particles are back at the cell centres exactly."""
+    say("bve remesh vs oracle, E=%d" % E)
+    P, A = cubed_sphere_grid(E)
+    X, zeta = _moved(P, E, 100 + E)
+    om = 2 * math.pi
+    want = obve.remesh(P, E, X, zeta, omega=om)
+    g = torch.tensor(P, dtype=torch.float64, device="cuda")
+    x = torch.tensor(X, dtype=torch.float64, device="cuda")
+    z = torch.tensor(zeta, dtype=torch.float64, device="cuda")
+    cs.bve_remesh(g, E, x, z, omega=om)
+    got = z.cpu().numpy()
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print("E=%d max rel diff %.3e" % (E, err), flush=True)
+    assert err < 1e-12
+    assert np.array_equal(x.cpu().numpy(), P)
+
+
+def test_remesh_rejects_bad_arguments():
+    say("bve remesh argument checks")
+    P, A = cubed_sphere_grid(4)
+    g = torch.tensor(P, dtype=torch.float64, device="cuda")
+    z = torch.zeros(P.shape[0], dtype=torch.float64, device="cuda")
+    with pytest.raises(RuntimeError):
+        cs.bve_remesh(g, 4, g, z)           # grid overlaps x
+    P2, _ = cubed_sphere_grid(2)
+    g2 = torch.tensor(P2, dtype=torch.float64, device="cuda")
+    with pytest.raises(RuntimeError):
+        cs.bve_remesh(g2, 2, g2.clone(), torch.zeros(24, dtype=torch.float64, device="cuda"))
+
+
+def test_remesh_full_size_on_sampled_cells():
+    """E = 512 (N = 1,572,864, the largest grid of the benchmarks): 4,096
+    seeded cell centres against the oracle's remap of the same particles."""
+    E = 512
+    say("bve remesh at E=%d, 4,096 sampled cells" % E)
+    P, A = cubed_sphere_grid(E)
+    X, zeta = _moved(P, E, 7)
+    S = config_subset(P.shape[0], 4096, 8)
+    want = obve.remesh(P, E, X, zeta, sample=S)
+    g = torch.tensor(P, dtype=torch.float64, device="cuda")
+    x = torch.tensor(X, dtype=torch.float64, device="cuda")
+    z = torch.tensor(zeta, dtype=torch.float64, device="cuda")
+    cs.bve_remesh(g, E, x, z)
+    got = z.cpu().numpy()[S]
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print("E=%d sampled max rel diff %.3e" % (E, err), flush=True)
+    assert err < 1e-12
+
+
+def _remeshed_run(E, steps, direct, p=6, theta=0.7):
+    P, A = cubed_sphere_grid(E)
+    g = torch.tensor(P, dtype=torch.float64, device="cuda")
+    a = torch.tensor(A, dtype=torch.float64, device="cuda")
+    x = g.clone()
+    z = torch.tensor(obve.rh_vorticity(P), dtype=torch.float64, device="cuda")
+    for _ in range(steps):
+        cs.bve_rk4_step(x, z, a, 0.01, p=p, theta=theta, leaf_size=64, use_direct=direct)
+        cs.bve_remesh(g, E, x, z)
+    return P, A, z.cpu().numpy()
+
+
+def test_remeshed_bve_direct_matches_oracle():
+    """The Rossby-Haurwitz wave on the cubed-sphere grid (E = 16), each of 10
+    RK4 steps followed by a remesh, direct-sum velocity: the vorticity at the
+    cell centres equals the oracle's run to rounding."""
+    say("remeshed bve, direct velocity, E=16, 10 steps")
+    P, A, got = _remeshed_run(16, 10, True)
+    want = obve.run_remeshed(P, A, 16, 10)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print("max rel diff %.3e, E_zeta %.4e" % (err, obve.vorticity_error(P, got, A)), flush=True)
+    assert err < 1e-11
+
+
+def test_remeshed_bve_csfmm_error_equals_direct():
+    """E = 64 (N = 24,576), 10 remeshed steps: the CSFMM velocity (MAC 0.7,
+    n = 6) gives the vorticity error of the direct-sum velocity within 1%, at
+    the oracle's second-order level (2.5e-4 at this grid)."""
+    say("remeshed bve, csfmm vs direct velocity, E=64, 10 steps")
+    P, A, zd = _remeshed_run(64, 10, True)
+    _, _, zf = _remeshed_run(64, 10, False)
+    ed, ef = obve.vorticity_error(P, zd, A), obve.vorticity_error(P, zf, A)
+    print("E_zeta direct %.4e csfmm %.4e" % (ed, ef), flush=True)
+    assert abs(ef - ed) < 0.01 * ed
+    assert ed < 3e-4
