@@ -321,11 +321,15 @@ __global__ __launch_bounds__(256) void k_m2m_cells(Batch b) {
 // each level is two 1-D passes over the (p+1) x (p+1) proxy array:
 //   t[n1][m2] = sum_m1 A_bi[n1][m1] psi[m1][m2],
 //   psi'[n1][n2] = own[n1][n2] + sum_m2 A_bj[n2][m2] t[n1][m2],
-// starting from the root's own proxy potential.  The wave walks its leaf's
-// path from the root (a table built with the plan; the upper levels are
-// recomputed per leaf instead of one launch per level) and loads each level's
-// own proxy potential one level ahead.  The accumulated proxy potential of the
-// leaf is stored back into psi (no other wave reads a leaf's psi).
+// starting from the root's own proxy potential.  The levels the block's
+// leaves share (their common ancestors: all but the last for four sibling
+// leaves) are computed once, by the whole block, one element a thread; each
+// wave then walks the rest of its leaf's path (a table built with the plan;
+// upper levels recomputed per block instead of one launch per level), loading
+// each level's own proxy potential one level ahead.  Both follow the same
+// order of operations, so the result does not depend on how the chain was
+// split.  The accumulated proxy potential of the leaf is stored back into psi
+// (no other wave reads a leaf's psi).
 // The occupancy hint holds the scalar kernels of degree p <= 6 at 80 VGPRs
 // (6 waves per SIMD, no spills): 6,144 leaves then fit the device at once.
 template <int VD, int P1>
@@ -337,6 +341,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VD == 1 && 
     __shared__ double psw[4][VD][K], tbw[4][VD][K];
     __shared__ double opw[4][2][K];  // shrunk plans: the child's own factors
     __shared__ int ancw[4][kAncStride];
+    __shared__ int ncom, wref;
     int r, local;
     locate(b, r, local);
     const ReqView& V = *b.v[r];
@@ -344,40 +349,135 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VD == 1 && 
     // nodes, weights and 1-D factors, shared by the block's waves (one request)
     cheb_setup(P1 - 1, s, beta);
     for (int k = threadIdx.x; k < 2 * K; k += blockDim.x) (&A1[0][0][0])[k] = V.lag1d[k];
-    __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
     const int leaf = 4 * local + wave;
-    if (leaf >= V.nleaves_t) return;  // the whole wave leaves
-    const int c = V.t_leaves[leaf];
-    const int bgn = V.t_begin[c], m = V.t_count[c];
-    if (m == 0) return;
+    const int tid = threadIdx.x & 63;
+    int c = 0, bgn = 0, m = 0;
+    if (leaf < V.nleaves_t) {
+        c = V.t_leaves[leaf];
+        bgn = V.t_begin[c];
+        m = V.t_count[c];
+    }
+    const bool has = m > 0;  // uniform over the wave
     double(&ps)[VD][K] = psw[wave];
     double(&tb)[VD][K] = tbw[wave];
     int* anc = ancw[wave];
     const int KS = V.KS;
-    const int tid = threadIdx.x & 63;
-    const int32_t* path = V.t_leaf_anc + int64_t(leaf) * kAncStride;
-    for (int k = tid; k < kAncStride; k += 64) anc[k] = path[k];
-    wave_lds_sync();
+    if (has) {
+        const int32_t* path = V.t_leaf_anc + int64_t(leaf) * kAncStride;
+        for (int k = tid; k < kAncStride; k += 64) anc[k] = path[k];
+    } else if (tid == 0) {
+        anc[0] = 0;  // no path
+    }
+    __syncthreads();
+    // the leading cells common to the paths of the block's leaves
+    if (threadIdx.x == 0) {
+        int lim = kAncStride, w0 = -1;
+        for (int w = 0; w < 4; ++w)
+            if (ancw[w][0] > 0) {
+                lim = min(lim, ancw[w][0]);
+                if (w0 < 0) w0 = w;
+            }
+        int n = 0;
+        if (w0 >= 0)
+            for (int l = 1; l <= lim; ++l) {
+                bool same = true;
+                for (int w = 0; w < 4; ++w)
+                    if (ancw[w][0] > 0 && ancw[w][l] != ancw[w0][l]) same = false;
+                if (!same) break;
+                n = l;
+            }
+        ncom = n;
+        wref = w0;
+    }
+    __syncthreads();
+    const int nc = ncom;
     const int na = anc[0];  // anc[1] is the root, anc[na] the leaf
+    auto own_at = [&](int cell, int k) {
+        return V.psi[(k / K) * V.psi_stride + int64_t(cell) * KS + k % K];
+    };
     // own proxy potential of a cell, this thread's elements (k = tid + 64 i)
     auto load_own = [&](int cell, double (&dst)[kRegs]) {
 #pragma unroll
         for (int i = 0; i < kRegs; ++i) {
             const int k = tid + 64 * i;
-            dst[i] = k < VD * K ? V.psi[(k / K) * V.psi_stride + int64_t(cell) * KS + k % K] : 0.0;
+            dst[i] = k < VD * K ? own_at(cell, k) : 0.0;
         }
     };
     double cur[kRegs], nxt[kRegs];
-    load_own(anc[1], cur);
+    const int l0 = nc >= 1 ? nc : 1;  // the wave's path goes on from its cell l0
+    // the wave's first own level after the shared ones, in flight meanwhile
+    if (has && na >= l0 + 1) load_own(anc[l0 + 1], nxt);
+    if (nc >= 1) {
+        // the shared levels, block-wide, in wave 0's arrays; each level's own
+        // proxy potential is loaded one level ahead
+        constexpr int kB = (VD * K + 255) / 256;
+        const int* ac = ancw[wref];
+        double(&bp)[VD][K] = psw[0];
+        double(&bt)[VD][K] = tbw[0];
+        double bown[kB];
+        for (int k = threadIdx.x; k < VD * K; k += blockDim.x) bp[k / K][k % K] = own_at(ac[1], k);
+        auto load_bown = [&](int cell) {
 #pragma unroll
-    for (int i = 0; i < kRegs; ++i) {
-        const int k = tid + 64 * i;
-        if (k < VD * K) ps[k / K][k % K] = cur[i];
+            for (int i = 0; i < kB; ++i) {
+                const int k = int(threadIdx.x) + 256 * i;
+                bown[i] = k < VD * K ? own_at(cell, k) : 0.0;
+            }
+        };
+        if (nc >= 2) load_bown(ac[2]);
+        __syncthreads();
+        for (int l = 2; l <= nc; ++l) {
+            const int ch = ac[l], par = ac[l - 1];
+            const int q = ch - V.t_child0[par];
+            const double* Ax = &A1[q >> 1][0][0];
+            const double* Ay = &A1[q & 1][0][0];
+            if (V.t_ops) {
+                const double* src = V.t_ops + int64_t(ch) * 2 * K;
+                for (int k = threadIdx.x; k < 2 * K; k += blockDim.x) (&opw[0][0][0])[k] = src[k];
+                __syncthreads();
+                Ax = &opw[0][0][0];
+                Ay = &opw[0][1][0];
+            }
+            for (int k = threadIdx.x; k < VD * K; k += blockDim.x) {
+                const int d = k / K, e = k % K, n1 = e / P1, m2 = e % P1;
+                double t = 0.0;
+#pragma unroll
+                for (int m1 = 0; m1 < P1; ++m1) t = fma(Ax[n1 * P1 + m1], bp[d][m1 * P1 + m2], t);
+                bt[d][e] = t;
+            }
+            __syncthreads();
+            double own[kB];
+#pragma unroll
+            for (int i = 0; i < kB; ++i) own[i] = bown[i];
+            if (l < nc) load_bown(ac[l + 1]);
+#pragma unroll
+            for (int i = 0; i < kB; ++i) {
+                const int k = int(threadIdx.x) + 256 * i;
+                if (k < VD * K) {
+                    const int d = k / K, e = k % K, n1 = e / P1, n2 = e % P1;
+                    double t = own[i];
+#pragma unroll
+                    for (int m2 = 0; m2 < P1; ++m2) t = fma(Ay[n2 * P1 + m2], bt[d][n1 * P1 + m2], t);
+                    bp[d][e] = t;
+                }
+            }
+            __syncthreads();
+        }
+        if (has && wave != 0)
+            for (int k = tid; k < VD * K; k += 64) ps[k / K][k % K] = bp[k / K][k % K];
+        __syncthreads();  // before wave 0 goes on in its arrays
     }
-    if (na >= 2) load_own(anc[2], nxt);
+    if (!has) return;  // the whole wave leaves (no block barrier after this)
+    if (nc == 0) {
+        load_own(anc[1], cur);
+#pragma unroll
+        for (int i = 0; i < kRegs; ++i) {
+            const int k = tid + 64 * i;
+            if (k < VD * K) ps[k / K][k % K] = cur[i];
+        }
+    }
     wave_lds_sync();
-    for (int l = 2; l <= na; ++l) {
+    for (int l = l0 + 1; l <= na; ++l) {
         const int ch = anc[l], par = anc[l - 1];
         const int q = ch - V.t_child0[par];
         const int bi = q >> 1, bj = q & 1;
