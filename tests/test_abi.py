@@ -82,3 +82,15 @@ def test_bve_argument_errors():
     assert f(1, 1, 1, 10, 0.0, 6.28, 6, 0.7, 64, 0, 0, None) == -1
     assert f(1, 1, 1, 10, 0.01, 6.28, 6, 0.7, 64, 8, 0, None) == -1
     assert "bve" in L.csfmm_last_error().decode() or "flags" in L.csfmm_last_error().decode()
+
+
+def test_bve_remesh_argument_errors():
+    """Host-side checks of csfmm_bve_remesh; none of these reaches the device."""
+    L = cs.load_library()
+    f = L.csfmm_bve_remesh
+    assert f(None, 4, 1, 1, 6.28, None) == -1
+    assert f(4096, 2, 1 << 20, 1 << 21, 6.28, None) == -1        # E < 3
+    assert f(4096, 1 << 15, 1 << 40, 1 << 41, 6.28, None) == -1  # E too large
+    assert f(4096, 4, 1 << 20, 1 << 21, float("inf"), None) == -1
+    assert f(4096, 4, 4096 + 8, 1 << 21, 6.28, None) == -1       # grid overlaps x
+    assert "remesh" in L.csfmm_last_error().decode()
