@@ -238,6 +238,95 @@ __global__ __launch_bounds__(256) void k_m2m(Batch b) {
     }
 }
 
+// The same product for levels of many parents (kM2mRowsMin or more), where
+// the tiles above would read each parent's children once per column tile:
+// one block per 32 parents and all nb1 columns: wave w takes the rows
+// 16 (w >> 1) .. +15 and every other 16-column tile from w & 1.  K runs in
+// chunks of 16: the block stages the chunk's A rows (32 x 16) and B rows
+// (16 x nb1) in LDS, each thread holding its share of the next chunk in
+// registers meanwhile, so the children's weights are read from HBM once and
+// B (shared by every block) from L2 once a chunk.
+// Measured on the 1/|x-y| workload's deepest level (24,576 parents, p = 10):
+// the eval 8.42 -> 8.29 ms in FP64; on levels of a few thousand parents the
+// 32-parent blocks leave most CUs idle, and the tiles above are faster.
+constexpr int kM2mRows = 32;
+constexpr int kM2mRowsMin = 8192;
+constexpr int kM2mMaxNb = ((kMaxP1 * kMaxP1 + 3) / 4 * 4 + 15) / 16 * 16;
+constexpr int kM2mMaxTiles = kM2mMaxNb / 16;
+// LDS row stride of the B chunk (doubles): rows 1 and 3 of an MFMA step fall
+// 128 bytes off rows 0 and 2, so a step's 64 lanes read in two conflict-free
+// passes
+__host__ __device__ constexpr int m2m_b_stride(int nb) { return nb % 32 == 0 ? nb + 16 : nb; }
+__global__ __launch_bounds__(256) void k_m2m_rows(Batch b) {
+    constexpr int kTW = (kM2mMaxTiles + 1) / 2;  // column tiles per wave
+    __shared__ double As[kM2mRows][16];
+    __shared__ double Bs[16 * m2m_b_stride(kM2mMaxNb)];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int r, local;
+    locate(b, r, local);
+    const ReqView& V = *b.v[r];
+    const int32_t* rows = V.s_parents + b.a0[r];
+    const int np = b.a1[r];
+    const int KS = V.KS, nb = V.nb1, K4 = 4 * KS;
+    const int ntiles = nb / 16, SB = m2m_b_stride(nb);
+    const int r0 = local * kM2mRows;
+    if (r0 >= np) return;  // uniform over the block
+    // A staging: thread t loads row t / 8, values 2 (t % 8) and 2 (t % 8) + 1
+    const int ar = tid >> 3, ak = 2 * (tid & 7);
+    const double* arow =
+        r0 + ar < np ? V.wbar + int64_t(V.s_child0[rows[r0 + ar]]) * KS : nullptr;
+    // B staging: thread t loads row t / 16 of the chunk, columns t % 16 + 16 j
+    const int br = tid >> 4, bc = tid & 15;
+    double a0 = 0.0, a1 = 0.0, bv[kM2mMaxTiles];
+    auto fetch = [&](int kc) {
+        if (arow) {
+            a0 = arow[kc + ak];
+            a1 = arow[kc + ak + 1];
+        }
+        const double* bsrc = V.bm2m + int64_t(kc + br) * nb + bc;
+#pragma unroll
+        for (int j = 0; j < kM2mMaxTiles; ++j) bv[j] = j < ntiles ? bsrc[16 * j] : 0.0;
+    };
+    const int rs = wave >> 1, ch = wave & 1;
+    const int l16 = lane & 15, kq = lane >> 4;
+    double4_t acc[kTW];
+#pragma unroll
+    for (int i = 0; i < kTW; ++i) acc[i] = double4_t{0.0, 0.0, 0.0, 0.0};
+    fetch(0);
+    for (int kc = 0; kc < K4; kc += 16) {
+        __syncthreads();  // the previous chunk is consumed
+        As[ar][ak] = a0;
+        As[ar][ak + 1] = a1;
+#pragma unroll
+        for (int j = 0; j < kM2mMaxTiles; ++j)
+            if (j < ntiles) Bs[br * SB + bc + 16 * j] = bv[j];
+        __syncthreads();
+        if (kc + 16 < K4) fetch(kc + 16);  // in flight while this chunk multiplies
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const double av = As[16 * rs + l16][4 * st + kq];
+            const double* brow = Bs + (4 * st + kq) * SB + l16;
+#pragma unroll
+            for (int i = 0; i < kTW; ++i) {
+                const int t = ch + 2 * i;
+                if (t < ntiles) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, brow[16 * t], acc[i], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kTW; ++i) {
+        const int col = 16 * (ch + 2 * i) + l16;
+        if (ch + 2 * i < ntiles && col < KS) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int rr = r0 + 16 * rs + kq + 4 * q;
+                if (rr < np) V.wbar[int64_t(rows[rr]) * KS + col] = acc[i][q];
+            }
+        }
+    }
+}
+
 // e3 M2M (eq. upwardpass2) of shrunk plans, one level: every parent has its
 // own operator (the children's boxes differ), so instead of one GEMM a wave
 // applies it to one parent (four per block) as two 1-D passes per child with
@@ -681,14 +770,20 @@ int launch_m2m(Batch& b, const EvalReq* reqs, int n, hipStream_t s, int lhi, int
     bool any_shrunk = false;
     for (int r = 0; r < n; ++r) any_shrunk = any_shrunk || reqs[r].plan->st->ops != nullptr;
     for (int l = lhi; l >= std::max(llo, 0); --l) {
+        int64_t blk_rows[kMaxBatch];
+        bool any_rows = false;
         for (int r = 0; r < n; ++r) {
             const Tree& S = *reqs[r].plan->st;
             const int np = l < S.depth ? S.parents_begin[l + 1] - S.parents_begin[l] : 0;
             b.a0[r] = l < S.depth ? S.parents_begin[l] : 0;
             b.a1[r] = np;
-            blk[r] = S.ops ? 0 : mfma_tiles(np, reqs[r].plan->nb1);
+            blk[r] = (S.ops || np >= kM2mRowsMin) ? 0 : mfma_tiles(np, reqs[r].plan->nb1);
+            blk_rows[r] = (S.ops || np < kM2mRowsMin) ? 0 : (int64_t(np) + kM2mRows - 1) / kM2mRows;
+            any_rows = any_rows || blk_rows[r] > 0;
         }
         RCX(launch_batched(b, blk, [&](unsigned g) { k_m2m<<<g, 256, 0, s>>>(b); }));
+        if (any_rows)
+            RCX(launch_batched(b, blk_rows, [&](unsigned g) { k_m2m_rows<<<g, 256, 0, s>>>(b); }));
         if (!any_shrunk) continue;
         for (int P1 = 2; P1 <= kMaxP1; ++P1) {
             bool any = false;
