@@ -606,7 +606,11 @@ struct TileSmem {
 };
 
 // One target cell of one request: near field (TPROX = false) or far field.
-template <int KERN, bool F32, bool TPROX>
+// The forms a launch can meet (kFormsAll, or kFormsPP: PP launches, no
+// MAC-separated form; kFormsFar: PC + far launches, that form only), so that
+// an instance holds no target registers for forms it never takes.
+enum { kFormsAll = 0, kFormsPP = 1, kFormsFar = 2 };
+template <int KERN, bool F32, bool TPROX, int FORMS = kFormsAll>
 __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
                                           TileSmem<KERN, F32>& sm) {
     using R = Real<F32>;
@@ -702,7 +706,7 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
             bnd[4] = e_pref[kMaxEntries];
 #pragma unroll
             for (int q = 1; q < 4; ++q) bnd[q] = e_pref[min(max(ph_hi[q - 1] - ebase, 0), kMaxEntries)];
-            for (int ph = 0; ph < 4; ++ph) {
+            for (int ph = FORMS == kFormsFar ? 3 : 0; ph < (FORMS == kFormsPP ? 3 : 4); ++ph) {
                 for (int q0 = bnd[ph]; q0 < bnd[ph + 1]; q0 += kTileChunk) {
                     const int nq = min(kTileChunk, bnd[ph + 1] - q0);
                     const int Tj = nq == kTileChunk ? Tj_full : group_len(nq, G);
@@ -742,14 +746,17 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
 #pragma unroll
                             for (int v = 0; v < VD; ++v) p[q][v] = R(0);
                         constexpr int CAP = lds_sources<F32>();
-                        if (ph == 0)
-                            run_group<KERN, F32, FORM_CHECK, CAP, TPT>(Lb, g * Tj, Tj, TR, p);
-                        else if (ph == 1)
-                            run_group<KERN, F32, FORM_EXACT, CAP, TPT>(Lb, g * Tj, Tj, TR, p);
-                        else if (ph == 2)
-                            run_group<KERN, F32, FORM_NEAR, CAP, TPT>(Lb, g * Tj, Tj, TR, p);
-                        else
-                            run_group<KERN, F32, FORM_FAR, CAP, TPT>(Lb, g * Tj, Tj, TR, p);
+                        if constexpr (FORMS != kFormsFar) {
+                            if (ph == 0)
+                                run_group<KERN, F32, FORM_CHECK, CAP, TPT>(Lb, g * Tj, Tj, TR, p);
+                            else if (ph == 1)
+                                run_group<KERN, F32, FORM_EXACT, CAP, TPT>(Lb, g * Tj, Tj, TR, p);
+                            else if (ph == 2)
+                                run_group<KERN, F32, FORM_NEAR, CAP, TPT>(Lb, g * Tj, Tj, TR, p);
+                        }
+                        if constexpr (FORMS != kFormsPP)
+                            if (ph == 3)
+                                run_group<KERN, F32, FORM_FAR, CAP, TPT>(Lb, g * Tj, Tj, TR, p);
 #pragma unroll
                         for (int q = 0; q < TPT; ++q)
 #pragma unroll
@@ -980,7 +987,7 @@ __device__ __forceinline__ void sym_pairs(const TileArgs& a, const ReqView& V, i
 // block barrier.  The entries are taken in list order, split into the same
 // three forms as tile_body (overlapping PP entries, the other PP entries, PC
 // entries), and staged up to wave_items x 64 sources at a time.
-template <int KERN, bool F32>
+template <int KERN, bool F32, int FORMS = kFormsAll>
 __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int leaf, bool sym,
                                                char* lds) {
     WaveStage<F32>& L = *reinterpret_cast<WaveStage<F32>*>(lds);
@@ -1019,7 +1026,7 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
     const int end1 = sym ? gload(V.one_off, T + 1) : nea;
     // phases: 0 overlapping entries (check), 1 close entries (exact
     // differences), 2 the other PP entries, 3 PC entries (far form)
-    for (int ph = 0; ph < 4; ++ph) {
+    for (int ph = FORMS == kFormsFar ? 3 : 0; ph < (FORMS == kFormsPP ? 3 : 4); ++ph) {
         const int e_beg = ph == 1 ? base1 : ph == 2 ? base1 + ncl : 0;
         const int e_end = ph == 0 ? nov : ph == 1 ? base1 + ncl : ph == 2 ? end1 : neb;
         // entry cache: lane l holds the code and size of entry cb + l
@@ -1087,20 +1094,22 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
             R p[VD];
 #pragma unroll
             for (int v = 0; v < VD; ++v) p[v] = R(0);
-            if (ph == 0)
-                run_group<KERN, F32, FORM_CHECK>(L, 0, npad, TR, p);
-            else if (ph == 1)
-                run_group<KERN, F32, FORM_EXACT>(L, 0, npad, TR, p);
-            else if (ph == 2)
-                run_group<KERN, F32, FORM_NEAR>(L, 0, npad, TR, p);
-            else
-                run_group<KERN, F32, FORM_FAR>(L, 0, npad, TR, p);
+            if constexpr (FORMS != kFormsFar) {
+                if (ph == 0)
+                    run_group<KERN, F32, FORM_CHECK>(L, 0, npad, TR, p);
+                else if (ph == 1)
+                    run_group<KERN, F32, FORM_EXACT>(L, 0, npad, TR, p);
+                else if (ph == 2)
+                    run_group<KERN, F32, FORM_NEAR>(L, 0, npad, TR, p);
+            }
+            if constexpr (FORMS != kFormsPP)
+                if (ph == 3) run_group<KERN, F32, FORM_FAR>(L, 0, npad, TR, p);
 #pragma unroll
             for (int v = 0; v < VD; ++v) acc[v] += double(p[v]);
             wave_sync();
         }
     }
-    if constexpr (kSymKernel) {
+    if constexpr (kSymKernel && FORMS != kFormsFar) {
         if (sym)
             sym_pairs<KERN, F32>(a, V, T, tb, nT, cx, cy, cz, TR, acc,
                                  *reinterpret_cast<SymLds<F32>*>(lds));
@@ -1124,18 +1133,25 @@ __device__ __forceinline__ void tile_leaf_wave(const ReqView& V, int mode, int l
 // Biot-Savart's FP32 instances (three components and the A - t B sums) at 96
 // (5 waves, which removes their spills; measured 1% faster than 6 on N =
 // 1,572,864); the FP64 instances, whose transcendentals are longer and which
-// hold two targets a thread, get 3 waves per SIMD, but 1/|x-y| 4 (128 VGPRs,
-// 12 spilled outside the inner loops; 1.5% faster on 6,291,456 sources x
-// 1,000,000 targets, p = 10: 8.74 -> 8.61 ms).
-template <int KERN, bool F32>
+// hold two targets a thread, get 3 waves per SIMD, but 1/|x-y| 4 (1.5% faster
+// on 6,291,456 sources x 1,000,000 targets, p = 10: 8.74 -> 8.61 ms, then with
+// 12 VGPRs spilled outside the inner loops).
+// PPONLY: the instance for PP launches (no far-field blocks, no
+// MAC-separated form); else the one for PC + far launches (that form only).
+// Each then holds only its forms' target registers: the 1/|x-y| FP64
+// instances fit 4 waves without spills (117 and 123 VGPRs; the PP launch of
+// that workload 7.15 -> 6.24 ms, results bitwise unchanged), FP64 Poisson's
+// PP instance 4 waves instead of 3.
+template <int KERN, bool F32, bool PPONLY>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? (KERN == CSFMM_K_BIOT_SAVART ? 5 : 6) : (KERN == CSFMM_K_INV_DIST ? 4 : 3)))) void k_tile(Batch b) {
     __shared__ TileSmem<KERN, F32> sm;
     bool far;
     const int blk = xcd_split_block(blockIdx.x, gridDim.x, b.prefix2[b.n], far);
     int req, local;
+    if (PPONLY) far = false;  // a PP launch has no far-field blocks
     if (far) {
         batch_locate2(b, blk, req, local);
-        tile_body<KERN, F32, true>(*b.v[req], b.mode, local, sm);
+        tile_body<KERN, F32, true, kFormsFar>(*b.v[req], b.mode, local, sm);
     } else {
         batch_locate(b, blk, req, local);
         const ReqView V = load_view(b.v[req]);
@@ -1149,9 +1165,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 
             const int leaf = 4 * local + wave;
             char* st = reinterpret_cast<char*>(&sm) + wave * kWaveBytes;
             if (leaf < V.nleaves_t)
-                tile_leaf_wave<KERN, F32>(V, b.mode, leaf, b.sym[req] != 0, st);
+                tile_leaf_wave<KERN, F32, PPONLY ? kFormsPP : kFormsFar>(V, b.mode, leaf,
+                                                                         b.sym[req] != 0, st);
         } else {
-            tile_body<KERN, F32, false>(V, b.mode, local, sm);
+            tile_body<KERN, F32, false, PPONLY ? kFormsPP : kFormsFar>(V, b.mode, local, sm);
         }
     }
 }
@@ -1169,7 +1186,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int leaf = 4 * local + wave;
     if (leaf < V.nleaves_t)
-        tile_leaf_wave<KERN, F32>(V, b.mode, leaf, b.sym[req] != 0, lds + wave * kWaveBytes);
+        tile_leaf_wave<KERN, F32, kFormsPP>(V, b.mode, leaf, b.sym[req] != 0,
+                                            lds + wave * kWaveBytes);
 }
 
 // Adds the column sums of the symmetric PP pairs owned by other leaves to the
@@ -1498,8 +1516,10 @@ int launch_tile_t(const Batch& b, hipStream_t s) {
     if (nblocks <= 0) return CSFMM_OK;
     if (b.wave_kernel)
         k_tile_wave<KERN, F32><<<nblocks, kThreads, 0, s>>>(b);
+    else if (b.mode == kTileNearPP)
+        k_tile<KERN, F32, true><<<nblocks, kThreads, 0, s>>>(b);
     else
-        k_tile<KERN, F32><<<nblocks, kThreads, 0, s>>>(b);
+        k_tile<KERN, F32, false><<<nblocks, kThreads, 0, s>>>(b);
     CSFMM_LAUNCH_CHECK();
     return CSFMM_OK;
 }
