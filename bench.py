@@ -877,13 +877,11 @@ def fold_counters(args):
                      "traffic_bytes": fk * 1024.0 * ffac + wk * 1024.0 * wfac,
                      "sq": {k: v for k, v in sq.get(key, {}).items() if k.startswith("SQ_")},
                      "pp": False})
-    # the PP launch: k_tile_wave and k_sym_merge always; of a k_tile kernel
-    # seen at two grid sizes, the smaller (target leaves only; the PC + far
-    # launch adds the far-field target cells)
+    # the PP launch: k_tile_wave and k_sym_merge always, and the k_tile
+    # instance for PP launches (its last template argument true)
     for x in disp:
-        sizes = [y["grid_size"] for y in disp if y["kernel"] == x["kernel"]]
         x["pp"] = (not re.search(r"::k_tile<", x["kernel"]) or
-                   (len(sizes) > 1 and x["grid_size"] == min(sizes)))
+                   re.search(r"::k_tile<\d+, (true|false), true>", x["kernel"]) is not None)
     rec = {"record": args.record, "tile_hip_sha256": source_sha(),
            "copy_calibration": {"bytes": copy_bytes, "fetch_factor": ffac, "write_factor": wfac},
            "dispatches": disp}
