@@ -247,8 +247,9 @@ __global__ __launch_bounds__(256) void k_m2m(Batch b) {
 // registers meanwhile, so the children's weights are read from HBM once and
 // B (shared by every block) from L2 once a chunk.
 // Measured on the 1/|x-y| workload's deepest level (24,576 parents, p = 10):
-// the eval 8.42 -> 8.29 ms in FP64; on levels of a few thousand parents the
-// 32-parent blocks leave most CUs idle, and the tiles above are faster.
+// that level 208 -> 78 us, the eval 8.48 -> 8.41 ms in FP64 and 4.41 -> 4.29
+// ms in the FP32 form; on levels of a few thousand parents the 32-parent
+// blocks leave most CUs idle, and the tiles above are faster.
 constexpr int kM2mRows = 32;
 constexpr int kM2mRowsMin = 8192;
 constexpr int kM2mMaxNb = ((kMaxP1 * kMaxP1 + 3) / 4 * 4 + 15) / 16 * 16;
@@ -259,7 +260,7 @@ constexpr int kM2mMaxTiles = kM2mMaxNb / 16;
 __host__ __device__ constexpr int m2m_b_stride(int nb) { return nb % 32 == 0 ? nb + 16 : nb; }
 __global__ __launch_bounds__(256) void k_m2m_rows(Batch b) {
     constexpr int kTW = (kM2mMaxTiles + 1) / 2;  // column tiles per wave
-    __shared__ double As[kM2mRows][16];
+    __shared__ double As[kM2mRows][17];  // a row pad of one: an MFMA step's 16 rows in distinct banks
     __shared__ double Bs[16 * m2m_b_stride(kM2mMaxNb)];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
