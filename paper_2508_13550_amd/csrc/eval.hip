@@ -11,6 +11,7 @@
 // one, and every block's arithmetic depends only on its own request, so a
 // request's result does not depend on what it is batched with.
 #include <algorithm>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <new>
@@ -719,6 +720,17 @@ int launch_batched(Batch& b, const int64_t* blocks, F&& launch) {
 
 int64_t mfma_tiles(int64_t nrows, int nb) { return ((nrows + 15) / 16) * (nb / 16); }
 
+// Parents a level needs for the row-blocked M2M: kM2mRowsMin, or the value of
+// the environment variable CSFMM_M2M_ROWS_MIN (read at each eval), which lets
+// tests run that kernel on small trees; both kernels compute the same product.
+int64_t m2m_rows_min() {
+    const char* e = std::getenv("CSFMM_M2M_ROWS_MIN");
+    if (!e || !*e) return kM2mRowsMin;
+    char* end = nullptr;
+    const long long v = std::strtoll(e, &end, 10);
+    return (end && *end == 0 && v >= 0) ? int64_t(v) : int64_t(kM2mRowsMin);
+}
+
 #define RCX(x)                              \
     do {                                    \
         int rc_ = (x);                      \
@@ -770,6 +782,7 @@ int launch_m2m(Batch& b, const EvalReq* reqs, int n, hipStream_t s, int lhi, int
     int64_t blk[kMaxBatch];
     bool any_shrunk = false;
     for (int r = 0; r < n; ++r) any_shrunk = any_shrunk || reqs[r].plan->st->ops != nullptr;
+    const int64_t rows_min = m2m_rows_min();
     for (int l = lhi; l >= std::max(llo, 0); --l) {
         int64_t blk_rows[kMaxBatch];
         bool any_rows = false;
@@ -778,8 +791,8 @@ int launch_m2m(Batch& b, const EvalReq* reqs, int n, hipStream_t s, int lhi, int
             const int np = l < S.depth ? S.parents_begin[l + 1] - S.parents_begin[l] : 0;
             b.a0[r] = l < S.depth ? S.parents_begin[l] : 0;
             b.a1[r] = np;
-            blk[r] = (S.ops || np >= kM2mRowsMin) ? 0 : mfma_tiles(np, reqs[r].plan->nb1);
-            blk_rows[r] = (S.ops || np < kM2mRowsMin) ? 0 : (int64_t(np) + kM2mRows - 1) / kM2mRows;
+            blk[r] = (S.ops || np >= rows_min) ? 0 : mfma_tiles(np, reqs[r].plan->nb1);
+            blk_rows[r] = (S.ops || np < rows_min) ? 0 : (int64_t(np) + kM2mRows - 1) / kM2mRows;
             any_rows = any_rows || blk_rows[r] > 0;
         }
         RCX(launch_batched(b, blk, [&](unsigned g) { k_m2m<<<g, 256, 0, s>>>(b); }));

@@ -156,6 +156,8 @@ CASES = {
     # components at p = 12 (LDS near its limit); PC (p = 14) and CC (p = 12) present
     "high_p14": lambda: (cubed_sphere_grid(32)[0], None, 1, 14, 0.5, 64),
     "bs_p12": lambda: (cubed_sphere_grid(32)[0], None, 2, 12, 0.6, 64),
+    # the largest degree the library takes (p = 16: 289 proxies a cell)
+    "max_p16": lambda: (cubed_sphere_grid(24)[0], None, 3, 16, 0.6, 64),
     # cluster shrinking (paper §3): boxes from the points, per-cell operators;
     # a clustered cloud, distinct sets (both trees shrunk), and the
     # one-wave-per-leaf near field with symmetric pairs
@@ -487,3 +489,30 @@ def test_plan_rejects_points_off_the_sphere():
     with pytest.raises(cs.CsfmmError) as ei:
         cs.Plan(tdev(X), None, kernel=1, p=4, theta=0.5, leaf_size=8)
     assert ei.value.status == -2
+
+
+@pytest.mark.parametrize("name", ["config1", "high_p14", "bs_p12", "max_p16", "distinct_random"])
+def test_m2m_row_kernel_matches_the_oracle(name, monkeypatch):
+    """The row-blocked M2M (levels of 8,192 parents or more at full size) forced
+    onto every level of small trees: the proxy weights and the result match the
+    oracle's as tightly as the default per-tile kernel's do, and the two
+    kernels agree to rounding (the same product, summed in another order)."""
+    T, S, k, p, th, leaf, shrink = _case(name)
+    _announce("row-blocked M2M on case %s (p=%d)" % (name, p))
+    ofmm = F.FMM(T, S, k, p, th, leaf)
+    src = T if S is None else S
+    w = np.random.default_rng(8).standard_normal(src.shape[0])
+    ref, stg = ofmm.evaluate(w, stages=True)
+    plan = cs.Plan(tdev(T), None if S is None else tdev(S), kernel=k, p=p, theta=th, leaf_size=leaf)
+    out0, wbar0 = (host(x) for x in plan.eval_stages(tdev(w))[:2])
+    monkeypatch.setenv("CSFMM_M2M_ROWS_MIN", "0")
+    out1, wbar1 = (host(x) for x in plan.eval_stages(tdev(w))[:2])
+    plan.close()
+    scale = np.max(np.abs(wbar0))
+    print("wbar rows vs tiles %.3e, out rows vs tiles %.3e" % (
+        np.max(np.abs(wbar1 - wbar0)) / scale, rel_max(out1, out0)), flush=True)
+    assert np.max(np.abs(wbar1 - wbar0)) <= 1e-13 * scale
+    ow = np.array([stg["wbar"][C.id].reshape(-1) for C in ofmm.stree.cells])
+    assert rel_max(wbar1, ow) < 1e-13
+    assert rel_max(out1, out0) < 1e-12
+    assert rel_l2(out1, ref) < 1e-12 * CANCEL[k]
