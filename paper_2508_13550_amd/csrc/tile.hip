@@ -639,10 +639,12 @@ __device__ __forceinline__ void tile_body(const ReqView& V, int mode, int local,
     const int ph_hi[4] = {TPROX ? 0 : nov, TPROX ? 0 : nov + ncl, TPROX ? 0 : nea, nea + neb};
     const int ne_all = nea + neb;
 
-    // FP64 instances give each thread two targets (t and t + TC), so that a
-    // block's threads split a leaf of any size evenly over source groups and
-    // each staged source read serves two evaluations
-    constexpr int TPT = F32 ? 1 : 2;
+    // each thread takes two targets (t and t + TC), so that a block's threads
+    // split a leaf of any size evenly over source groups and each staged
+    // source read serves two evaluations (in the FP32 form too: the
+    // 1/|x-y| workload's FP32 form 4.20 -> 3.89 ms, although the FP32
+    // instances then spill more at 80 VGPRs)
+    constexpr int TPT = 2;
     for (int t0 = 0; t0 < nT; t0 += TPT * kThreads) {
         const int TC = min((nT - t0 + TPT - 1) / TPT, kThreads);
         const int G = min(kThreads / TC, kMaxG);
