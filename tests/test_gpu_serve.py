@@ -66,8 +66,15 @@ def test_packed_mixed_near_field_paths_equal_alone_bitwise(fp32):
     small.close()
 
 
-def test_packed_equals_alone_bitwise():
-    say("eval_many vs alone")
+@pytest.mark.parametrize("rows_min", [None, "0"])
+def test_packed_equals_alone_bitwise(rows_min, monkeypatch):
+    """Packed requests of mixed sizes and kernels equal each request alone, bit
+    for bit; also with the row-blocked M2M forced onto every level (at full
+    size it takes levels of 8,192 parents or more), whose blocks then belong
+    to several requests of one launch."""
+    if rows_min is not None:
+        monkeypatch.setenv("CSFMM_M2M_ROWS_MIN", rows_min)
+    say("eval_many vs alone, CSFMM_M2M_ROWS_MIN=%s" % rows_min)
     mix = request_mix(10, seed_mix=11, e_choices=(8, 16, 32))
     plans, alone, batch = {}, [], []
     for E, k, p, c in mix:
