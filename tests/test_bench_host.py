@@ -57,3 +57,53 @@ def test_vector_errors_use_the_euclidean_norm_per_target():
     e = bench.errors(got, ref)
     assert np.isclose(e["rel_l2_err"], 0.5 / np.sqrt(26.0))
     assert np.isclose(e["max_err"], 0.5 / 5.0)
+
+
+def _csv(path, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        f.write("Dispatch_Id,Kernel_Name,Grid_Size,Counter_Name,Counter_Value\n")
+        for r in rows:
+            f.write("%d,\"%s\",%d,%s,%r\n" % r)
+
+
+def test_counter_folding(tmp_path, monkeypatch):
+    """Counter runs fold into per-launch HBM bytes: rows of one dispatch are
+    summed, dispatches of one (kernel, grid) averaged, KiB scaled by what the
+    same counter reads for a 256 MiB copy; only the tile kernels are kept, and
+    the PP launch is told apart by the instance's last template argument."""
+    pp = "void csfmm::(anonymous namespace)::k_tile<3, false, true>(csfmm::Batch)"
+    far = "void csfmm::(anonymous namespace)::k_tile<3, false, false>(csfmm::Batch)"
+    wave = "void csfmm::(anonymous namespace)::k_tile_wave<1, true>(csfmm::Batch)"
+    other = "void csfmm::(anonymous namespace)::k_l2p(csfmm::Batch)"
+    copy = "__amd_rocclr_copyBuffer"
+    d = tmp_path / "ctr"
+    _csv(str(d / "FETCH_SIZE" / "a_counter_collection.csv"),
+         [(1, pp, 4096, "FETCH_SIZE", 100.0), (1, pp, 4096, "FETCH_SIZE", 20.0),
+          (2, pp, 4096, "FETCH_SIZE", 140.0), (3, far, 8192, "FETCH_SIZE", 50.0),
+          (4, wave, 1024, "FETCH_SIZE", 10.0), (5, other, 64, "FETCH_SIZE", 999.0)])
+    _csv(str(d / "WRITE_SIZE" / "a_counter_collection.csv"),
+         [(1, pp, 4096, "WRITE_SIZE", 8.0), (2, pp, 4096, "WRITE_SIZE", 12.0),
+          (3, far, 8192, "WRITE_SIZE", 5.0), (4, wave, 1024, "WRITE_SIZE", 1.0)])
+    _csv(str(d / "FETCH_SIZE_copy" / "a_counter_collection.csv"),
+         [(1, copy, 65536, "FETCH_SIZE", 2.0 * 262144)])     # reads twice the copy's bytes
+    _csv(str(d / "WRITE_SIZE_copy" / "a_counter_collection.csv"),
+         [(1, copy, 65536, "WRITE_SIZE", 262144.0)])         # writes exactly them
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_sha", lambda name="tile.hip": "ab" * 32)
+
+    class A:
+        counters = str(d)
+        record = "rec.json"
+    bench.fold_counters(A)
+    rec = json.load(open(str(tmp_path / "profiles" / "rec.json")))
+    assert rec["tile_hip_sha256"] == "ab" * 32
+    assert rec["copy_calibration"]["fetch_factor"] == 0.5
+    assert rec["copy_calibration"]["write_factor"] == 1.0
+    by = {x["kernel"]: x for x in rec["dispatches"]}
+    assert set(by) == {pp, far, wave}
+    assert by[pp]["dispatches"] == 2 and by[pp]["fetch_size_kib"] == 130.0
+    assert by[pp]["traffic_bytes"] == 130.0 * 1024 * 0.5 + 10.0 * 1024
+    assert by[far]["traffic_bytes"] == 50.0 * 1024 * 0.5 + 5.0 * 1024
+    assert by[pp]["pp"] and by[wave]["pp"] and not by[far]["pp"]
