@@ -107,3 +107,34 @@ def test_counter_folding(tmp_path, monkeypatch):
     assert by[pp]["traffic_bytes"] == 130.0 * 1024 * 0.5 + 10.0 * 1024
     assert by[far]["traffic_bytes"] == 50.0 * 1024 * 0.5 + 5.0 * 1024
     assert by[pp]["pp"] and by[wave]["pp"] and not by[far]["pp"]
+
+
+def test_roofline_of_the_interaction_launches(monkeypatch):
+    """The dominant kernel's roofline: both interaction launches' evaluations
+    at 11 flops over the span they occupy (never shorter than either launch),
+    against the form's vector peak; traffic from the counter record only when
+    its PP dispatch has this plan's grid."""
+    st = {"evals_pp": 4e9, "evals_pc": 1e9, "evals_cp": 0, "evals_cc": 3e9,
+          "n_leaves_t": 1000, "near_wave": 0}
+    stage = {"near_pp_timed_region": 5.0, "pc_far_timed_region": 6.0,
+             "interaction_span_timed_region": 7.0}
+    rec = {"dispatches": [
+        {"kernel": "k_tile<3, false, true>", "grid_size": 256 * 1000, "pp": True,
+         "traffic_bytes": 3e8},
+        {"kernel": "x::k_tile<3, false, false>", "grid_size": 99, "pp": False,
+         "traffic_bytes": 4e8}]}
+    monkeypatch.setattr(bench, "recorded_traffic", lambda name: rec)
+    r = bench.roofline_of({"stats": st, "stage": stage}, False, "rec.json", "k")
+    assert np.isclose(r["achieved"], 8e9 * 11 / 7e-3 / 1e12)
+    assert r["peak"] == 78.6 and np.isclose(r["frac"], r["achieved"] / 78.6)
+    assert r["traffic"] == 7e8 and r["traffic_record"] == "rec.json"
+    assert np.isclose(r["launches"]["pp"]["achieved"], 4e9 * 11 / 5e-3 / 1e12)
+    assert np.isclose(r["launches"]["pc_far"]["achieved"], 4e9 * 11 / 6e-3 / 1e12)
+    # a span shorter than a launch is taken as that launch; FP32 peak
+    stage["interaction_span_timed_region"] = 1.0
+    r = bench.roofline_of({"stats": st, "stage": stage}, True, "rec.json", "k")
+    assert r["span_ms"] == 6.0 and r["peak"] == 157.3
+    # a record of another workload (its PP grid differs) gives no traffic
+    st["near_wave"] = 1
+    r = bench.roofline_of({"stats": st, "stage": stage}, False, "rec.json", "k")
+    assert r["traffic"] is None and r["traffic_record"] is None
