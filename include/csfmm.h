@@ -218,7 +218,7 @@ int csfmm_bve_rk4_step(double* x, double* zeta, const double* area, int64_t n, d
  * Asynchronous on `stream`; the call allocates 32 N bytes of stream-ordered
  * scratch.
  * Errors: CSFMM_E_INVALID (NULL arrays, E outside [3, 16384], a non-finite
- * omega, grid overlapping x), CSFMM_E_OOM, CSFMM_E_HIP.
+ * omega, any two of grid, x and zeta overlapping), CSFMM_E_OOM, CSFMM_E_HIP.
  */
 int csfmm_bve_remesh(const double* grid, int64_t E, double* x, double* zeta, double omega,
                      void* stream);

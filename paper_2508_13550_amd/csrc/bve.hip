@@ -234,8 +234,9 @@ extern "C" int csfmm_bve_remesh(const double* grid, int64_t E, double* x, double
         return CSFMM_E_INVALID;
     }
     const int64_t n = 6 * E * E;
-    if ((grid < x + 3 * n && x < grid + 3 * n)) {
-        set_error("bve remesh: grid must not overlap x");
+    if ((grid < x + 3 * n && x < grid + 3 * n) || (zeta < grid + 3 * n && grid < zeta + n) ||
+        (zeta < x + 3 * n && x < zeta + n)) {
+        set_error("bve remesh: grid, x and zeta must not overlap");
         return CSFMM_E_INVALID;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);

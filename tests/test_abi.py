@@ -93,4 +93,7 @@ def test_bve_remesh_argument_errors():
     assert f(4096, 1 << 15, 1 << 40, 1 << 41, 6.28, None) == -1  # E too large
     assert f(4096, 4, 1 << 20, 1 << 21, float("inf"), None) == -1
     assert f(4096, 4, 4096 + 8, 1 << 21, 6.28, None) == -1       # grid overlaps x
+    assert f(4096, 4, 1 << 20, 4096 + 8, 6.28, None) == -1       # zeta inside grid
+    assert f(4096, 4, 1 << 20, (1 << 20) + 16, 6.28, None) == -1  # zeta inside x
+    assert f(4096, 4, 1 << 20, (1 << 20) - 8, 6.28, None) == -1   # zeta runs into x
     assert "remesh" in L.csfmm_last_error().decode()
